@@ -1,0 +1,557 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test ties one oracle function to something other than itself: closed-form
+eigenpairs, the closed form of Chebyshev polynomials, the paper's theorems
+(FGS residual structure, backward stability, MGS equivalence), invariants
+(energy identity, Galerkin orthogonality, symmetry/definiteness), textbook
+special cases (s = 1 steepest descent, Cholesky) and dense direct solves on
+tiny grids.  Dense NumPy linear algebra is used only as an independent check.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+EPS = np.finfo(np.float64).eps
+
+
+def dense(A):
+    rp, ci, v = A
+    n = rp.size - 1
+    M = np.zeros((n, n))
+    for i in range(n):
+        M[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    return M
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# P1 / P12: operator assembly and spectral bounds (sine eigenpairs, closed form)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny", [(7, 5), (64, 64)])
+def test_poisson2d_sine_eigenpairs(nx, ny):
+    A = gen.poisson2d_csr(nx, ny)
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    for a, b in [(1, 1), (2, 3), (nx, ny), (3, 1)]:
+        v = (np.sin(a * math.pi * (i + 1) / (nx + 1)) * np.sin(b * math.pi * (j + 1) / (ny + 1))).ravel()
+        lam = 4 - 2 * math.cos(a * math.pi / (nx + 1)) - 2 * math.cos(b * math.pi / (ny + 1))
+        # backward-error scale: ||A|| <= 8
+        assert np.linalg.norm(oracle.spmv(A, v) - lam * v) < 8 * 1e-14 * np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (9, 9, 9)])
+def test_poisson3d_sine_eigenpairs(dims):
+    nx, ny, nz = dims
+    Ao = oracle.assemble_stencil7(nx, ny, nz)
+    Ag = gen.poisson3d_csr(nx, ny, nz)
+    # P12-style: the generator's CSR and the oracle's assembly are the same matrix
+    for a, b in zip(Ao, Ag):
+        assert np.array_equal(a, b)
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    for a, b, c in [(1, 1, 1), (2, 1, 3), (nx, ny, nz)]:
+        v = (np.sin(a * math.pi * (i + 1) / (nx + 1)) * np.sin(b * math.pi * (j + 1) / (ny + 1))
+             * np.sin(c * math.pi * (k + 1) / (nz + 1))).ravel()
+        lam = 6 - 2 * (math.cos(a * math.pi / (nx + 1)) + math.cos(b * math.pi / (ny + 1))
+                       + math.cos(c * math.pi / (nz + 1)))
+        assert np.linalg.norm(oracle.spmv(Ao, v) - lam * v) < 12 * 1e-14 * np.linalg.norm(v)
+
+
+def test_unit_faces_reproduce_poisson_bitwise():
+    nx, ny, nz = 6, 5, 4
+    ones = [np.ones(nz * ny * (nx + 1)), np.ones(nz * (ny + 1) * nx), np.ones((nz + 1) * ny * nx)]
+    A1 = oracle.assemble_stencil7(nx, ny, nz, *ones)
+    A0 = oracle.assemble_stencil7(nx, ny, nz)
+    for a, b in zip(A1, A0):
+        assert np.array_equal(a, b)
+    assert oracle.csr_valid(nx * ny * nz, A0)
+
+
+def test_face_operator_quadratic_form_and_generator():
+    """u^T A u equals the sum over faces of k_f (u_p - u_q)^2 (u_q = 0 across the
+    boundary), the defining energy of the face operator; the generator's CSR is
+    the same matrix."""
+    nx, ny, nz = 5, 4, 3
+    r = gen.rng(3)
+    kx, ky, kz = gen.face_coefficients(r, nx, ny, nz, 1.0)
+    A = oracle.assemble_stencil7(nx, ny, nz, kx, ky, kz)
+    for a, b in zip(A, gen.faces3d_csr(nx, ny, nz, kx, ky, kz)):
+        assert np.array_equal(a, b)
+    Ad = dense(A)
+    assert np.array_equal(Ad, Ad.T)
+    u = r.standard_normal(nx * ny * nz)
+    U = np.pad(u.reshape(nz, ny, nx), 1)
+    KX = kx.reshape(nz, ny, nx + 1)
+    KY = ky.reshape(nz, ny + 1, nx)
+    KZ = kz.reshape(nz + 1, ny, nx)
+    e = (KX * np.diff(U[1:-1, 1:-1, :], axis=2) ** 2).sum()
+    e += (KY * np.diff(U[1:-1, :, 1:-1], axis=1) ** 2).sum()
+    e += (KZ * np.diff(U[:, 1:-1, 1:-1], axis=0) ** 2).sum()
+    assert abs(u @ Ad @ u - e) < 1e-12 * e
+
+
+@pytest.mark.parametrize("dims", [(7, 5), (6, 6), (4, 5, 3), (5, 5, 5)])
+def test_jacobi_bounds_closed_form(dims):
+    A = gen.poisson2d_csr(*dims) if len(dims) == 2 else gen.poisson3d_csr(*dims)
+    Ad = dense(A)
+    ev = np.linalg.eigvalsh(Ad / np.diag(Ad)[0])
+    lmin, lmax = gen.jacobi_poisson_bounds(*dims)
+    assert abs(ev[0] - lmin) < 1e-13 and abs(ev[-1] - lmax) < 1e-13
+
+
+def test_gershgorin_bounds_contain_face_spectrum():
+    nx, ny, nz = 5, 4, 3
+    kx, ky, kz = gen.face_coefficients(gen.rng(1), nx, ny, nz, 1.0)
+    Ad = dense(oracle.assemble_stencil7(nx, ny, nz, kx, ky, kz))
+    dh = 1 / np.sqrt(np.diag(Ad))
+    ev = np.linalg.eigvalsh(dh[:, None] * Ad * dh[None, :])
+    lo, hi = gen.gershgorin_jacobi_bounds()
+    assert lo <= ev[0] and ev[-1] <= hi
+
+
+# ---------------------------------------------------------------------------
+# Chebyshev basis (Sec. 2, Definition): p_j = T_j(theta (M^{-1}A - sigma I)) p_0
+# checked against T_j(cos phi) = cos(j phi) on the eigen-decomposition.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["poisson2d", "faces3d"])
+def test_chebyshev_basis_closed_form(case):
+    if case == "poisson2d":
+        A = gen.poisson2d_csr(6, 5)
+        lmin, lmax = gen.jacobi_poisson_bounds(6, 5)
+    else:
+        kx, ky, kz = gen.face_coefficients(gen.rng(2), 4, 3, 3, 0.5)
+        A = oracle.assemble_stencil7(4, 3, 3, kx, ky, kz)
+        lmin, lmax = gen.gershgorin_jacobi_bounds()
+    Ad = dense(A)
+    n = Ad.shape[0]
+    invd, dv = oracle.jacobi(A)
+    s = 12
+    p0 = gen.uniform(gen.rng(5), n)
+    P, AP = oracle.chebyshev_basis(A, invd, p0, s, lmin, lmax)
+    # M^{-1} A = D^{-1/2} (V diag(lam) V^T) D^{1/2}
+    dh = np.sqrt(dv)
+    lam, V = np.linalg.eigh(Ad / dh[:, None] / dh[None, :])
+    theta, sigma = 2 / (lmax - lmin), (lmax + lmin) / 2
+    t = np.clip(theta * (lam - sigma), -1, 1)
+    q = V.T @ (dh * p0)
+    for j in range(s):
+        pj = (V @ (np.cos(j * np.arccos(t)) * q)) / dh
+        assert rel(P[j], pj) < 1e-12, j
+        assert rel(AP[j], Ad @ P[j]) < 1e-14, j
+
+
+# ---------------------------------------------------------------------------
+# FGS (Sec. 2 / Sec. 3)
+# ---------------------------------------------------------------------------
+
+def synthetic_gram(s, seed, cond_shift=0.5):
+    r = np.random.default_rng(seed)
+    B = r.standard_normal((s + 3, s))
+    H = B.T @ B + cond_shift * np.eye(s)
+    dd = 1 / np.sqrt(np.diag(H))
+    G = dd[:, None] * H * dd[None, :]
+    np.fill_diagonal(G, 1.0)
+    return G, r.standard_normal(s)
+
+
+@pytest.mark.parametrize("s", [2, 5, 16, 32])
+def test_fgs_converges_to_cholesky(s):
+    """P2: with many sweeps FGS reaches the Cholesky solution of the SPD system."""
+    G, c = synthetic_gram(s, s)
+    Lc = np.linalg.cholesky(G)
+    exact = np.linalg.solve(Lc.T, np.linalg.solve(Lc, c))
+    a = oracle.fgs(G, c, 20000)
+    assert rel(a, exact) < 1e-12
+
+
+def test_fgs_two_by_two_closed_form():
+    g, c0, c1 = 0.4, 1.3, -0.7
+    G = np.array([[1.0, g], [g, 1.0]])
+    a0, a1 = 0.0, 0.0
+    for nu in range(1, 6):
+        a0 = c0 - g * a1
+        a1 = c1 - g * a0
+        assert np.allclose(oracle.fgs(G, np.array([c0, c1]), nu), [a0, a1], rtol=0, atol=1e-15)
+
+
+def test_fgs_identity_one_sweep():
+    c = np.arange(1.0, 9.0)
+    assert np.array_equal(oracle.fgs(np.eye(8), c, 1), c)
+
+
+@pytest.mark.parametrize("s", [4, 16, 32])
+def test_fgs_residual_structure(s):
+    """P4 (Sec. 3, Proposition "FGS Residual Structure"):
+    c - G a^{(l+1)} = L^T (a^{(l)} - a^{(l+1)}), and r^{(1)} = -L^T a^{(1)}."""
+    G, c = synthetic_gram(s, 100 + s)
+    LT = np.triu(G, 1)
+    prev = np.zeros(s)
+    for nu in range(1, 8):
+        a = oracle.fgs(G, c, nu)
+        lhs = c - G @ a
+        rhs = LT @ (prev - a)
+        assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(c)
+        prev = a
+    a1 = oracle.fgs(G, c, 1)
+    assert np.linalg.norm((c - G @ a1) + LT @ a1) <= 1e-13 * np.linalg.norm(c)
+
+
+def test_fgs_is_forward_not_backward():
+    """A backward sweep would satisfy the identity with L instead of L^T; make
+    sure the two differ on this example and the oracle matches the forward one."""
+    G, c = synthetic_gram(6, 7)
+    a1 = oracle.fgs(G, c, 1)
+    assert np.linalg.norm((c - G @ a1) + np.triu(G, 1) @ a1) < 1e-14
+    assert np.linalg.norm((c - G @ a1) + np.tril(G, -1) @ a1) > 1e-3
+
+
+@pytest.mark.parametrize("s", [4, 16, 20])
+def test_fgs_backward_stability(s):
+    """P10 (Sec. 3, Theorem "Backward Stability"): the computed sweep solves
+    (I + L) a^{(l+1)} = c - L^T a^{(l)} + dr with
+    ||dr|| <= eps C(s) (||c|| + ||I+L|| ||a^{(l+1)}|| + ||L^T|| ||a^{(l)}||);
+    the residual is recomputed in extended precision.  The last term accounts
+    for the rounding of the right-hand side c - L^T a^{(l)}, which the sweep
+    forms in the same accumulation."""
+    G, c = synthetic_gram(s, 200 + s, cond_shift=0.05)
+    L = np.tril(G, -1)
+    ILl = (np.eye(s) + L).astype(np.longdouble)
+    LTl = L.T.astype(np.longdouble)
+    cl = c.astype(np.longdouble)
+    prev = np.zeros(s)
+    for nu in range(1, 6):
+        a = oracle.fgs(G, c, nu)
+        dr = ILl @ a.astype(np.longdouble) - (cl - LTl @ prev.astype(np.longdouble))
+        bound = EPS * s * (np.linalg.norm(c) + np.linalg.norm(np.eye(s) + L, 2) * np.linalg.norm(a)
+                           + np.linalg.norm(L.T, 2) * np.linalg.norm(prev))
+        assert float(np.linalg.norm(dr.astype(np.float64))) <= bound
+        prev = a
+
+
+def test_fgs_g_norm_error_monotone():
+    """Gauss-Seidel on an SPD matrix contracts the G-norm of the error at every
+    sweep (Ostrowski-Reich), the valid form of the multi-sweep lemma (Sec. 3)."""
+    G, c = synthetic_gram(16, 9, cond_shift=0.01)
+    exact = np.linalg.solve(G, c)
+    prev = np.inf
+    for nu in range(0, 40):
+        e = exact - oracle.fgs(G, c, nu) if nu else exact
+        en = math.sqrt(e @ G @ e)
+        assert en <= prev * (1 + 1e-12)
+        prev = en
+
+
+# ---------------------------------------------------------------------------
+# Outer iteration (Sec. 2, Sec. 5, Sec. 7)
+# ---------------------------------------------------------------------------
+
+def small_problem(kind="poisson3d", seed=0):
+    if kind == "poisson3d":
+        pr = gen.small_poisson3d(6, 5, 4, seed=seed)
+    elif kind == "faces3d":
+        pr = gen.small_faces3d(5, 4, 4, seed=seed, sigma=1.0)
+    else:
+        r = gen.rng(seed)
+        lmin, lmax = gen.jacobi_poisson_bounds(9, 7)
+        pr = gen.Problem("p2d", "csr", (9, 7), 6, 25, lmin, lmax, xstar=gen.uniform(r, 63))
+    A = oracle.problem_csr(pr)
+    b = oracle.spmv(A, pr.xstar)
+    return pr, A, b
+
+
+@pytest.mark.parametrize("kind", ["poisson3d", "faces3d", "poisson2d"])
+def test_gram_symmetric_spd_unit_diagonal(kind):
+    """P5: G is exactly symmetric with unit diagonal and positive definite."""
+    pr, A, b = small_problem(kind)
+    out = oracle.step(A, b, np.zeros(pr.n), 6, 10, pr.lmin, pr.lmax)
+    assert out["status"] == 0
+    G = out["G"]
+    assert np.array_equal(G, G.T) and np.array_equal(out["Graw"], out["Graw"].T)
+    assert np.all(np.diag(G) == 1.0)
+    np.linalg.cholesky(G)
+
+
+@pytest.mark.parametrize("kind", ["poisson3d", "faces3d", "poisson2d"])
+@pytest.mark.parametrize("p0_mode", [0, 1])
+def test_one_sweep_equals_a_norm_mgs(kind, p0_mode):
+    """P3 (Sec. 5, Theorem "Algebraic Equivalence"): one FGS sweep from zero on
+    G a = P~^T A e, with e = x* - x_k (so that P~^T A e = P~^T r_k), gives the
+    coefficients of one A-norm MGS pass of e against the scaled basis."""
+    pr, A, b = small_problem(kind, seed=1)
+    Ad = dense(A)
+    xk = 0.3 * gen.uniform(gen.rng(11), pr.n)
+    out = oracle.step(A, b, xk, 5, 1, pr.lmin, pr.lmax, p0_mode=p0_mode, want_basis=True)
+    Pt = out["P"] * out["d"][:, None]
+    w = pr.xstar - xk
+    gam = np.zeros(5)
+    for j in range(5):
+        gam[j] = w @ (Ad @ Pt[j])
+        w = w - gam[j] * Pt[j]
+    assert rel(out["atil"], gam) < 1e-12
+    # and the scaled right-hand side is P~^T r_k
+    assert rel(out["ctil"], Pt @ (b - Ad @ xk)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["poisson3d", "faces3d"])
+def test_energy_identity_each_outer(kind):
+    """P6: ||e_{k+1}||_A^2 - ||e_k||_A^2 = atil^T G atil - 2 ctil^T atil <= 0,
+    the A-norm error never grows even with an inexact Gram solve."""
+    pr, A, b = small_problem(kind, seed=2)
+    Ad = dense(A)
+    x = np.zeros(pr.n)
+    for _ in range(6):
+        out = oracle.step(A, b, x, 6, 3, pr.lmin, pr.lmax)
+        e0 = pr.xstar - x
+        e1 = pr.xstar - out["x"]
+        lhs = e1 @ Ad @ e1 - e0 @ Ad @ e0
+        a, G, c = out["atil"], out["G"], out["ctil"]
+        rhs = a @ G @ a - 2 * c @ a
+        assert rhs <= 0
+        assert abs(lhs - rhs) <= 1e-11 * (e0 @ Ad @ e0)
+        x = out["x"]
+
+
+def test_s1_is_preconditioned_steepest_descent():
+    """P7: with s = 1 the update is x + (z^T r / z^T A z) z, z = M^{-1} r."""
+    pr, A, b = small_problem("faces3d", seed=4)
+    Ad = dense(A)
+    xk = 0.1 * gen.uniform(gen.rng(1), pr.n)
+    r = b - Ad @ xk
+    z = r / np.diag(Ad)
+    want = xk + (z @ r) / (z @ Ad @ z) * z
+    out = oracle.step(A, b, xk, 1, 7, pr.lmin, pr.lmax)
+    assert rel(out["x"], want) < 1e-14
+
+
+def test_exact_gram_solve_gives_galerkin_orthogonality():
+    """P8: with enough sweeps the new residual is orthogonal to the basis."""
+    pr, A, b = small_problem("poisson3d", seed=3)
+    Ad = dense(A)
+    xk = np.zeros(pr.n)
+    out = oracle.step(A, b, xk, 4, 20000, pr.lmin, pr.lmax, want_basis=True)
+    Pt = out["P"] * out["d"][:, None]
+    r1 = b - Ad @ out["x"]
+    assert np.linalg.norm(Pt @ r1) <= 1e-10 * np.linalg.norm(out["ctil"])
+
+
+@pytest.mark.parametrize("dims,s", [((8, 8), 4), ((8, 8), 8), ((6, 6, 6), 4), ((6, 6, 6), 8)])
+def test_converges_to_dense_direct_solve(dims, s):
+    """P9: tight tolerance reaches the direct solution within kappa(A) * tol."""
+    r = gen.rng(7)
+    A = gen.poisson2d_csr(*dims) if len(dims) == 2 else gen.poisson3d_csr(*dims)
+    lmin, lmax = gen.jacobi_poisson_bounds(*dims)
+    n = int(np.prod(dims))
+    b = gen.uniform(r, n)
+    out = oracle.solve(A, b, None, s, 25, lmin, lmax, 1e-12)
+    assert out["status"] == 0
+    Ad = dense(A)
+    xs = np.linalg.solve(Ad, b)
+    assert rel(out["x"], xs) <= np.linalg.cond(Ad) * 1e-12
+
+
+def test_stencil_and_csr_forms_agree():
+    """P13: the oracle's stencil assembly and the generator's CSR of the same
+    face operator give the same outer iteration."""
+    pr = gen.small_faces3d(6, 5, 4, seed=8)
+    A1 = oracle.problem_csr(pr)
+    A2 = pr.csr()
+    b = oracle.spmv(A1, pr.xstar)
+    o1 = oracle.step(A1, b, np.zeros(pr.n), 8, 25, pr.lmin, pr.lmax)
+    o2 = oracle.step(A2, b, np.zeros(pr.n), 8, 25, pr.lmin, pr.lmax)
+    assert rel(o1["atil"], o2["atil"]) < 1e-12 and rel(o1["x"], o2["x"]) < 1e-12
+
+
+def test_p0_modes_identical_for_constant_diagonal():
+    """With a constant Jacobi diagonal, p_0 = M^{-1} r and p_0 = r differ by a
+    scalar that the column scaling absorbs: same scaled coefficients."""
+    pr, A, b = small_problem("poisson3d", seed=5)
+    o0 = oracle.step(A, b, np.zeros(pr.n), 8, 25, pr.lmin, pr.lmax, p0_mode=0)
+    o1 = oracle.step(A, b, np.zeros(pr.n), 8, 25, pr.lmin, pr.lmax, p0_mode=1)
+    assert rel(o0["atil"], o1["atil"]) < 1e-12 and rel(o0["x"], o1["x"]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Solve loop: stopping rule and failure paths
+# ---------------------------------------------------------------------------
+
+def test_stopping_rule_strict_and_counts():
+    pr = gen.config1()
+    A = pr.csr()
+    b = oracle.spmv(A, pr.xstar)
+    out = oracle.solve(A, b, None, pr.s, pr.nu, pr.lmin, pr.lmax, 1e-8, hist_cap=1000)
+    k = out["iters"]
+    h = out["hist_relres"]
+    assert out["status"] == 0 and h[k] < 1e-8 and np.all(h[:k] >= 1e-8) and h[0] == 1.0
+    assert abs(out["relres"] - h[k]) == 0
+    # the reported residual is the true one of the returned x
+    assert abs(np.linalg.norm(b - oracle.spmv(A, out["x"])) / np.linalg.norm(b) - out["relres"]) < 1e-12
+
+
+def test_zero_rhs_returns_immediately():
+    A = gen.poisson2d_csr(5, 5)
+    out = oracle.solve(A, np.zeros(25), None, 4, 5, *gen.jacobi_poisson_bounds(5, 5), 1e-8)
+    assert out["status"] == 0 and out["iters"] == 0 and np.all(out["x"] == 0)
+
+
+def test_max_outer_gives_noconv_with_last_iterate():
+    pr = gen.config1()
+    A = pr.csr()
+    b = oracle.spmv(A, pr.xstar)
+    out = oracle.solve(A, b, None, pr.s, pr.nu, pr.lmin, pr.lmax, 1e-8, max_outer=3)
+    assert out["status"] == 5 and out["iters"] == 3
+    x = np.zeros(pr.n)
+    for _ in range(3):
+        x = oracle.step(A, b, x, pr.s, pr.nu, pr.lmin, pr.lmax)["x"]
+    assert np.array_equal(x, out["x"])
+
+
+def test_breakdown_when_basis_vector_vanishes():
+    """A = 2I, no preconditioner, bounds [1, 3] -> sigma = 2, so p_1 = 0 exactly
+    and p_1^T A p_1 = 0: the column scaling is undefined."""
+    n = 10
+    A = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
+    out = oracle.solve(A, np.ones(n), None, 3, 5, 1.0, 3.0, 1e-8, precond=0)
+    assert out["status"] == 4 and out["iters"] == 0 and np.all(out["x"] == 0)
+
+
+def test_nonfinite_rhs():
+    A = gen.poisson2d_csr(5, 5)
+    b = np.ones(25)
+    b[3] = np.nan
+    out = oracle.solve(A, b, None, 4, 5, *gen.jacobi_poisson_bounds(5, 5), 1e-8)
+    assert out["status"] == 6
+
+
+@pytest.mark.parametrize("bad", ["s0", "nu0", "bounds", "tol", "csr"])
+def test_argument_errors(bad):
+    A = gen.poisson2d_csr(4, 4)
+    args = dict(s=4, nu=5, lmin=0.1, lmax=1.9, tol=1e-8)
+    if bad == "s0":
+        args["s"] = 0
+    elif bad == "nu0":
+        args["nu"] = 0
+    elif bad == "bounds":
+        args["lmin"], args["lmax"] = 1.9, 0.1
+    elif bad == "tol":
+        args["tol"] = 1.5
+    else:
+        rp, ci, v = A
+        ci = ci.copy()
+        ci[3] = 99
+        A = (rp, ci, v)
+    out = oracle.solve(A, np.ones(16), None, args["s"], args["nu"], args["lmin"], args["lmax"], args["tol"])
+    assert out["status"] == 1
+
+
+# ---------------------------------------------------------------------------
+# P11: gradient through the solve (adjoint), against complex-step derivatives
+# of a dense direct solve (exact to rounding, no finite-difference error)
+# ---------------------------------------------------------------------------
+
+def dense_faces(nx, ny, nz, kx, ky, kz):
+    """Dense face operator built from its definition, complex-safe."""
+    n = nx * ny * nz
+    M = np.zeros((n, n), dtype=np.result_type(kx, ky, kz))
+    KX = kx.reshape(nz, ny, nx + 1)
+    KY = ky.reshape(nz, ny + 1, nx)
+    KZ = kz.reshape(nz + 1, ny, nx)
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                p = idx(i, j, k)
+                for kf, q in [(KX[k, j, i], idx(i - 1, j, k) if i > 0 else None),
+                              (KX[k, j, i + 1], idx(i + 1, j, k) if i < nx - 1 else None),
+                              (KY[k, j, i], idx(i, j - 1, k) if j > 0 else None),
+                              (KY[k, j + 1, i], idx(i, j + 1, k) if j < ny - 1 else None),
+                              (KZ[k, j, i], idx(i, j, k - 1) if k > 0 else None),
+                              (KZ[k + 1, j, i], idx(i, j, k + 1) if k < nz - 1 else None)]:
+                    M[p, p] += kf
+                    if q is not None:
+                        M[p, q] -= kf
+    return M
+
+
+def test_gradient_faces_matches_complex_step():
+    nx, ny, nz = 4, 3, 3
+    r = gen.rng(12)
+    kx, ky, kz = gen.face_coefficients(r, nx, ny, nz, 0.5)
+    n = nx * ny * nz
+    b = gen.uniform(r, n)
+    xt = gen.uniform(r, n)
+
+    def loss(kx_, ky_, kz_, b_):
+        x = np.linalg.solve(dense_faces(nx, ny, nz, kx_, ky_, kz_), b_)
+        return 0.5 * np.sum((x - xt) ** 2)
+
+    A = oracle.assemble_stencil7(nx, ny, nz, kx, ky, kz)
+    assert np.allclose(dense(A), dense_faces(nx, ny, nz, kx, ky, kz), rtol=0, atol=1e-15)
+    lmin, lmax = gen.gershgorin_jacobi_bounds()
+    fwd = oracle.solve(A, b, None, 8, 25, lmin, lmax, 1e-13)
+    x = fwd["x"]
+    adj = oracle.solve(A, x - xt, None, 8, 25, lmin, lmax, 1e-13)
+    lam = adj["x"]
+    assert fwd["status"] == 0 and adj["status"] == 0
+    gx, gy, gz = oracle.grad_faces(nx, ny, nz, lam, x)
+    h = 1e-30
+    scale = max(np.abs(gx).max(), np.abs(gy).max(), np.abs(gz).max())
+    for arr, g, which in [(kx, gx, 0), (ky, gy, 1), (kz, gz, 2)]:
+        for f in range(arr.size):
+            kk = [kx.astype(complex), ky.astype(complex), kz.astype(complex)]
+            kk[which][f] += 1j * h
+            cs = loss(*kk, b.astype(complex)).imag / h
+            assert abs(cs - g[f]) <= 1e-9 * scale, (which, f)
+    for m in range(n):
+        bb = b.astype(complex)
+        bb[m] += 1j * h
+        cs = loss(kx, ky, kz, bb).imag / h
+        assert abs(cs - lam[m]) <= 1e-9 * np.abs(lam).max()
+
+
+def test_gradient_csr_matches_complex_step():
+    A = gen.poisson2d_csr(4, 4)
+    rp, ci, v = A
+    r = gen.rng(13)
+    b = gen.uniform(r, 16)
+    xt = gen.uniform(r, 16)
+    lmin, lmax = gen.jacobi_poisson_bounds(4, 4)
+    x = oracle.solve(A, b, None, 4, 25, lmin, lmax, 1e-13)["x"]
+    lam = oracle.solve(A, x - xt, None, 4, 25, lmin, lmax, 1e-13)["x"]
+    g = oracle.grad_csr(A, lam, x)
+    h = 1e-30
+    for k in range(v.size):
+        vals = v.astype(complex)
+        vals[k] += 1j * h
+        M = np.zeros((16, 16), complex)
+        for i in range(16):
+            M[i, ci[rp[i]:rp[i + 1]]] = vals[rp[i]:rp[i + 1]]
+        cs = (0.5 * np.sum((np.linalg.solve(M, b) - xt) ** 2)).imag / h
+        assert abs(cs - g[k]) <= 1e-9 * np.abs(g).max(), k
+
+
+def test_golden_c1_trajectory_unchanged():
+    """Regression fixture written by tests/golden/make_golden.py (oracle only)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_oracle.json")) as f:
+        g = json.load(f)
+    pr = gen.config1(0)
+    A = pr.csr()
+    b = oracle.spmv(A, pr.xstar)
+    out = oracle.solve(A, b, None, pr.s, pr.nu, pr.lmin, pr.lmax, pr.tol, hist_cap=1000)
+    assert out["iters"] == g["iters"]
+    assert np.allclose(out["hist_relres"], g["hist_relres"], rtol=1e-12, atol=0)
+    first = oracle.step(A, b, np.zeros(pr.n), pr.s, pr.nu, pr.lmin, pr.lmax)
+    assert np.allclose(first["atil"], g["atil_first"], rtol=1e-13, atol=0)
+    assert (g["lmin"], g["lmax"]) == (pr.lmin, pr.lmax)
