@@ -1,0 +1,197 @@
+/*
+ * sstep.h -- C ABI of the MI355X (gfx950) s-step CG library.
+ *
+ * The library solves a sparse symmetric positive definite system A x = b with
+ * the s-step conjugate-gradient outer iteration of S. Thomas and P. D'Ambra,
+ * "Inexact Gauss-Seidel Coarse Solvers for AMG and s-step CG"
+ * (arXiv:2512.09642), Sec. 2:
+ *   1. r = b - A x, stop when ||r|| < tol ||r_0||            (Sec. 8, stopping rule)
+ *   2. Chebyshev basis P = [p_0 .. p_{s-1}] of K_s(M^{-1}A, r)  (Sec. 2, Definition)
+ *      by the three-term recurrence, keeping the products A P
+ *   3. Gram system G = P^T (A P), c = P^T r as block reductions (Sec. 1, Sec. 2)
+ *   4. column scaling d_i = (p_i^T A p_i)^{-1/2}, G <- S G S   (Sec. 2, column scaling)
+ *      and nu forward Gauss-Seidel sweeps from alpha = 0      (Sec. 2, FGS iteration)
+ *   5. x <- x + P alpha                                       (Sec. 2)
+ * Every step runs in hand-written HIP kernels; one outer iteration is captured
+ * in a HIP graph, so a solve performs no host synchronisation between outer
+ * iterations (the host polls a device flag between graph replays).
+ *
+ * Conventions for every function below:
+ *   - Vector arguments (b, x, g, lam, dA, P_out, AP_out, y) are DEVICE pointers
+ *     to FP64 arrays on the GPU that was current at sstep_setup.  The matrix
+ *     arrays of sstep_operator are host or device pointers (ptr_space).
+ *   - Work is ordered after all work previously enqueued on options.stream
+ *     (NULL = the legacy default stream) and the call returns after the
+ *     library's own stream has finished, so outputs are ready on return.
+ *   - Nothing allocates device memory after sstep_setup /
+ *     sstep_setup_batched.
+ *   - A context is used by one host thread at a time.
+ *   - Errors are returned as sstep_status; sstep_last_error() gives a message.
+ *     No exception crosses the ABI.
+ */
+#ifndef SSTEP_H
+#define SSTEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sstep_ctx sstep_ctx; /* opaque, library-owned */
+
+typedef enum {
+    SSTEP_OK = 0,
+    SSTEP_E_ARG = 1,         /* invalid argument (sizes, bounds, pointers, malformed CSR, diagonal <= 0) */
+    SSTEP_E_HIP = 2,         /* a HIP runtime call failed */
+    SSTEP_E_NOMEM = 3,       /* device or pinned host allocation failed */
+    SSTEP_E_BREAKDOWN = 4,   /* a basis column has p^T A p <= 0 or non-finite: scaling undefined */
+    SSTEP_E_NOCONV = 5,      /* max_outer outer iterations without reaching tol */
+    SSTEP_E_NONFINITE = 6,   /* the residual norm became NaN or Inf */
+    SSTEP_E_UNSUPPORTED = 7  /* valid request this build does not provide */
+} sstep_status;
+
+typedef enum {
+    SSTEP_OP_CSR = 0,      /* general sparse SPD matrix, CSR */
+    SSTEP_OP_STENCIL7 = 1  /* matrix-free 7-point operator on a 3D grid */
+} sstep_op_kind;
+
+typedef enum {
+    SSTEP_FP64 = 0,    /* every step in FP64 */
+    SSTEP_FP32_IR = 1  /* basis, SpMV and Gram in FP32 with FP32 accumulation; residual, scaling,
+                          FGS and x update in FP64 (one FP64 refinement per outer iteration) */
+} sstep_precision;
+
+/* Sparse SPD operator.
+ *  CSR (kind = SSTEP_OP_CSR): n rows, nnz entries, 0-based int32 row_ptr[n+1]
+ *     and col_idx[nnz] (columns strictly ascending within a row), FP64 val[nnz].
+ *  Stencil (kind = SSTEP_OP_STENCIL7): interior grid nx x ny x nz, unknown
+ *     (i,j,k) at i + nx*(j + ny*k) (x fastest), homogeneous Dirichlet boundary.
+ *     (A u)_p = sum over the six faces f of p of k_f (u_p - u_q), u_q = 0 outside
+ *     the grid, with face coefficients (boundary faces included, x fastest)
+ *        kx[(k*ny + j)*(nx+1) + i]   face between cells i-1 and i,
+ *        ky[(k*(ny+1) + j)*nx + i],  kz[(k*ny + j)*nx + i].
+ *     kx = ky = kz = NULL selects the constant Poisson operator (every k_f = 1:
+ *     diagonal 6, off-diagonal -1).  n and nnz are ignored.
+ *  ptr_space: 0 = the arrays are host memory, 1 = device memory.  They are
+ *  copied into library memory; the caller may free them on return. */
+typedef struct {
+    int32_t kind;
+    int32_t ptr_space;
+    int64_t n, nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+    int32_t nx, ny, nz;
+    const double *kx, *ky, *kz;
+} sstep_operator;
+
+typedef struct {
+    int32_t precision;      /* sstep_precision, default SSTEP_FP64 */
+    int32_t precond;        /* 1 = Jacobi M = diag(A) (default), 0 = none */
+    int32_t p0_mode;        /* 0 = p_0 = M^{-1} r (default), 1 = p_0 = r as printed in Sec. 2 */
+    int32_t max_outer;      /* outer-iteration limit, default 10000 */
+    int32_t graph_chunk;    /* outer iterations per graph replay, default 4 */
+    int32_t record_history; /* 1 = keep per-iteration relative residual and delta on the device */
+    void *stream;           /* hipStream_t the caller's data is ordered on (NULL = default) */
+} sstep_options;
+
+typedef struct {
+    int32_t outer_iters;  /* completed outer updates */
+    int32_t status;       /* sstep_status of the solve */
+    double rel_res;       /* ||b - A x|| / ||b - A x_0|| of the returned x */
+    double res0;          /* ||b - A x_0|| */
+    double *hist_relres;  /* (host, optional) relative residual for k = 0..outer_iters */
+    double *hist_delta;   /* (host, optional) ||ctil - G atil|| / ||ctil|| per update (Sec. 7) */
+    int32_t hist_cap;     /* capacity of both history arrays (0 = none) */
+} sstep_stats;
+
+/* Fills *opt with the defaults listed above. */
+void sstep_default_options(sstep_options *opt);
+
+/* Creates a context for operator A, basis width s in [1, 32], nu >= 1 FGS sweeps
+ * (Sec. 2), and Chebyshev bounds 0 <= lambda_min < lambda_max enclosing the
+ * spectrum of M^{-1} A (Sec. 2, Definition).  Copies A to the device,
+ * allocates every workspace (basis P and products AP, n x s each, column-major,
+ * partial sums, device state) and captures the outer-iteration graph.
+ * opt may be NULL (defaults).  Returns SSTEP_E_ARG for invalid sizes, bounds,
+ * a malformed CSR pattern or, with Jacobi, a non-positive diagonal. */
+sstep_status sstep_setup(sstep_ctx **out, const sstep_operator *A, int32_t s, int32_t nu,
+                         double lambda_min, double lambda_max, const sstep_options *opt);
+
+/* Replaces the coefficients of the operator (same kind, same sizes, same CSR
+ * pattern): val for CSR, kx/ky/kz for stencils. */
+sstep_status sstep_update_coefficients(sstep_ctx *ctx, const sstep_operator *A);
+
+/* y = A x (FP64). x and y: n doubles, distinct. */
+sstep_status sstep_apply(sstep_ctx *ctx, const double *x, double *y);
+
+/* Solves A x = b.  x holds the initial guess on entry and the result on exit.
+ * Stops at the first k with ||b - A x_k|| < tol ||b - A x_0|| (tol in (0, 1));
+ * returns immediately if ||b - A x_0|| = 0.  On SSTEP_E_NOCONV, _BREAKDOWN or
+ * _NONFINITE, x holds the last completed iterate.  st may be NULL. */
+sstep_status sstep_solve(sstep_ctx *ctx, const double *b, double *x, double tol, sstep_stats *st);
+
+/* Adjoint solve A^T lam = g.  A is symmetric, so this is the same s-step
+ * iteration applied to g; lam holds the initial guess on entry. */
+sstep_status sstep_solve_adjoint(sstep_ctx *ctx, const double *g, double *lam, double tol, sstep_stats *st);
+
+/* Gradient of a loss through x = A^{-1} b with respect to the operator's
+ * coefficients, given x and the adjoint solution lam: dL/dA = -lam x^T, i.e.
+ *   CSR:      dA[k] = -lam_i x_j for stored entry k = (i, j)        (nnz values)
+ *   stencil:  interior face f between p and q: -(lam_p - lam_q)(x_p - x_q),
+ *             boundary face of p: -lam_p x_p; dA = [dkx | dky | dkz] concatenated
+ *             ((nx+1)ny nz + nx(ny+1)nz + nx ny(nz+1) values, layouts as in
+ *             sstep_operator; also for the constant Poisson operator, whose faces are 1).
+ * accumulate = 1 adds to dA instead of overwriting it. */
+sstep_status sstep_grad_operator(sstep_ctx *ctx, const double *lam, const double *x, double *dA, int32_t accumulate);
+
+/* Number of values sstep_grad_operator writes. */
+int64_t sstep_grad_size(const sstep_ctx *ctx);
+
+/* Number of unknowns n. */
+int64_t sstep_n(const sstep_ctx *ctx);
+
+/* ONE outer iteration from x (no stopping test, no graph): x <- x + P alpha.
+ * Host outputs (each may be NULL): alpha_tilde[s] (scaled FGS solution),
+ * G[s*s] (scaled Gram matrix, row-major), ctil[s] (scaled right-hand side),
+ * rnorm[1] (||b - A x|| before the update).  Device outputs (may be NULL):
+ * P_out, AP_out: n x s FP64 column-major (leading dimension n).  Used by the
+ * lockstep parity tests. */
+sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alpha_tilde, double *G, double *ctil,
+                        double *rnorm, double *P_out, double *AP_out);
+
+/* Kernel classes timed by sstep_kernel_times, in this order. */
+enum { SSTEP_KT_RESIDUAL = 0, SSTEP_KT_BASIS = 1, SSTEP_KT_GRAM = 2, SSTEP_KT_FGS = 3, SSTEP_KT_UPDATE = 4,
+       SSTEP_KT_COUNT = 5 };
+
+/* Average duration in milliseconds of one launch of each kernel class of the
+ * outer iteration (the same kernels, grids and arguments a solve uses),
+ * measured with HIP events on the library stream over reps repetitions of
+ * the class; the basis figure is the average over the s launches of one basis
+ * (positions 0..s-1).  b is read; x is used as scratch and overwritten. */
+sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int32_t reps, double *ms_out);
+
+/* Batched solves: nsys independent operators (each its own size), nrhs
+ * right-hand sides per operator, one shared s and nu, per-system bounds
+ * lmin[q] < lmax[q] (host arrays).  The outer iteration of every
+ * (system, rhs) pair advances in one launch per step over all pairs. */
+sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_operator *A, int32_t nrhs, int32_t s,
+                                 int32_t nu, const double *lmin, const double *lmax, const sstep_options *opt);
+
+/* b[q], x[q] (host arrays of nsys device pointers): n_q x nrhs FP64,
+ * column-major (right-hand side r at offset r*n_q).  st: host array of
+ * nsys*nrhs entries (pair (q, r) at q*nrhs + r), may be NULL.  Returns the
+ * first non-OK pair status, or SSTEP_OK. */
+sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double *const *x, double tol,
+                                 sstep_stats *st);
+
+const char *sstep_last_error(const sstep_ctx *ctx);
+const char *sstep_status_string(sstep_status s);
+void sstep_destroy(sstep_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSTEP_H */

@@ -1,0 +1,53 @@
+"""Differentiable s-step CG solve.
+
+Forward: x = A(k)^{-1} b with the library's s-step solver.  Backward, given
+dL/dx: the adjoint system A^T lam = dL/dx is solved by the same s-step
+iteration (A is symmetric), then dL/db = lam and dL/dk = -lam^T (dA/dk) x,
+which the library scatters onto the operator's coefficients
+(``sstep_grad_operator``: -lam_i x_j on a CSR pattern, -(lam_p - lam_q)(x_p - x_q)
+on an interior face, -lam_p x_p on a boundary face).
+"""
+from __future__ import annotations
+
+import torch
+
+from .solver import Operator, Solver
+
+
+class SStepSolve(torch.autograd.Function):
+    """``x = SStepSolve.apply(coeffs, b, solver, tol)``.
+
+    ``coeffs`` holds the operator's coefficient values: the CSR ``val`` array
+    or the concatenated face coefficients ``[kx | ky | kz]`` (device float64).
+    They are loaded into ``solver`` before the solve.  Returns x; gradients
+    flow to ``coeffs`` and ``b``.
+    """
+
+    @staticmethod
+    def forward(ctx, coeffs: torch.Tensor, b: torch.Tensor, solver: Solver, tol: float = 1e-8):
+        op = solver.op
+        if op.kind == 0:
+            new = Operator.csr(op.row_ptr, op.col_idx, coeffs.detach())
+        else:
+            kx, ky, kz = op.split_faces(coeffs.detach())
+            new = Operator.stencil(*op.dims, kx, ky, kz)
+        solver.update_coefficients(new)
+        x, _ = solver.solve(b.detach().contiguous(), None, tol)
+        ctx.solver = solver
+        ctx.tol = tol
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx: torch.Tensor):
+        (x,) = ctx.saved_tensors
+        solver: Solver = ctx.solver
+        lam, _ = solver.solve_adjoint(gx.detach().contiguous(), None, ctx.tol)
+        dcoef = solver.grad_operator(lam, x) if ctx.needs_input_grad[0] else None
+        db = lam if ctx.needs_input_grad[1] else None
+        return dcoef, db, None, None
+
+
+def sstep_solve(coeffs: torch.Tensor, b: torch.Tensor, solver: Solver, tol: float = 1e-8) -> torch.Tensor:
+    """Functional form of :class:`SStepSolve`."""
+    return SStepSolve.apply(coeffs, b, solver, tol)

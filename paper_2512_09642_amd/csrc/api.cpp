@@ -1,0 +1,725 @@
+// C ABI of the s-step CG library: argument checking, device copies of the
+// operator, workspace, the captured outer-iteration graph and the solve loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "sstep.h"
+
+using namespace sstep;
+
+namespace {
+thread_local std::string g_setup_error;  // message of a failed setup (no context yet)
+}
+
+
+struct sstep_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t user = nullptr;
+    hipEvent_t ev_in = nullptr;
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    IterArgs it;
+    sstep_options opt{};
+    std::vector<void *> dev_allocs;
+    DevState *st_host = nullptr;  // pinned host mirror of the device state
+    int32_t *poll_host = nullptr; // pinned [2][4]: done, status, iter of the last replays
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int chunk = 4;
+    int64_t grad_size = 0;
+    int *bad_flag = nullptr;       // device flag of the diagonal check
+    std::string err;
+};
+
+namespace {
+
+sstep_status fail(sstep_ctx *ctx, sstep_status code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_setup_error = msg;
+    return code;
+}
+
+sstep_status hip_fail(sstep_ctx *ctx, const char *what, hipError_t e)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? SSTEP_E_NOMEM : SSTEP_E_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                 \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess)                             \
+            return hip_fail((ctx), #call, e_);            \
+    } while (0)
+
+template <typename T>
+sstep_status dalloc(sstep_ctx *ctx, T **p, size_t count)
+{
+    void *v = nullptr;
+    const size_t bytes = count * sizeof(T) > 0 ? count * sizeof(T) : 256;
+    hipError_t e = hipMalloc(&v, bytes);
+    if (e != hipSuccess)
+        return hip_fail(ctx, "hipMalloc", e);
+    ctx->dev_allocs.push_back(v);
+    *p = static_cast<T *>(v);
+    return SSTEP_OK;
+}
+
+#define OKCHK(call)                          \
+    do {                                     \
+        sstep_status s_ = (call);            \
+        if (s_ != SSTEP_OK)                  \
+            return s_;                       \
+    } while (0)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Copies count elements from host or device memory into a fresh device buffer.
+template <typename T>
+sstep_status to_device(sstep_ctx *ctx, T **dst, const T *src, size_t count, int ptr_space)
+{
+    OKCHK(dalloc(ctx, dst, count));
+    HIPCHK(ctx, hipMemcpy(*dst, src, count * sizeof(T), ptr_space ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    return SSTEP_OK;
+}
+
+template <typename T>
+sstep_status overwrite_device(sstep_ctx *ctx, T *dst, const T *src, size_t count, int ptr_space)
+{
+    HIPCHK(ctx, hipMemcpy(dst, src, count * sizeof(T), ptr_space ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    return SSTEP_OK;
+}
+
+template <typename T>
+std::vector<T> to_host(const T *src, size_t count, int ptr_space, hipError_t *err)
+{
+    std::vector<T> h(count);
+    *err = hipSuccess;
+    if (count == 0)
+        return h;
+    if (ptr_space)
+        *err = hipMemcpy(h.data(), src, count * sizeof(T), hipMemcpyDeviceToHost);
+    else
+        std::memcpy(h.data(), src, count * sizeof(T));
+    return h;
+}
+
+int64_t faces_x(const sstep_operator *A) { return int64_t(A->nx + 1) * A->ny * A->nz; }
+int64_t faces_y(const sstep_operator *A) { return int64_t(A->nx) * (A->ny + 1) * A->nz; }
+int64_t faces_z(const sstep_operator *A) { return int64_t(A->nx) * A->ny * (A->nz + 1); }
+
+sstep_status check_operator(sstep_ctx *ctx, const sstep_operator *A)
+{
+    if (!A)
+        return fail(ctx, SSTEP_E_ARG, "operator is NULL");
+    if (A->ptr_space != 0 && A->ptr_space != 1)
+        return fail(ctx, SSTEP_E_ARG, "ptr_space must be 0 (host) or 1 (device)");
+    if (A->kind == SSTEP_OP_STENCIL7) {
+        if (A->nx < 1 || A->ny < 1 || A->nz < 1)
+            return fail(ctx, SSTEP_E_ARG, "stencil grid sizes must be >= 1");
+        const int64_t n = int64_t(A->nx) * A->ny * A->nz;
+        if (n >= (int64_t(1) << 31) || faces_x(A) >= (int64_t(1) << 31) || faces_y(A) >= (int64_t(1) << 31) ||
+            faces_z(A) >= (int64_t(1) << 31))
+            return fail(ctx, SSTEP_E_ARG, "stencil grid too large (n must be < 2^31)");
+        const int given = (A->kx != nullptr) + (A->ky != nullptr) + (A->kz != nullptr);
+        if (given != 0 && given != 3)
+            return fail(ctx, SSTEP_E_ARG, "give all three face arrays kx, ky, kz or none");
+        return SSTEP_OK;
+    }
+    if (A->kind == SSTEP_OP_CSR) {
+        if (A->n < 1 || A->n >= (int64_t(1) << 31))
+            return fail(ctx, SSTEP_E_ARG, "CSR n must be in [1, 2^31)");
+        if (A->nnz < 1 || A->nnz >= (int64_t(1) << 31))
+            return fail(ctx, SSTEP_E_ARG, "CSR nnz must be in [1, 2^31)");
+        if (!A->row_ptr || !A->col_idx || !A->val)
+            return fail(ctx, SSTEP_E_ARG, "CSR arrays must not be NULL");
+        return SSTEP_OK;
+    }
+    return fail(ctx, SSTEP_E_ARG, "unknown operator kind");
+}
+
+// CSR pattern check on the host: row_ptr[0] = 0, monotone, row_ptr[n] = nnz,
+// columns in range and strictly ascending within a row.
+sstep_status check_csr_pattern(sstep_ctx *ctx, const sstep_operator *A)
+{
+    hipError_t e1, e2;
+    std::vector<int32_t> rp = to_host(A->row_ptr, size_t(A->n + 1), A->ptr_space, &e1);
+    std::vector<int32_t> ci = to_host(A->col_idx, size_t(A->nnz), A->ptr_space, &e2);
+    if (e1 != hipSuccess)
+        return hip_fail(ctx, "hipMemcpy(row_ptr)", e1);
+    if (e2 != hipSuccess)
+        return hip_fail(ctx, "hipMemcpy(col_idx)", e2);
+    if (rp[0] != 0 || rp[size_t(A->n)] != A->nnz)
+        return fail(ctx, SSTEP_E_ARG, "malformed CSR: row_ptr[0] != 0 or row_ptr[n] != nnz");
+    for (int64_t i = 0; i < A->n; ++i) {
+        if (rp[i + 1] < rp[i])
+            return fail(ctx, SSTEP_E_ARG, "malformed CSR: row_ptr not monotone at row " + std::to_string(i));
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if (ci[k] < 0 || ci[k] >= A->n)
+                return fail(ctx, SSTEP_E_ARG, "malformed CSR: column out of range in row " + std::to_string(i));
+            if (k > rp[i] && ci[k] <= ci[k - 1])
+                return fail(ctx, SSTEP_E_ARG, "malformed CSR: columns not strictly ascending in row " +
+                                                  std::to_string(i));
+        }
+    }
+    return SSTEP_OK;
+}
+
+// Loads (or reloads) the operator's coefficients and everything derived from
+// them: M diagonal, its inverse, FP32 copies.
+sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool first)
+{
+    OpDev &op = ctx->it.op;
+    const int fp32 = ctx->it.fp32;
+    hipStream_t s = ctx->stream;
+    if (first)
+        OKCHK(dalloc(ctx, &ctx->bad_flag, 1));
+    int *bad = ctx->bad_flag;
+    HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int), s));
+    if (op.kind == kOpCsr) {
+        double *val = const_cast<double *>(op.val);
+        double *dvec = const_cast<double *>(op.dvec);
+        double *invd = const_cast<double *>(op.invd);
+        if (first) {
+            OKCHK(to_device(ctx, &val, A->val, size_t(op.nnz), A->ptr_space));
+            OKCHK(dalloc(ctx, &dvec, size_t(op.n)));
+            OKCHK(dalloc(ctx, &invd, size_t(op.n)));
+            op.val = val;
+            op.dvec = dvec;
+            op.invd = invd;
+        } else {
+            OKCHK(overwrite_device(ctx, val, A->val, size_t(op.nnz), A->ptr_space));
+        }
+        HIPCHK(ctx, launch_diag_from_csr(op, dvec, bad, s));
+        HIPCHK(ctx, launch_invert(dvec, invd, op.n, op.precond, s));
+        if (fp32) {
+            float *val32 = const_cast<float *>(op.val32), *invd32 = const_cast<float *>(op.invd32);
+            float *dvec32 = const_cast<float *>(op.dvec32);
+            if (first) {
+                OKCHK(dalloc(ctx, &val32, size_t(op.nnz)));
+                OKCHK(dalloc(ctx, &invd32, size_t(op.n)));
+                OKCHK(dalloc(ctx, &dvec32, size_t(op.n)));
+                op.val32 = val32;
+                op.invd32 = invd32;
+                op.dvec32 = dvec32;
+            }
+            HIPCHK(ctx, launch_to_fp32(val, val32, op.nnz, s));
+            HIPCHK(ctx, launch_to_fp32(invd, invd32, op.n, s));
+            HIPCHK(ctx, launch_to_fp32(dvec, dvec32, op.n, s));
+        }
+    } else if (op.kind == kOpFaces) {
+        const int64_t nfx = faces_x(A), nfy = faces_y(A), nfz = faces_z(A);
+        double *k = const_cast<double *>(op.kx);
+        double *dvec = const_cast<double *>(op.dvec);
+        if (first) {
+            OKCHK(dalloc(ctx, &k, size_t(nfx + nfy + nfz)));
+            OKCHK(dalloc(ctx, &dvec, size_t(op.n)));
+            op.kx = k;
+            op.ky = k + nfx;
+            op.kz = k + nfx + nfy;
+            op.dvec = dvec;
+        }
+        OKCHK(overwrite_device(ctx, k, A->kx, size_t(nfx), A->ptr_space));
+        OKCHK(overwrite_device(ctx, k + nfx, A->ky, size_t(nfy), A->ptr_space));
+        OKCHK(overwrite_device(ctx, k + nfx + nfy, A->kz, size_t(nfz), A->ptr_space));
+        HIPCHK(ctx, launch_diag_from_faces(op, dvec, bad, s));
+        if (fp32) {
+            float *k32 = const_cast<float *>(op.kx32), *dvec32 = const_cast<float *>(op.dvec32);
+            if (first) {
+                OKCHK(dalloc(ctx, &k32, size_t(nfx + nfy + nfz)));
+                OKCHK(dalloc(ctx, &dvec32, size_t(op.n)));
+                op.kx32 = k32;
+                op.ky32 = k32 + nfx;
+                op.kz32 = k32 + nfx + nfy;
+                op.dvec32 = dvec32;
+            }
+            HIPCHK(ctx, launch_to_fp32(k, k32, nfx + nfy + nfz, s));
+            HIPCHK(ctx, launch_to_fp32(dvec, dvec32, op.n, s));
+        }
+    }
+    int hbad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (hbad)
+        return fail(ctx, SSTEP_E_ARG, "matrix has a missing, non-positive or non-finite diagonal entry");
+    return SSTEP_OK;
+}
+
+// Enqueues one outer iteration: residual + p_0, s basis steps, Gram partials,
+// FGS, update.
+hipError_t enqueue_iteration(const IterArgs &a, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_residual(a, s, true)) != hipSuccess)
+        return e;
+    for (int j = 0; j < a.s; ++j)
+        if ((e = launch_basis(a, j, s)) != hipSuccess)
+            return e;
+    if ((e = launch_gram(a, s)) != hipSuccess)
+        return e;
+    if ((e = launch_fgs(a, s)) != hipSuccess)
+        return e;
+    return launch_update(a, s);
+}
+
+// Initial device state for a solve (or a single step) on b, x.
+sstep_status start_state(sstep_ctx *ctx, const double *b, double *x, double tol, int no_stop)
+{
+    DevState &h = *ctx->st_host;
+    std::memset(&h, 0, sizeof(DevState));
+    h.b = b;
+    h.x = x;
+    h.tol = tol;
+    h.p0scale = 1.0;
+    h.first = 1;
+    h.no_stop = no_stop;
+    h.max_outer = no_stop ? (1 << 30) : ctx->opt.max_outer;
+    h.hist_cap = ctx->it.hist_cap;
+    HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->it.st, &h, sizeof(DevState), hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->it.fp32) {
+        HIPCHK(ctx, launch_residual(ctx->it, ctx->stream, false));
+        HIPCHK(ctx, launch_p0scale(ctx->it, ctx->stream));
+    }
+    return SSTEP_OK;
+}
+
+sstep_status capture_graph(sstep_ctx *ctx)
+{
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < ctx->chunk && e == hipSuccess; ++c)
+        e = enqueue_iteration(ctx->it, ctx->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+    if (e != hipSuccess)
+        return hip_fail(ctx, "kernel launch during graph capture", e);
+    if (e2 != hipSuccess)
+        return hip_fail(ctx, "hipStreamEndCapture", e2);
+    ctx->graph = g;
+    HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    return SSTEP_OK;
+}
+
+sstep_status run_solve(sstep_ctx *ctx, const double *b, double *x, double tol, sstep_stats *stats)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!b || !x)
+        return fail(ctx, SSTEP_E_ARG, "b and x must not be NULL");
+    if (!(tol > 0.0) || !(tol < 1.0))
+        return fail(ctx, SSTEP_E_ARG, "tol must be in (0, 1)");
+    OKCHK(start_state(ctx, b, x, tol, 0));
+    const int max_replays = (ctx->opt.max_outer + 1 + ctx->chunk - 1) / ctx->chunk + 1;
+    int launched = 0, checked = 0;
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = hipGraphLaunch(ctx->gexec, ctx->stream);
+        if (e != hipSuccess)
+            return e;
+        int32_t *slot = ctx->poll_host + 4 * (launched % 2);
+        e = hipMemcpyAsync(slot, &ctx->it.st->done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream);
+        if (e != hipSuccess)
+            return e;
+        e = hipEventRecord(ctx->ev_poll[launched % 2], ctx->stream);
+        ++launched;
+        return e;
+    };
+    HIPCHK(ctx, enqueue());
+    for (;;) {
+        if (launched < max_replays)
+            HIPCHK(ctx, enqueue());  // keep one replay queued behind the one being checked
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev_poll[checked % 2]));
+        const int32_t done = ctx->poll_host[4 * (checked % 2)];
+        ++checked;
+        if (done)
+            break;
+        if (checked >= launched) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            return fail(ctx, SSTEP_E_HIP, "solve did not stop within the replay bound");
+        }
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    DevState h;
+    HIPCHK(ctx, hipMemcpy(&h, ctx->it.st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (stats) {
+        stats->outer_iters = h.iter;
+        stats->status = h.status;
+        stats->rel_res = h.relres;
+        stats->res0 = h.rho0;
+        if (stats->hist_cap > 0 && ctx->it.hist_cap > 0) {
+            const int nr = std::min(std::min(stats->hist_cap, ctx->it.hist_cap), h.iter + 1);
+            const int nd = std::min(std::min(stats->hist_cap, ctx->it.hist_cap), h.iter);
+            if (stats->hist_relres && nr > 0)
+                HIPCHK(ctx, hipMemcpy(stats->hist_relres, ctx->it.hist, nr * sizeof(double), hipMemcpyDeviceToHost));
+            if (stats->hist_delta && nd > 0)
+                HIPCHK(ctx, hipMemcpy(stats->hist_delta, ctx->it.hist + ctx->it.hist_cap, nd * sizeof(double),
+                                      hipMemcpyDeviceToHost));
+        }
+    }
+    const sstep_status code = static_cast<sstep_status>(h.status);
+    if (code != SSTEP_OK)
+        return fail(ctx, code, std::string("solve stopped: ") + sstep_status_string(code));
+    return SSTEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sstep_default_options(sstep_options *opt)
+{
+    if (!opt)
+        return;
+    opt->precision = SSTEP_FP64;
+    opt->precond = 1;
+    opt->p0_mode = 0;
+    opt->max_outer = 10000;
+    opt->graph_chunk = 4;
+    opt->record_history = 0;
+    opt->stream = nullptr;
+}
+
+const char *sstep_status_string(sstep_status s)
+{
+    switch (s) {
+    case SSTEP_OK:
+        return "SSTEP_OK";
+    case SSTEP_E_ARG:
+        return "SSTEP_E_ARG";
+    case SSTEP_E_HIP:
+        return "SSTEP_E_HIP";
+    case SSTEP_E_NOMEM:
+        return "SSTEP_E_NOMEM";
+    case SSTEP_E_BREAKDOWN:
+        return "SSTEP_E_BREAKDOWN";
+    case SSTEP_E_NOCONV:
+        return "SSTEP_E_NOCONV";
+    case SSTEP_E_NONFINITE:
+        return "SSTEP_E_NONFINITE";
+    case SSTEP_E_UNSUPPORTED:
+        return "SSTEP_E_UNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+const char *sstep_last_error(const sstep_ctx *ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
+
+void sstep_destroy(sstep_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    if (ctx->stream)
+        (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->gexec)
+        (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph)
+        (void)hipGraphDestroy(ctx->graph);
+    for (void *p : ctx->dev_allocs)
+        (void)hipFree(p);
+    if (ctx->st_host)
+        (void)hipHostFree(ctx->st_host);
+    if (ctx->poll_host)
+        (void)hipHostFree(ctx->poll_host);
+    for (hipEvent_t e : {ctx->ev_in, ctx->ev_poll[0], ctx->ev_poll[1], ctx->ev_t0, ctx->ev_t1})
+        if (e)
+            (void)hipEventDestroy(e);
+    if (ctx->stream)
+        (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t s, int32_t nu, double lmin,
+                               double lmax, const sstep_options *opt)
+{
+    if (opt)
+        ctx->opt = *opt;
+    else
+        sstep_default_options(&ctx->opt);
+    sstep_options &o = ctx->opt;
+    if (s < 1 || s > kMaxS)
+        return fail(ctx, SSTEP_E_ARG, "s must be in [1, 32]");
+    if (nu < 1)
+        return fail(ctx, SSTEP_E_ARG, "nu must be >= 1");
+    if (!std::isfinite(lmin) || !std::isfinite(lmax) || lmin < 0.0 || !(lmax > lmin))
+        return fail(ctx, SSTEP_E_ARG, "bounds must be finite with 0 <= lambda_min < lambda_max");
+    if (o.precision != SSTEP_FP64 && o.precision != SSTEP_FP32_IR)
+        return fail(ctx, SSTEP_E_ARG, "unknown precision");
+    if (o.precond != 0 && o.precond != 1)
+        return fail(ctx, SSTEP_E_ARG, "precond must be 0 or 1");
+    if (o.p0_mode != 0 && o.p0_mode != 1)
+        return fail(ctx, SSTEP_E_ARG, "p0_mode must be 0 or 1");
+    if (o.max_outer < 0)
+        return fail(ctx, SSTEP_E_ARG, "max_outer must be >= 0");
+    if (o.graph_chunk <= 0)
+        o.graph_chunk = 4;
+    OKCHK(check_operator(ctx, A));
+    if (A->kind == SSTEP_OP_CSR)
+        OKCHK(check_csr_pattern(ctx, A));
+
+    HIPCHK(ctx, hipGetDevice(&ctx->device));
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    ctx->user = static_cast<hipStream_t>(o.stream);
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_poll[0], hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_poll[1], hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreate(&ctx->ev_t0));
+    HIPCHK(ctx, hipEventCreate(&ctx->ev_t1));
+    {
+        void *p = nullptr;
+        HIPCHK(ctx, hipHostMalloc(&p, sizeof(DevState), hipHostMallocDefault));
+        ctx->st_host = static_cast<DevState *>(p);
+        HIPCHK(ctx, hipHostMalloc(&p, 8 * sizeof(int32_t), hipHostMallocDefault));
+        ctx->poll_host = static_cast<int32_t *>(p);
+    }
+
+    IterArgs &it = ctx->it;
+    OpDev &op = it.op;
+    it.fp32 = o.precision == SSTEP_FP32_IR;
+    it.p0_mode = o.p0_mode;
+    it.s = s;
+    it.nu = nu;
+    it.theta = 2.0 / (lmax - lmin);
+    it.sigma = (lmax + lmin) / 2.0;
+    op.precond = o.precond;
+    if (A->kind == SSTEP_OP_STENCIL7) {
+        op.kind = A->kx ? kOpFaces : kOpPoisson;
+        op.n = int64_t(A->nx) * A->ny * A->nz;
+        op.g.nx = A->nx;
+        op.g.ny = A->ny;
+        op.g.nz = A->nz;
+        op.g.nxy = int64_t(A->nx) * A->ny;
+        op.g.dx = make_fastdiv(uint32_t(A->nx));
+        op.g.dy = make_fastdiv(uint32_t(A->ny));
+        ctx->grad_size = faces_x(A) + faces_y(A) + faces_z(A);
+    } else {
+        op.kind = kOpCsr;
+        op.n = A->n;
+        op.nnz = A->nnz;
+        int32_t *rp = nullptr, *ci = nullptr;
+        OKCHK(to_device(ctx, &rp, A->row_ptr, size_t(A->n + 1), A->ptr_space));
+        OKCHK(to_device(ctx, &ci, A->col_idx, size_t(A->nnz), A->ptr_space));
+        op.rp = rp;
+        op.ci = ci;
+        ctx->grad_size = A->nnz;
+    }
+    OKCHK(load_coefficients(ctx, A, true));
+
+    // right-hand side of the Gram system: c = P^T r with r = M p_0 (p0_mode 0)
+    // or r = p_0 (p0_mode 1 or no preconditioner)
+    const bool jac_p0 = o.precond == 1 && o.p0_mode == 0;
+    it.wdvec = jac_p0 && op.kind != kOpPoisson;
+    it.cscale = (jac_p0 && op.kind == kOpPoisson) ? 6.0 : 1.0;
+
+    // workspace
+    const int64_t n = op.n;
+    const size_t w = it.fp32 ? sizeof(float) : sizeof(double);
+    it.ld = round_up(n, 64);
+    {
+        char *P = nullptr, *AP = nullptr;
+        OKCHK(dalloc(ctx, &P, size_t(it.ld) * s * w));
+        OKCHK(dalloc(ctx, &AP, size_t(it.ld) * s * w));
+        it.P = P;
+        it.AP = AP;
+    }
+    it.nbr = int(std::min<int64_t>(2048, (n + kBlock - 1) / kBlock));
+    it.rchunk = round_up((n + it.nbr - 1) / it.nbr, kBlock);
+    const int ng = s <= 6 ? 1 : s <= 10 ? 2 : s <= 16 ? 4 : s <= 24 ? 8 : 16;
+    const int64_t target = ng <= 4 ? 1024 : ng == 8 ? 512 : 256;
+    it.nbg = int(std::min<int64_t>(target, (n + kWave - 1) / kWave));
+    it.gchunk = round_up((n + it.nbg - 1) / it.nbg, kWave);
+    OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
+    OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * it.nbg));
+    OKCHK(dalloc(ctx, &it.st, 1));
+    OKCHK(dalloc(ctx, &it.dbg, size_t(dbg_size(s))));
+    it.hist_cap = o.record_history ? o.max_outer + 1 : 0;
+    OKCHK(dalloc(ctx, &it.hist, size_t(2 * std::max(it.hist_cap, 1))));
+    it.inv_sqrt_n = 1.0 / std::sqrt(double(n));
+    HIPCHK(ctx, hipMemsetAsync(it.st, 0, sizeof(DevState), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+
+    ctx->chunk = o.graph_chunk;
+    OKCHK(capture_graph(ctx));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_setup(sstep_ctx **out, const sstep_operator *A, int32_t s, int32_t nu, double lambda_min,
+                         double lambda_max, const sstep_options *opt)
+{
+    if (!out)
+        return fail(nullptr, SSTEP_E_ARG, "out is NULL");
+    *out = nullptr;
+    sstep_ctx *ctx = new (std::nothrow) sstep_ctx();
+    if (!ctx)
+        return fail(nullptr, SSTEP_E_NOMEM, "out of host memory");
+    const sstep_status st = setup_impl(ctx, A, s, nu, lambda_min, lambda_max, opt);
+    if (st != SSTEP_OK) {
+        g_setup_error = ctx->err;
+        sstep_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return SSTEP_OK;
+}
+
+sstep_status sstep_update_coefficients(sstep_ctx *ctx, const sstep_operator *A)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    OKCHK(check_operator(ctx, A));
+    const OpDev &op = ctx->it.op;
+    if (op.kind == kOpCsr) {
+        if (A->kind != SSTEP_OP_CSR || A->n != op.n || A->nnz != op.nnz)
+            return fail(ctx, SSTEP_E_ARG, "operator kind or sizes differ from setup");
+    } else {
+        if (A->kind != SSTEP_OP_STENCIL7 || A->nx != op.g.nx || A->ny != op.g.ny || A->nz != op.g.nz)
+            return fail(ctx, SSTEP_E_ARG, "operator kind or grid differ from setup");
+        if ((op.kind == kOpFaces) != (A->kx != nullptr))
+            return fail(ctx, SSTEP_E_ARG, "constant and face-coefficient stencils cannot be swapped");
+        if (op.kind == kOpPoisson)
+            return SSTEP_OK;  // no coefficients
+    }
+    return load_coefficients(ctx, A, false);
+}
+
+int64_t sstep_n(const sstep_ctx *ctx) { return ctx ? ctx->it.op.n : 0; }
+
+int64_t sstep_grad_size(const sstep_ctx *ctx) { return ctx ? ctx->grad_size : 0; }
+
+sstep_status sstep_apply(sstep_ctx *ctx, const double *x, double *y)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!x || !y || x == y)
+        return fail(ctx, SSTEP_E_ARG, "x and y must be distinct non-NULL device pointers");
+    HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    HIPCHK(ctx, launch_apply(ctx->it.op, x, y, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_solve(sstep_ctx *ctx, const double *b, double *x, double tol, sstep_stats *st)
+{
+    return run_solve(ctx, b, x, tol, st);
+}
+
+sstep_status sstep_solve_adjoint(sstep_ctx *ctx, const double *g, double *lam, double tol, sstep_stats *st)
+{
+    // A is symmetric positive definite, so A^T lam = g is the same system.
+    return run_solve(ctx, g, lam, tol, st);
+}
+
+sstep_status sstep_grad_operator(sstep_ctx *ctx, const double *lam, const double *x, double *dA, int32_t accumulate)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!lam || !x || !dA)
+        return fail(ctx, SSTEP_E_ARG, "lam, x and dA must not be NULL");
+    HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    HIPCHK(ctx, launch_grad(ctx->it.op, lam, x, dA, accumulate ? 1 : 0, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alpha_tilde, double *G, double *ctil,
+                        double *rnorm, double *P_out, double *AP_out)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!b || !x)
+        return fail(ctx, SSTEP_E_ARG, "b and x must not be NULL");
+    const IterArgs &it = ctx->it;
+    const int s = it.s;
+    HIPCHK(ctx, hipMemsetAsync(it.dbg, 0, size_t(dbg_size(s)) * sizeof(double), ctx->stream));
+    OKCHK(start_state(ctx, b, x, 0.5, 1));
+    HIPCHK(ctx, enqueue_iteration(it, ctx->stream));
+    if (P_out)
+        HIPCHK(ctx, launch_copy_cols(it.P, it.ld, it.fp32, s, it.op.n, P_out, ctx->stream));
+    if (AP_out)
+        HIPCHK(ctx, launch_copy_cols(it.AP, it.ld, it.fp32, s, it.op.n, AP_out, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<double> dbg(size_t(dbg_size(s)));
+    HIPCHK(ctx, hipMemcpy(dbg.data(), it.dbg, dbg.size() * sizeof(double), hipMemcpyDeviceToHost));
+    DevState h;
+    HIPCHK(ctx, hipMemcpy(&h, it.st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (alpha_tilde)
+        std::memcpy(alpha_tilde, dbg.data() + dbg_atil(s), s * sizeof(double));
+    if (G)
+        std::memcpy(G, dbg.data() + dbg_G(s), size_t(s) * s * sizeof(double));
+    if (ctil)
+        std::memcpy(ctil, dbg.data() + dbg_ctil(s), s * sizeof(double));
+    if (rnorm)
+        *rnorm = dbg[size_t(dbg_rho(s))];
+    if (h.status != SSTEP_OK)
+        return fail(ctx, static_cast<sstep_status>(h.status), "step stopped");
+    return SSTEP_OK;
+}
+
+sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int32_t reps, double *ms_out)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!b || !x || !ms_out || reps < 1)
+        return fail(ctx, SSTEP_E_ARG, "b, x, ms_out must not be NULL and reps >= 1");
+    const IterArgs &it = ctx->it;
+    hipStream_t s = ctx->stream;
+    OKCHK(start_state(ctx, b, x, 0.5, 1));
+    HIPCHK(ctx, enqueue_iteration(it, s));  // warm-up, leaves a valid basis and alpha behind
+    for (int cls = 0; cls < SSTEP_KT_COUNT; ++cls) {
+        HIPCHK(ctx, hipEventRecord(ctx->ev_t0, s));
+        for (int r = 0; r < reps; ++r) {
+            switch (cls) {
+            case SSTEP_KT_RESIDUAL:
+                HIPCHK(ctx, launch_residual(it, s, true));
+                break;
+            case SSTEP_KT_BASIS:
+                for (int j = 0; j < it.s; ++j)
+                    HIPCHK(ctx, launch_basis(it, j, s));
+                break;
+            case SSTEP_KT_GRAM:
+                HIPCHK(ctx, launch_gram(it, s));
+                break;
+            case SSTEP_KT_FGS:
+                HIPCHK(ctx, launch_fgs(it, s));
+                break;
+            default:
+                HIPCHK(ctx, launch_update(it, s));
+            }
+        }
+        HIPCHK(ctx, hipEventRecord(ctx->ev_t1, s));
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev_t1));
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+        ms_out[cls] = double(ms) / (cls == SSTEP_KT_BASIS ? double(reps) * it.s : double(reps));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_setup_batched(sstep_ctx **out, int32_t, const sstep_operator *, int32_t, int32_t, int32_t,
+                                 const double *, const double *, const sstep_options *)
+{
+    if (out)
+        *out = nullptr;
+    return fail(nullptr, SSTEP_E_UNSUPPORTED, "batched solves are not available");
+}
+
+sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *, double *const *, double, sstep_stats *)
+{
+    return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves are not available");
+}
+
+}  // extern "C"

@@ -1,0 +1,30 @@
+// Gram kernels for basis widths s = 17..24 (see gram_impl.h).
+#include "gram_impl.h"
+
+namespace sstep {
+
+hipError_t gram_launch_17_24(const IterArgs &a, hipStream_t st)
+{
+    switch (a.s) {
+    case 17:
+        return a.fp32 ? gram_launch_s<float, 17>(a, st) : gram_launch_s<double, 17>(a, st);
+    case 18:
+        return a.fp32 ? gram_launch_s<float, 18>(a, st) : gram_launch_s<double, 18>(a, st);
+    case 19:
+        return a.fp32 ? gram_launch_s<float, 19>(a, st) : gram_launch_s<double, 19>(a, st);
+    case 20:
+        return a.fp32 ? gram_launch_s<float, 20>(a, st) : gram_launch_s<double, 20>(a, st);
+    case 21:
+        return a.fp32 ? gram_launch_s<float, 21>(a, st) : gram_launch_s<double, 21>(a, st);
+    case 22:
+        return a.fp32 ? gram_launch_s<float, 22>(a, st) : gram_launch_s<double, 22>(a, st);
+    case 23:
+        return a.fp32 ? gram_launch_s<float, 23>(a, st) : gram_launch_s<double, 23>(a, st);
+    case 24:
+        return a.fp32 ? gram_launch_s<float, 24>(a, st) : gram_launch_s<double, 24>(a, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sstep

@@ -1,0 +1,491 @@
+// Streaming kernels of the outer iteration: residual + basis start, the fused
+// SpMV/Jacobi/Chebyshev basis step, the update x += P alpha, and helpers.
+// All of them are bound by HBM bandwidth (well under one flop per byte).
+#include "launch.h"
+
+namespace sstep {
+namespace {
+
+struct Launch1D {
+    uint32_t nbl;   // logical blocks
+    uint32_t per;   // logical blocks per XCD
+    uint32_t grid;  // hardware blocks (multiple of 8)
+};
+
+Launch1D plan_points(int64_t n)
+{
+    Launch1D l;
+    l.nbl = static_cast<uint32_t>((n + kBlock - 1) / kBlock);
+    l.per = (l.nbl + kNumXcd - 1) / kNumXcd;
+    l.grid = l.per * kNumXcd;
+    return l;
+}
+
+template <typename T>
+__device__ __forceinline__ void block_sum_store(T v, T *out)
+{
+    __shared__ T part[kBlock / kWave];
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0)
+        part[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = part[0];
+#pragma unroll
+        for (int q = 1; q < kBlock / kWave; ++q)
+            acc += part[q];
+        *out = acc;
+    }
+}
+
+// r = b - A x in FP64, partial sums of r^2 per logical block, and the basis
+// start p_0 = p0scale * (M^{-1} r or r) written as column 0 of P.
+template <class Op, typename TP>
+__global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict__ st, Op op, TP *__restrict__ p0,
+                                                     double *__restrict__ rpart, int64_t n, int64_t chunk,
+                                                     uint32_t per, uint32_t nbl, int p0_mode, int write_p0)
+{
+    if (st->done)
+        return;
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;
+    const double *__restrict__ b = st->b;
+    const double *__restrict__ x = st->x;
+    const double scale = st->p0scale;
+    const int64_t beg = static_cast<int64_t>(lb) * chunk;
+    const int64_t end = beg + chunk < n ? beg + chunk : n;
+    double acc = 0.0;
+    for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+        double pc, y, dinv;
+        op.apply(x, c, pc, y, dinv);
+        const double r = b[c] - y;
+        acc += r * r;
+        if (write_p0)
+            p0[c] = static_cast<TP>(scale * (p0_mode ? r : dinv * r));
+    }
+    block_sum_store(acc, rpart + lb);
+}
+
+// One step of the Chebyshev recurrence fused with the operator apply
+// (Sec. 2, Definition), for column j of the basis:
+//   y = A p_j                                   -> AP[:, j]
+//   p_1     = theta (M^{-1} y - sigma p_0)            (STEP 0, j = 0)
+//   p_{j+1} = 2 theta (M^{-1} y - sigma p_j) - p_{j-1} (STEP 1, 0 < j < s-1)
+//   nothing more for j = s-1                          (STEP 2)
+template <class Op, typename T, int STEP>
+__global__ __launch_bounds__(kBlock) void k_basis(const DevState *__restrict__ st, Op op, const T *__restrict__ pj,
+                                                  const T *__restrict__ pprev, T *__restrict__ apj,
+                                                  T *__restrict__ pnext, T theta, T sigma, int64_t n, uint32_t per,
+                                                  uint32_t nbl)
+{
+    if (st->done)
+        return;
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;
+    const int64_t c = static_cast<int64_t>(lb) * kBlock + threadIdx.x;
+    if (c >= n)
+        return;
+    T pc, y, dinv;
+    op.apply(pj, c, pc, y, dinv);
+    __builtin_nontemporal_store(y, apj + c);
+    if constexpr (STEP == 0) {
+        pnext[c] = theta * (dinv * y - sigma * pc);
+    } else if constexpr (STEP == 1) {
+        const T two_theta = T(2) * theta;
+        pnext[c] = two_theta * (dinv * y - sigma * pc) - pprev[c];
+    }
+}
+
+// x += P alpha, alpha = S atil from the FGS kernel (FP64; P in FP64 or FP32).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(const DevState *__restrict__ st, const T *__restrict__ P,
+                                                   int64_t ld, int s, int64_t n, uint32_t per, uint32_t nbl)
+{
+    if (st->done)
+        return;
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;
+    const int64_t c = static_cast<int64_t>(lb) * kBlock + threadIdx.x;
+    if (c >= n)
+        return;
+    double *__restrict__ x = st->x;
+    double acc = 0.0;
+    int i = 0;
+    for (; i + 4 <= s; i += 4) {
+        const T v0 = P[(i + 0) * ld + c];
+        const T v1 = P[(i + 1) * ld + c];
+        const T v2 = P[(i + 2) * ld + c];
+        const T v3 = P[(i + 3) * ld + c];
+        acc += static_cast<double>(v0) * st->alpha[i + 0];
+        acc += static_cast<double>(v1) * st->alpha[i + 1];
+        acc += static_cast<double>(v2) * st->alpha[i + 2];
+        acc += static_cast<double>(v3) * st->alpha[i + 3];
+    }
+    for (; i < s; ++i)
+        acc += static_cast<double>(P[i * ld + c]) * st->alpha[i];
+    x[c] += acc;
+}
+
+// FP32+IR only: p0scale = 2^-e with e the exponent of ||r_0|| / sqrt(n), so
+// that p_0 has entries of order one; the scaling is exact and the column
+// scaling of the Gram matrix absorbs it.  Reads the residual partials of a
+// norm-only residual pass.
+__global__ __launch_bounds__(kBlock) void k_p0scale(DevState *st, const double *__restrict__ rpart, int nbr,
+                                                    double inv_sqrt_n)
+{
+    if (st->done)
+        return;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nbr; q += kBlock)
+        acc += rpart[q];
+    __shared__ double tot;
+    block_sum_store(acc, &tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double rms = sqrt(tot) * inv_sqrt_n;
+        st->p0scale = (rms > 0.0 && isfinite(rms)) ? ldexp(1.0, -ilogb(rms)) : 1.0;
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_apply(Op op, const double *__restrict__ x, double *__restrict__ y,
+                                                  int64_t n, uint32_t per, uint32_t nbl)
+{
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;
+    const int64_t c = static_cast<int64_t>(lb) * kBlock + threadIdx.x;
+    if (c >= n)
+        return;
+    double pc, yy, dinv;
+    op.apply(x, c, pc, yy, dinv);
+    y[c] = yy;
+}
+
+// dA = -lam x^T on the CSR pattern.
+__global__ __launch_bounds__(kBlock) void k_grad_csr(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                     const double *__restrict__ lam, const double *__restrict__ x,
+                                                     double *__restrict__ dA, int64_t n, int accumulate)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const double li = lam[i];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const double g = -li * x[ci[k]];
+        dA[k] = accumulate ? dA[k] + g : g;
+    }
+}
+
+// Face gradient for one face array.  Faces along axis a are indexed
+// (c0, c1, c2) with c_a in [0, N_a] (N_a + 1 faces) and the other two
+// coordinates over the grid; face f separates cells f-1 and f along a.
+// interior: -(lam_p - lam_q)(x_p - x_q); boundary: -lam_p x_p.
+__global__ __launch_bounds__(kBlock) void k_grad_faces(const double *__restrict__ lam, const double *__restrict__ x,
+                                                       double *__restrict__ dk, int nx, int ny, int nz, int axis,
+                                                       int accumulate)
+{
+    const int fx = nx + (axis == 0), fy = ny + (axis == 1), fz = nz + (axis == 2);
+    const int64_t nf = static_cast<int64_t>(fx) * fy * fz;
+    const int64_t f = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (f >= nf)
+        return;
+    const int i = static_cast<int>(f % fx);
+    const int64_t q = f / fx;
+    const int j = static_cast<int>(q % fy);
+    const int k = static_cast<int>(q / fy);
+    const int64_t nxy = static_cast<int64_t>(nx) * ny;
+    int pos, lim;
+    int64_t stride;
+    if (axis == 0) {
+        pos = i, lim = nx, stride = 1;
+    } else if (axis == 1) {
+        pos = j, lim = ny, stride = nx;
+    } else {
+        pos = k, lim = nz, stride = nxy;
+    }
+    // cell on the high side of the face (coordinate pos along the axis)
+    const int ci0 = axis == 0 ? (i < nx ? i : nx - 1) : i;
+    const int cj0 = axis == 1 ? (j < ny ? j : ny - 1) : j;
+    const int ck0 = axis == 2 ? (k < nz ? k : nz - 1) : k;
+    const int64_t cell = ci0 + nx * (static_cast<int64_t>(cj0) + static_cast<int64_t>(ny) * ck0);
+    double g;
+    if (pos == 0) {
+        g = -lam[cell] * x[cell];
+    } else if (pos == lim) {
+        g = -lam[cell] * x[cell];  // clamped to the last cell: the boundary face's own cell
+    } else {
+        const int64_t lo = cell - stride;
+        g = -(lam[lo] - lam[cell]) * (x[lo] - x[cell]);
+    }
+    dk[f] = accumulate ? dk[f] + g : g;
+}
+
+__global__ __launch_bounds__(kBlock) void k_convert(const float *__restrict__ src, double *__restrict__ dst, int64_t n)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c < n)
+        dst[c] = static_cast<double>(src[c]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_fp32(const double *__restrict__ src, float *__restrict__ dst, int64_t n)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c < n)
+        dst[c] = static_cast<float>(src[c]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_cols(const T *__restrict__ src, int64_t ld, int s, int64_t n,
+                                                      double *__restrict__ dst)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c >= n)
+        return;
+    for (int j = 0; j < s; ++j)
+        dst[j * n + c] = static_cast<double>(src[j * ld + c]);
+}
+
+// Diagonal of the face operator, summed in the order west, east, south,
+// north, bottom, top.
+// Flags a non-positive or non-finite diagonal.
+__global__ __launch_bounds__(kBlock) void k_diag_faces(Grid3 g, const double *__restrict__ kx,
+                                                       const double *__restrict__ ky, const double *__restrict__ kz,
+                                                       double *__restrict__ dvec, int *__restrict__ bad, int64_t n)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c >= n)
+        return;
+    const uint32_t q = fdiv(static_cast<uint32_t>(c), g.dx);
+    const uint32_t k = fdiv(q, g.dy);
+    const int64_t fx = c + q;
+    const int64_t fy = c + static_cast<int64_t>(k) * g.nx;
+    const double d = ((((kx[fx] + kx[fx + 1]) + ky[fy]) + ky[fy + g.nx]) + kz[c]) + kz[c + g.nxy];
+    dvec[c] = d;
+    if (!(d > 0.0) || !isfinite(d))
+        atomicOr(bad, 1);
+}
+
+// Diagonal of a CSR matrix; flags a missing, non-positive or non-finite entry.
+__global__ __launch_bounds__(kBlock) void k_diag_csr(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                     const double *__restrict__ val, double *__restrict__ dvec,
+                                                     int *__restrict__ bad, int64_t n)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    double d = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i)
+            d = val[k];
+    dvec[i] = d;
+    if (!(d > 0.0) || !isfinite(d))
+        atomicOr(bad, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_invert(const double *__restrict__ src, double *__restrict__ dst,
+                                                   int64_t n, int precond)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c < n)
+        dst[c] = precond ? 1.0 / src[c] : 1.0;
+}
+
+inline uint32_t blocks_for(int64_t n) { return static_cast<uint32_t>((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+OpPoisson7<T> make_poisson(const OpDev &op)
+{
+    return OpPoisson7<T>{op.g, op.precond ? T(1) / T(6) : T(1)};
+}
+
+template <typename T>
+struct Ops;
+template <>
+struct Ops<double> {
+    static OpFaces7<double> faces(const OpDev &op) { return {op.g, op.kx, op.ky, op.kz, op.precond}; }
+    static OpCsr<double> csr(const OpDev &op) { return {op.rp, op.ci, op.val, op.invd}; }
+};
+template <>
+struct Ops<float> {
+    static OpFaces7<float> faces(const OpDev &op) { return {op.g, op.kx32, op.ky32, op.kz32, op.precond}; }
+    static OpCsr<float> csr(const OpDev &op) { return {op.rp, op.ci, op.val32, op.invd32}; }
+};
+
+template <class Op, typename TP>
+hipError_t residual_for(const IterArgs &a, const Op &op, hipStream_t st, bool write_p0)
+{
+    const uint32_t per = (static_cast<uint32_t>(a.nbr) + kNumXcd - 1) / kNumXcd;
+    hipLaunchKernelGGL((k_residual<Op, TP>), dim3(per * kNumXcd), dim3(kBlock), 0, st, a.st, op,
+                       static_cast<TP *>(a.P), a.rpart, a.op.n, a.rchunk, per, static_cast<uint32_t>(a.nbr),
+                       a.p0_mode, write_p0 ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <typename TP>
+hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
+{
+    switch (a.op.kind) {
+    case kOpPoisson:
+        return residual_for<OpPoisson7<double>, TP>(a, make_poisson<double>(a.op), st, write_p0);
+    case kOpFaces:
+        return residual_for<OpFaces7<double>, TP>(a, Ops<double>::faces(a.op), st, write_p0);
+    default:
+        return residual_for<OpCsr<double>, TP>(a, Ops<double>::csr(a.op), st, write_p0);
+    }
+}
+
+template <class Op, typename T>
+hipError_t basis_for(const IterArgs &a, const Op &op, int j, hipStream_t st)
+{
+    const Launch1D l = plan_points(a.op.n);
+    T *P = static_cast<T *>(a.P);
+    T *AP = static_cast<T *>(a.AP);
+    const T *pj = P + j * a.ld;
+    const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
+    T *apj = AP + j * a.ld;
+    T *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
+    const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
+    if (j + 1 >= a.s)
+        hipLaunchKernelGGL((k_basis<Op, T, 2>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
+                           theta, sigma, a.op.n, l.per, l.nbl);
+    else if (j == 0)
+        hipLaunchKernelGGL((k_basis<Op, T, 0>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
+                           theta, sigma, a.op.n, l.per, l.nbl);
+    else
+        hipLaunchKernelGGL((k_basis<Op, T, 1>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
+                           theta, sigma, a.op.n, l.per, l.nbl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t basis_t(const IterArgs &a, int j, hipStream_t st)
+{
+    switch (a.op.kind) {
+    case kOpPoisson:
+        return basis_for<OpPoisson7<T>, T>(a, make_poisson<T>(a.op), j, st);
+    case kOpFaces:
+        return basis_for<OpFaces7<T>, T>(a, Ops<T>::faces(a.op), j, st);
+    default:
+        return basis_for<OpCsr<T>, T>(a, Ops<T>::csr(a.op), j, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0)
+{
+    return a.fp32 ? residual_t<float>(a, st, write_p0) : residual_t<double>(a, st, write_p0);
+}
+
+hipError_t launch_p0scale(const IterArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_p0scale, dim3(1), dim3(kBlock), 0, st, a.st, a.rpart, a.nbr, a.inv_sqrt_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st)
+{
+    return a.fp32 ? basis_t<float>(a, j, st) : basis_t<double>(a, j, st);
+}
+
+hipError_t launch_update(const IterArgs &a, hipStream_t st)
+{
+    const Launch1D l = plan_points(a.op.n);
+    if (a.fp32)
+        hipLaunchKernelGGL(k_update<float>, dim3(l.grid), dim3(kBlock), 0, st, a.st, static_cast<const float *>(a.P),
+                           a.ld, a.s, a.op.n, l.per, l.nbl);
+    else
+        hipLaunchKernelGGL(k_update<double>, dim3(l.grid), dim3(kBlock), 0, st, a.st,
+                           static_cast<const double *>(a.P), a.ld, a.s, a.op.n, l.per, l.nbl);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const OpDev &op, const double *x, double *y, hipStream_t st)
+{
+    const Launch1D l = plan_points(op.n);
+    switch (op.kind) {
+    case kOpPoisson:
+        hipLaunchKernelGGL(k_apply<OpPoisson7<double>>, dim3(l.grid), dim3(kBlock), 0, st, make_poisson<double>(op),
+                           x, y, op.n, l.per, l.nbl);
+        break;
+    case kOpFaces:
+        hipLaunchKernelGGL(k_apply<OpFaces7<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::faces(op), x,
+                           y, op.n, l.per, l.nbl);
+        break;
+    default:
+        hipLaunchKernelGGL(k_apply<OpCsr<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::csr(op), x, y,
+                           op.n, l.per, l.nbl);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const OpDev &op, const double *lam, const double *x, double *dA, int accumulate,
+                       hipStream_t st)
+{
+    if (op.kind == kOpCsr) {
+        hipLaunchKernelGGL(k_grad_csr, dim3(blocks_for(op.n)), dim3(kBlock), 0, st, op.rp, op.ci, lam, x, dA, op.n,
+                           accumulate);
+        return hipGetLastError();
+    }
+    const int nx = op.g.nx, ny = op.g.ny, nz = op.g.nz;
+    const int64_t nfx = static_cast<int64_t>(nx + 1) * ny * nz;
+    const int64_t nfy = static_cast<int64_t>(nx) * (ny + 1) * nz;
+    const int64_t nfz = static_cast<int64_t>(nx) * ny * (nz + 1);
+    hipLaunchKernelGGL(k_grad_faces, dim3(blocks_for(nfx)), dim3(kBlock), 0, st, lam, x, dA, nx, ny, nz, 0,
+                       accumulate);
+    hipLaunchKernelGGL(k_grad_faces, dim3(blocks_for(nfy)), dim3(kBlock), 0, st, lam, x, dA + nfx, nx, ny, nz, 1,
+                       accumulate);
+    hipLaunchKernelGGL(k_grad_faces, dim3(blocks_for(nfz)), dim3(kBlock), 0, st, lam, x, dA + nfx + nfy, nx, ny, nz,
+                       2, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const float *src, double *dst, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_convert, dim3(blocks_for(n)), dim3(kBlock), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(const void *src, int64_t ld, int fp32, int s, int64_t n, double *dst, hipStream_t st)
+{
+    if (fp32)
+        hipLaunchKernelGGL(k_copy_cols<float>, dim3(blocks_for(n)), dim3(kBlock), 0, st,
+                           static_cast<const float *>(src), ld, s, n, dst);
+    else
+        hipLaunchKernelGGL(k_copy_cols<double>, dim3(blocks_for(n)), dim3(kBlock), 0, st,
+                           static_cast<const double *>(src), ld, s, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_from_faces(const OpDev &op, double *dvec, int *bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_faces, dim3(blocks_for(op.n)), dim3(kBlock), 0, st, op.g, op.kx, op.ky, op.kz, dvec,
+                       bad, op.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_from_csr(const OpDev &op, double *dvec, int *bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_csr, dim3(blocks_for(op.n)), dim3(kBlock), 0, st, op.rp, op.ci, op.val, dvec, bad,
+                       op.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_fp32(const double *src, float *dst, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_fp32, dim3(blocks_for(n)), dim3(kBlock), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert(const double *src, double *dst, int64_t n, int precond, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_invert, dim3(blocks_for(n)), dim3(kBlock), 0, st, src, dst, n, precond);
+    return hipGetLastError();
+}
+
+}  // namespace sstep

@@ -1,0 +1,85 @@
+// Host-side launch interface between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+
+namespace sstep {
+
+enum OpKind { kOpCsr = 0, kOpPoisson = 1, kOpFaces = 2 };
+
+// Device copy of the operator in both precisions (the FP32 arrays exist only
+// in FP32+IR mode).
+struct OpDev {
+    int kind = kOpPoisson;
+    int precond = 1;
+    int64_t n = 0;
+    int64_t nnz = 0;
+    Grid3 g{};
+    const int32_t *rp = nullptr;
+    const int32_t *ci = nullptr;
+    const double *val = nullptr;
+    const float *val32 = nullptr;
+    const double *kx = nullptr, *ky = nullptr, *kz = nullptr;
+    const float *kx32 = nullptr, *ky32 = nullptr, *kz32 = nullptr;
+    const double *invd = nullptr;  // CSR: M^{-1} diagonal
+    const float *invd32 = nullptr;
+    const double *dvec = nullptr;  // M diagonal (Jacobi, non-constant diagonal)
+    const float *dvec32 = nullptr;
+};
+
+// Everything one outer iteration needs; all pointers are device memory.
+struct IterArgs {
+    DevState *st = nullptr;
+    OpDev op;
+    int fp32 = 0;     // 1 = FP32 basis / SpMV / Gram
+    int p0_mode = 0;  // 0: p_0 = M^{-1} r, 1: p_0 = r
+    int s = 0, nu = 0;
+    double theta = 0, sigma = 0;
+    void *P = nullptr;   // n x s, column-major, leading dimension ld
+    void *AP = nullptr;  // n x s
+    int64_t ld = 0;
+    double *rpart = nullptr;  // residual-norm partial sums [nbr]
+    int nbr = 0;
+    int64_t rchunk = 0;
+    double *gpart = nullptr;  // Gram partial sums [E][nbg]
+    int nbg = 0;
+    int64_t gchunk = 0;
+    int wdvec = 0;        // Gram right-hand side uses M-diagonal * p_0 (else p_0)
+    double cscale = 1.0;  // constant factor applied to c = P^T (W) in the FGS kernel
+    double *dbg = nullptr;   // G (s*s), ctil (s), atil (s), d (s), rho: written by the FGS kernel
+    double *hist = nullptr;  // [2 * hist_cap]: relres then delta
+    int hist_cap = 0;
+    double inv_sqrt_n = 1.0;
+};
+
+// Debug block layout written by the FGS kernel.
+__host__ __device__ inline int64_t dbg_G(int) { return 0; }
+__host__ __device__ inline int64_t dbg_ctil(int s) { return int64_t(s) * s; }
+__host__ __device__ inline int64_t dbg_atil(int s) { return int64_t(s) * s + s; }
+__host__ __device__ inline int64_t dbg_d(int s) { return int64_t(s) * s + 2 * s; }
+__host__ __device__ inline int64_t dbg_rho(int s) { return int64_t(s) * s + 3 * s; }
+__host__ __device__ inline int64_t dbg_size(int s) { return int64_t(s) * s + 3 * s + 1; }
+
+__host__ __device__ inline int gram_entries(int s) { return s * (s + 1) / 2 + s; }
+
+hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
+hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
+hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);
+hipError_t launch_gram(const IterArgs &a, hipStream_t st);
+hipError_t launch_fgs(const IterArgs &a, hipStream_t st);
+hipError_t launch_update(const IterArgs &a, hipStream_t st);
+hipError_t launch_apply(const OpDev &op, const double *x, double *y, hipStream_t st);
+hipError_t launch_grad(const OpDev &op, const double *lam, const double *x, double *dA, int accumulate,
+                       hipStream_t st);
+hipError_t launch_convert(const float *src, double *dst, int64_t n, hipStream_t st);
+hipError_t launch_copy_cols(const void *src, int64_t ld, int fp32, int s, int64_t n, double *dst, hipStream_t st);
+hipError_t launch_diag_from_faces(const OpDev &op, double *dvec, int *bad, hipStream_t st);
+hipError_t launch_diag_from_csr(const OpDev &op, double *dvec, int *bad, hipStream_t st);
+hipError_t launch_to_fp32(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_invert(const double *src, double *dst, int64_t n, int precond, hipStream_t st);
+
+}  // namespace sstep
