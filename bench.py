@@ -24,6 +24,10 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 METRIC = "time-to-1e-8 residual & HBM GB/s, 11.2M-unknown Poisson: FP64 vs FP32+IR"
 HBM_PEAK_GBPS = 8000.0
 
@@ -102,6 +106,7 @@ def main():
     b = solvers[modes[0]].apply(xstar)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    log(f"setup done: n={n}, s={s}, nu={nu}, modes={modes}")
 
     def one_step(times, iters, relres):
         for m in modes:
@@ -117,6 +122,7 @@ def main():
     iters, relres = {}, {}
     for _ in range(args.warmup):
         one_step(scratch, iters, relres)
+    log(f"warmup done: {scratch}, iters {iters}")
     times = {m: [] for m in modes}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -124,6 +130,7 @@ def main():
         one_step(times, iters, relres)
     torch.cuda.synchronize()
     total_ms = 1e3 * (time.perf_counter() - t_start)
+    log(f"timed steps done: {times}")
 
     # true residual of the last FP64 solve, recomputed with the library's apply
     results = {}
@@ -189,7 +196,9 @@ def main():
         "roofline": roofline,
         "results": results,
     }
+    log(f"kernel times: { {m: results[m]['kernel_ms'] for m in modes} }")
     if not args.no_cpu_baseline:
+        log("timing the oracle on the host (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(N, s, nu, results[main_mode]["outer_iters"], args.cpu_sample)
     for sv in solvers.values():
         sv.close()

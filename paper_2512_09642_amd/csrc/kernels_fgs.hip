@@ -110,8 +110,10 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
         }
         return;
     }
+    // c = P^T r: the reduction formed P^T (M p_0) (times cscale for a constant
+    // M) with p_0 = p0scale * M^{-1} r, so divide the scale back out.
     const double d = own ? 1.0 / sqrt(gii) : 0.0;
-    const double ct = own ? d * (sg[T0 + i] * cscale) : 0.0;
+    const double ct = own ? d * (sg[T0 + i] * cscale / st->p0scale) : 0.0;
     double grow[kMaxS];
 #pragma unroll
     for (int j = 0; j < kMaxS; ++j) {
