@@ -93,6 +93,10 @@ typedef struct {
     int32_t max_outer;      /* outer-iteration limit, default 10000 */
     int32_t graph_chunk;    /* outer iterations per graph replay, default 4 */
     int32_t record_history; /* 1 = keep per-iteration relative residual and delta on the device */
+    int32_t autotune;       /* 1 (default) = at setup, time the Gram kernel's schedules (blocks, row
+                               slabs) on the context's buffers and keep the fastest, cached in
+                               $SSTEP_TUNE_CACHE or ~/.cache/sstep/tune.json; systems under 2^20
+                               unknowns use the defaults; 0 = defaults */
     void *stream;           /* hipStream_t the caller's data is ordered on (NULL = default) */
 } sstep_options;
 

@@ -2,12 +2,21 @@
 // operator, workspace, the captured outer-iteration graph and the solve loop.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "launch.h"
 #include "sstep.h"
@@ -193,8 +202,9 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
         double *invd = const_cast<double *>(op.invd);
         if (first) {
             OKCHK(to_device(ctx, &val, A->val, size_t(op.nnz), A->ptr_space));
-            OKCHK(dalloc(ctx, &dvec, size_t(op.n)));
+            OKCHK(dalloc(ctx, &dvec, size_t(ctx->it.ld)));
             OKCHK(dalloc(ctx, &invd, size_t(op.n)));
+            HIPCHK(ctx, hipMemsetAsync(dvec, 0, size_t(ctx->it.ld) * sizeof(double), s));
             op.val = val;
             op.dvec = dvec;
             op.invd = invd;
@@ -209,7 +219,8 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
             if (first) {
                 OKCHK(dalloc(ctx, &val32, size_t(op.nnz)));
                 OKCHK(dalloc(ctx, &invd32, size_t(op.n)));
-                OKCHK(dalloc(ctx, &dvec32, size_t(op.n)));
+                OKCHK(dalloc(ctx, &dvec32, size_t(ctx->it.ld)));
+                HIPCHK(ctx, hipMemsetAsync(dvec32, 0, size_t(ctx->it.ld) * sizeof(float), s));
                 op.val32 = val32;
                 op.invd32 = invd32;
                 op.dvec32 = dvec32;
@@ -224,7 +235,8 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
         double *dvec = const_cast<double *>(op.dvec);
         if (first) {
             OKCHK(dalloc(ctx, &k, size_t(nfx + nfy + nfz)));
-            OKCHK(dalloc(ctx, &dvec, size_t(op.n)));
+            OKCHK(dalloc(ctx, &dvec, size_t(ctx->it.ld)));
+            HIPCHK(ctx, hipMemsetAsync(dvec, 0, size_t(ctx->it.ld) * sizeof(double), s));
             op.kx = k;
             op.ky = k + nfx;
             op.kz = k + nfx + nfy;
@@ -238,7 +250,8 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
             float *k32 = const_cast<float *>(op.kx32), *dvec32 = const_cast<float *>(op.dvec32);
             if (first) {
                 OKCHK(dalloc(ctx, &k32, size_t(nfx + nfy + nfz)));
-                OKCHK(dalloc(ctx, &dvec32, size_t(op.n)));
+                OKCHK(dalloc(ctx, &dvec32, size_t(ctx->it.ld)));
+                HIPCHK(ctx, hipMemsetAsync(dvec32, 0, size_t(ctx->it.ld) * sizeof(float), s));
                 op.kx32 = k32;
                 op.ky32 = k32 + nfx;
                 op.kz32 = k32 + nfx + nfy;
@@ -292,6 +305,140 @@ sstep_status start_state(sstep_ctx *ctx, const double *b, double *x, double tol,
     if (ctx->it.fp32) {
         HIPCHK(ctx, launch_residual(ctx->it, ctx->stream, false));
         HIPCHK(ctx, launch_p0scale(ctx->it, ctx->stream));
+    }
+    return SSTEP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Gram schedule and its autotuner.
+// ---------------------------------------------------------------------------
+struct GramSchedule {
+    int nbg;       // partial blocks
+    int64_t slab;  // 0: contiguous chunks; > 0: strided slabs of this many rows
+    double us;     // measured time per launch (0 = not measured)
+};
+
+GramSchedule default_gram_schedule(const IterArgs &it)
+{
+    // Measured on MI355X at 224^3, s = 16: FP64 prefers one contiguous chunk
+    // per CU, FP32 prefers grid-strided 2048-row slabs.
+    return it.fp32 ? GramSchedule{256, 2048, 0.0} : GramSchedule{256, 0, 0.0};
+}
+
+void set_gram_schedule(IterArgs &it, const GramSchedule &g)
+{
+    const int64_t blocks_needed = (it.ld + kPad - 1) / kPad;
+    it.nbg = int(std::max<int64_t>(1, std::min<int64_t>(g.nbg, blocks_needed)));
+    it.gslab = g.slab;
+    it.gchunk = round_up((it.ld + it.nbg - 1) / it.nbg, kPad);
+}
+
+std::string tune_cache_path()
+{
+    if (const char *p = std::getenv("SSTEP_TUNE_CACHE"))
+        return p;
+    const char *home = std::getenv("HOME");
+    if (!home)
+        return "";
+    std::string dir = std::string(home) + "/.cache";
+    mkdir(dir.c_str(), 0755);
+    dir += "/sstep";
+    mkdir(dir.c_str(), 0755);
+    return dir + "/tune.json";
+}
+
+std::string tune_key(const IterArgs &it)
+{
+    std::ostringstream k;
+    k << "gfx950 gram s=" << it.s << " prec=" << (it.fp32 ? "fp32" : "fp64") << " rows=" << it.ld
+      << " wd=" << it.wdvec;
+    return k.str();
+}
+
+// The cache is a JSON object written one entry per line:
+//   "key": {"nbg": 256, "slab": 0, "us": 507.3},
+std::map<std::string, GramSchedule> read_tune_cache(const std::string &path)
+{
+    std::map<std::string, GramSchedule> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"'), b = line.find("\": {");
+        if (a == std::string::npos || b == std::string::npos || b <= a)
+            continue;
+        GramSchedule g{0, 0, 0.0};
+        long long slab = 0;
+        if (std::sscanf(line.c_str() + b, "\": {\"nbg\": %d, \"slab\": %lld, \"us\": %lf", &g.nbg, &slab, &g.us) == 3) {
+            g.slab = slab;
+            m[line.substr(a + 1, b - a - 1)] = g;
+        }
+    }
+    return m;
+}
+
+void write_tune_cache(const std::string &path, const std::map<std::string, GramSchedule> &m)
+{
+    const std::string tmp = path + ".tmp" + std::to_string(::getpid());
+    {
+        std::ofstream f(tmp);
+        if (!f)
+            return;
+        f << "{\n";
+        size_t q = 0;
+        for (const auto &kv : m) {
+            f << "  \"" << kv.first << "\": {\"nbg\": " << kv.second.nbg << ", \"slab\": " << kv.second.slab
+              << ", \"us\": " << kv.second.us << "}" << (++q < m.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+// Times each candidate Gram schedule on the context's own buffers (the values
+// do not matter for the timing) and keeps the fastest; the result is cached
+// on disk per device, basis width, precision, row count and right-hand-side mode.
+sstep_status tune_gram(sstep_ctx *ctx)
+{
+    IterArgs &it = ctx->it;
+    const std::string path = tune_cache_path();
+    const std::string key = tune_key(it);
+    std::map<std::string, GramSchedule> cache;
+    if (!path.empty()) {
+        cache = read_tune_cache(path);
+        auto f = cache.find(key);
+        if (f != cache.end() && f->second.nbg > 0) {
+            set_gram_schedule(it, f->second);
+            return SSTEP_OK;
+        }
+    }
+    std::vector<GramSchedule> cand;
+    for (int nbg : {256, 384, 512, 1024, 2048})
+        cand.push_back({nbg, 0, 0.0});
+    for (int64_t slab : {int64_t(1024), int64_t(2048), int64_t(4096)})
+        for (int nbg : {256, 512, 1024, 2048})
+            cand.push_back({nbg, slab, 0.0});
+    GramSchedule best = default_gram_schedule(it);
+    best.us = 1e30;
+    for (GramSchedule &c : cand) {
+        set_gram_schedule(it, c);
+        HIPCHK(ctx, launch_gram(it, ctx->stream));  // warm-up
+        HIPCHK(ctx, hipEventRecord(ctx->ev_t0, ctx->stream));
+        const int reps = 3;
+        for (int r = 0; r < reps; ++r)
+            HIPCHK(ctx, launch_gram(it, ctx->stream));
+        HIPCHK(ctx, hipEventRecord(ctx->ev_t1, ctx->stream));
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev_t1));
+        float ms = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+        c.us = 1e3 * ms / reps;
+        if (c.us < best.us)
+            best = c;
+    }
+    set_gram_schedule(it, best);
+    if (!path.empty()) {
+        cache[key] = best;
+        write_tune_cache(path, cache);
     }
     return SSTEP_OK;
 }
@@ -388,6 +535,7 @@ void sstep_default_options(sstep_options *opt)
     opt->max_outer = 10000;
     opt->graph_chunk = 4;
     opt->record_history = 0;
+    opt->autotune = 1;
     opt->stream = nullptr;
 }
 
@@ -514,6 +662,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         op.ci = ci;
         ctx->grad_size = A->nnz;
     }
+    it.ld = round_up(op.n, kPad);
     OKCHK(load_coefficients(ctx, A, true));
 
     // right-hand side of the Gram system: c = P^T r with r = M p_0 (p0_mode 0)
@@ -522,25 +671,22 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     it.wdvec = jac_p0 && op.kind != kOpPoisson;
     it.cscale = (jac_p0 && op.kind == kOpPoisson) ? 6.0 : 1.0;
 
-    // workspace
+    // workspace: P and AP zero-filled, so the padding rows n..ld-1 read as 0
     const int64_t n = op.n;
     const size_t w = it.fp32 ? sizeof(float) : sizeof(double);
-    it.ld = round_up(n, 64);
     {
         char *P = nullptr, *AP = nullptr;
         OKCHK(dalloc(ctx, &P, size_t(it.ld) * s * w));
         OKCHK(dalloc(ctx, &AP, size_t(it.ld) * s * w));
+        HIPCHK(ctx, hipMemsetAsync(P, 0, size_t(it.ld) * s * w, ctx->stream));
+        HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(it.ld) * s * w, ctx->stream));
         it.P = P;
         it.AP = AP;
     }
-    it.nbr = int(std::min<int64_t>(2048, (n + kBlock - 1) / kBlock));
+    it.nbr = int(std::min<int64_t>(1024, (n + kBlock - 1) / kBlock));
     it.rchunk = round_up((n + it.nbr - 1) / it.nbr, kBlock);
-    const int ng = s <= 6 ? 1 : s <= 10 ? 2 : s <= 16 ? 4 : s <= 24 ? 8 : 16;
-    const int64_t target = ng <= 4 ? 1024 : ng == 8 ? 512 : 256;
-    it.nbg = int(std::min<int64_t>(target, (n + kWave - 1) / kWave));
-    it.gchunk = round_up((n + it.nbg - 1) / it.nbg, kWave);
     OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
-    OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * it.nbg));
+    OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * kMaxGramBlocks));
     OKCHK(dalloc(ctx, &it.st, 1));
     OKCHK(dalloc(ctx, &it.dbg, size_t(dbg_size(s))));
     it.hist_cap = o.record_history ? o.max_outer + 1 : 0;
@@ -548,6 +694,9 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     it.inv_sqrt_n = 1.0 / std::sqrt(double(n));
     HIPCHK(ctx, hipMemsetAsync(it.st, 0, sizeof(DevState), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    set_gram_schedule(it, default_gram_schedule(it));
+    if (o.autotune && n >= (int64_t(1) << 20))
+        OKCHK(tune_gram(ctx));
 
     ctx->chunk = o.graph_chunk;
     OKCHK(capture_graph(ctx));

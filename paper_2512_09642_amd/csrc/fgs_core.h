@@ -1,0 +1,212 @@
+// Stopping test, column scaling and forward Gauss-Seidel on the reduced Gram
+// system, executed by one wave.  Shared by the single-system and the batched
+// outer iterations.
+#pragma once
+
+#include "gram_impl.h"
+
+namespace sstep {
+
+// Value of v held by lane l (l uniform across the wave), as scalar registers.
+__device__ __forceinline__ double readlane(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// sg holds the reduced sums: Gram entries in canonical order (lower triangle
+// row by row, then the right-hand side) and ||r||^2 at index E.
+// 1. Stopping test on the true residual: stop when ||r_k|| < tol ||r_0||
+//    (strict; Sec. 8), at max_outer, or on a non-finite norm.
+// 2. Column scaling (Sec. 2): d_i = G_raw,ii^{-1/2}; G = S G_raw S with the
+//    diagonal set to one and each off-diagonal pair scaled once from the lower
+//    triangle, so G is exactly symmetric; ctil = S c.  A diagonal entry that is
+//    not positive and finite is a breakdown.
+// 3. nu forward Gauss-Seidel sweeps from atil = 0 (Sec. 2, FGS iteration;
+//    Sec. 3), j = 0..s-1 in order, in residual form: lane i keeps row i of G
+//    and rho_i = ctil_i - (G atil)_i; visiting j adds rho_j to atil_j and
+//    subtracts G_ij rho_j from every rho_i -- the same update as
+//    atil_j <- ctil_j - sum_{i != j} G_ji atil_i since G_jj = 1.
+// 4. alpha = S atil for the update kernel; delta = ||ctil - G atil|| / ||ctil||
+//    (the Gram-solve accuracy of Sec. 7) and the history.
+// The basis width s is a template parameter so that the ν·s dependent steps of
+// the sweeps carry no bound checks.  Returns 1 when this call stopped the
+// solve (the caller may count it).
+template <int s>
+__device__ __forceinline__ int fgs_wave(DevState *__restrict__ st, const double *__restrict__ sg, int nu,
+                                        double cscale, int fp32, double inv_sqrt_n, double *__restrict__ dbg,
+                                        double *__restrict__ hist, int hist_cap)
+{
+    const int lane = threadIdx.x % kWave;
+    constexpr int E = s * (s + 1) / 2 + s;
+    constexpr int T0 = s * (s + 1) / 2;
+    // ---- stopping test ----------------------------------------------------
+    const double rho = sqrt(sg[E]);
+    const int first = st->first;
+    const double rho0 = first ? rho : st->rho0;
+    const int k = st->iter;
+    int stop = 0, status = 0;
+    double relres = 0.0;
+    if (first && rho0 == 0.0) {
+        stop = 1;
+    } else if (!isfinite(rho)) {
+        stop = 1;
+        status = 6;  // SSTEP_E_NONFINITE
+        relres = rho;
+    } else {
+        relres = rho / rho0;
+        if (!st->no_stop) {
+            if (rho < st->tol * rho0)
+                stop = 1;
+            else if (k >= st->max_outer) {
+                stop = 1;
+                status = 5;  // SSTEP_E_NOCONV
+            }
+        }
+    }
+    if (lane == 0) {
+        st->first = 0;
+        st->rho0 = rho0;
+        st->rho = rho;
+        st->relres = relres;
+        if (k < hist_cap)
+            hist[k] = relres;
+        dbg[dbg_rho(s)] = rho;
+        if (stop) {
+            st->status = status;
+            st->done = 1;
+        }
+    }
+    if (stop)
+        return 1;
+
+    // ---- column scaling -----------------------------------------------------
+    const int i = lane;
+    const bool own = i < s;
+    const double gii = own ? sg[tri_index(i, i)] : 1.0;
+    const bool bad = own && !(gii > 0.0 && isfinite(gii));
+    if (__any(bad)) {
+        if (lane == 0) {
+            st->status = 4;  // SSTEP_E_BREAKDOWN
+            st->done = 1;
+        }
+        return 1;
+    }
+    // c = P^T r: the reduction formed P^T (M p_0) (times cscale for a constant
+    // M) with p_0 = p0scale * M^{-1} r, so divide the scale back out.
+    const double d = own ? 1.0 / sqrt(gii) : 0.0;
+    const double ct = own ? d * (sg[T0 + i] * cscale / st->p0scale) : 0.0;
+    double grow[s];
+#pragma unroll
+    for (int j = 0; j < s; ++j) {
+        double g = 0.0;
+        {
+            const double dj = readlane(d, j);
+            if (own) {
+                if (i == j)
+                    g = 1.0;
+                else if (i > j)
+                    g = (d * sg[tri_index(i, j)]) * dj;
+                else
+                    g = (dj * sg[tri_index(j, i)]) * d;
+            }
+        }
+        grow[j] = g;
+    }
+
+    // ---- forward Gauss-Seidel, residual form ---------------------------------
+    double rv = ct, a = 0.0;
+    for (int sweep = 0; sweep < nu; ++sweep) {
+#pragma unroll
+        for (int j = 0; j < s; ++j) {
+            const double delta = readlane(rv, j);
+            if (i == j)
+                a += delta;
+            rv -= grow[j] * delta;
+        }
+    }
+
+    // ---- outputs --------------------------------------------------------------
+    double res = ct;
+#pragma unroll
+    for (int j = 0; j < s; ++j)
+        res -= grow[j] * readlane(a, j);
+    const double num = wave_sum(res * res);
+    const double den = wave_sum(ct * ct);
+    const double delta = den > 0.0 ? sqrt(num / den) : 0.0;
+    if (own) {
+        st->alpha[i] = d * a;
+        dbg[dbg_ctil(s) + i] = ct;
+        dbg[dbg_atil(s) + i] = a;
+        dbg[dbg_d(s) + i] = d;
+#pragma unroll
+        for (int j = 0; j < s; ++j)
+            dbg[i * s + j] = grow[j];
+    }
+    if (lane == 0) {
+        st->delta = delta;
+        if (k < hist_cap)
+            hist[hist_cap + k] = delta;
+        st->iter = k + 1;
+        if (fp32) {
+            const double rms = rho * inv_sqrt_n;
+            st->p0scale = (rms > 0.0 && isfinite(rms)) ? ldexp(1.0, -ilogb(rms)) : 1.0;
+        }
+    }
+    return 0;
+}
+
+constexpr int kFgsThreads = 1024;
+
+// One outer iteration's Gram solve for a single system: the 1024 threads sum
+// the per-block partials of ||r||^2 and of the E Gram entries in a fixed order
+// (each wave owns whole entries), then wave 0 runs fgs_wave.
+template <int s>
+__global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, const double *__restrict__ rpart,
+                                                     int nbr, const double *__restrict__ gpart, int nbg, int nu,
+                                                     double cscale, int fp32, double inv_sqrt_n,
+                                                     double *__restrict__ dbg, double *__restrict__ hist,
+                                                     int hist_cap)
+{
+    if (st->done)
+        return;
+    __shared__ double sg[s * (s + 1) / 2 + s + 1];
+    constexpr int E = s * (s + 1) / 2 + s;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    constexpr int nw = kFgsThreads / kWave;
+    for (int t = wave; t <= E; t += nw) {
+        const double *src = t < E ? gpart + static_cast<int64_t>(t) * nbg : rpart;
+        const int cnt = t < E ? nbg : nbr;
+        // four independent loads per pass keep several memory requests in
+        // flight per lane; the summation order is fixed by cnt alone
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int q = lane;
+        for (; q + 3 * kWave < cnt; q += 4 * kWave) {
+            a0 += src[q];
+            a1 += src[q + kWave];
+            a2 += src[q + 2 * kWave];
+            a3 += src[q + 3 * kWave];
+        }
+        for (; q < cnt; q += kWave)
+            a0 += src[q];
+        const double acc = wave_sum((a0 + a1) + (a2 + a3));
+        if (lane == 0)
+            sg[t] = acc;
+    }
+    __syncthreads();
+    if (wave != 0)
+        return;
+    fgs_wave<s>(st, sg, nu, cscale, fp32, inv_sqrt_n, dbg, hist, hist_cap);
+}
+
+template <int s>
+hipError_t fgs_launch_s(const IterArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fgs<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.rpart, a.nbr, a.gpart, a.nbg, a.nu,
+                       a.cscale, a.fp32, a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap);
+    return hipGetLastError();
+}
+
+}  // namespace sstep

@@ -1,5 +1,5 @@
-// Gram kernels for basis widths s = 17..24 (see gram_impl.h).
-#include "gram_impl.h"
+// Gram and FGS kernels for basis widths s = 17..24 (see gram_impl.h, fgs_core.h).
+#include "fgs_core.h"
 
 namespace sstep {
 
@@ -22,6 +22,30 @@ hipError_t gram_launch_17_24(const IterArgs &a, hipStream_t st)
         return a.fp32 ? gram_launch_s<float, 23>(a, st) : gram_launch_s<double, 23>(a, st);
     case 24:
         return a.fp32 ? gram_launch_s<float, 24>(a, st) : gram_launch_s<double, 24>(a, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t fgs_launch_17_24(const IterArgs &a, hipStream_t st)
+{
+    switch (a.s) {
+    case 17:
+        return fgs_launch_s<17>(a, st);
+    case 18:
+        return fgs_launch_s<18>(a, st);
+    case 19:
+        return fgs_launch_s<19>(a, st);
+    case 20:
+        return fgs_launch_s<20>(a, st);
+    case 21:
+        return fgs_launch_s<21>(a, st);
+    case 22:
+        return fgs_launch_s<22>(a, st);
+    case 23:
+        return fgs_launch_s<23>(a, st);
+    case 24:
+        return fgs_launch_s<24>(a, st);
     default:
         return hipErrorInvalidValue;
     }

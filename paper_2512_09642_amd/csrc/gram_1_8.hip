@@ -1,5 +1,5 @@
-// Gram kernels for basis widths s = 1..8 (see gram_impl.h).
-#include "gram_impl.h"
+// Gram and FGS kernels for basis widths s = 1..8 (see gram_impl.h, fgs_core.h).
+#include "fgs_core.h"
 
 namespace sstep {
 
@@ -22,6 +22,30 @@ hipError_t gram_launch_1_8(const IterArgs &a, hipStream_t st)
         return a.fp32 ? gram_launch_s<float, 7>(a, st) : gram_launch_s<double, 7>(a, st);
     case 8:
         return a.fp32 ? gram_launch_s<float, 8>(a, st) : gram_launch_s<double, 8>(a, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t fgs_launch_1_8(const IterArgs &a, hipStream_t st)
+{
+    switch (a.s) {
+    case 1:
+        return fgs_launch_s<1>(a, st);
+    case 2:
+        return fgs_launch_s<2>(a, st);
+    case 3:
+        return fgs_launch_s<3>(a, st);
+    case 4:
+        return fgs_launch_s<4>(a, st);
+    case 5:
+        return fgs_launch_s<5>(a, st);
+    case 6:
+        return fgs_launch_s<6>(a, st);
+    case 7:
+        return fgs_launch_s<7>(a, st);
+    case 8:
+        return fgs_launch_s<8>(a, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -1,5 +1,5 @@
-// Gram kernels for basis widths s = 25..32 (see gram_impl.h).
-#include "gram_impl.h"
+// Gram and FGS kernels for basis widths s = 25..32 (see gram_impl.h, fgs_core.h).
+#include "fgs_core.h"
 
 namespace sstep {
 
@@ -22,6 +22,30 @@ hipError_t gram_launch_25_32(const IterArgs &a, hipStream_t st)
         return a.fp32 ? gram_launch_s<float, 31>(a, st) : gram_launch_s<double, 31>(a, st);
     case 32:
         return a.fp32 ? gram_launch_s<float, 32>(a, st) : gram_launch_s<double, 32>(a, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t fgs_launch_25_32(const IterArgs &a, hipStream_t st)
+{
+    switch (a.s) {
+    case 25:
+        return fgs_launch_s<25>(a, st);
+    case 26:
+        return fgs_launch_s<26>(a, st);
+    case 27:
+        return fgs_launch_s<27>(a, st);
+    case 28:
+        return fgs_launch_s<28>(a, st);
+    case 29:
+        return fgs_launch_s<29>(a, st);
+    case 30:
+        return fgs_launch_s<30>(a, st);
+    case 31:
+        return fgs_launch_s<31>(a, st);
+    case 32:
+        return fgs_launch_s<32>(a, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -1,5 +1,5 @@
-// Gram kernels for basis widths s = 9..16 (see gram_impl.h).
-#include "gram_impl.h"
+// Gram and FGS kernels for basis widths s = 9..16 (see gram_impl.h, fgs_core.h).
+#include "fgs_core.h"
 
 namespace sstep {
 
@@ -22,6 +22,30 @@ hipError_t gram_launch_9_16(const IterArgs &a, hipStream_t st)
         return a.fp32 ? gram_launch_s<float, 15>(a, st) : gram_launch_s<double, 15>(a, st);
     case 16:
         return a.fp32 ? gram_launch_s<float, 16>(a, st) : gram_launch_s<double, 16>(a, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t fgs_launch_9_16(const IterArgs &a, hipStream_t st)
+{
+    switch (a.s) {
+    case 9:
+        return fgs_launch_s<9>(a, st);
+    case 10:
+        return fgs_launch_s<10>(a, st);
+    case 11:
+        return fgs_launch_s<11>(a, st);
+    case 12:
+        return fgs_launch_s<12>(a, st);
+    case 13:
+        return fgs_launch_s<13>(a, st);
+    case 14:
+        return fgs_launch_s<14>(a, st);
+    case 15:
+        return fgs_launch_s<15>(a, st);
+    case 16:
+        return fgs_launch_s<16>(a, st);
     default:
         return hipErrorInvalidValue;
     }

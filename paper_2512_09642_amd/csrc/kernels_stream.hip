@@ -12,6 +12,8 @@ struct Launch1D {
     uint32_t grid;  // hardware blocks (multiple of 8)
 };
 
+inline uint32_t blocks_for(int64_t n) { return static_cast<uint32_t>((n + kBlock - 1) / kBlock); }
+
 Launch1D plan_points(int64_t n)
 {
     Launch1D l;
@@ -96,6 +98,114 @@ __global__ __launch_bounds__(kBlock) void k_basis(const DevState *__restrict__ s
     } else if constexpr (STEP == 1) {
         const T two_theta = T(2) * theta;
         pnext[c] = two_theta * (dinv * y - sigma * pc) - pprev[c];
+    }
+}
+
+// The same step for the constant Poisson operator in FP64 (nx even): a thread
+// owns two consecutive x-points and KZ = 2 consecutive z-planes, so the +-z
+// neighbours of the two planes come from registers (three 16-byte loads for
+// four z-values instead of six); south/north/centre/previous column are read
+// as 16-byte pairs, west/east of the pair as single values, AP and p_{j+1}
+// written as pairs.  Blocks run in-plane fastest (blockIdx.x over x-y pairs,
+// blockIdx.y over plane pairs): measured faster than an XCD-contiguous block
+// order for this access pattern.
+template <int STEP>
+__global__ __launch_bounds__(kBlock) void k_basis_p2(const DevState *__restrict__ st, Grid3 g, double minv,
+                                                     const double *__restrict__ pj, const double *__restrict__ pprev,
+                                                     double *__restrict__ apj, double *__restrict__ pnext,
+                                                     double theta, double sigma)
+{
+    constexpr int KZ = 2;
+    if (st->done)
+        return;
+    const uint32_t pl = (blockIdx.x * kBlock + threadIdx.x) * 2;  // in-plane index of the pair
+    if (pl >= static_cast<uint32_t>(g.nxy))
+        return;
+    const uint32_t j = fdiv(pl, g.dx);
+    const uint32_t i = pl - j * g.nx;
+    const int k0 = blockIdx.y * KZ;
+    const double2 z = {0.0, 0.0};
+    int64_t c = pl + static_cast<int64_t>(k0) * g.nxy;
+    double2 below = k0 > 0 ? *reinterpret_cast<const double2 *>(pj + c - g.nxy) : z;
+    double2 ctr = *reinterpret_cast<const double2 *>(pj + c);
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        const int k = k0 + kk;
+        if (k >= g.nz)
+            break;
+        const double2 above = k + 1 < g.nz ? *reinterpret_cast<const double2 *>(pj + c + g.nxy) : z;
+        const double w = i > 0 ? pj[c - 1] : 0.0;
+        const double e = i + 2 < static_cast<uint32_t>(g.nx) ? pj[c + 2] : 0.0;
+        const double2 s = j > 0 ? *reinterpret_cast<const double2 *>(pj + c - g.nx) : z;
+        const double2 nn = j + 1 < static_cast<uint32_t>(g.ny) ? *reinterpret_cast<const double2 *>(pj + c + g.nx) : z;
+        double2 y;
+        y.x = 6.0 * ctr.x - (((((w + ctr.y) + s.x) + nn.x) + below.x) + above.x);
+        y.y = 6.0 * ctr.y - (((((ctr.x + e) + s.y) + nn.y) + below.y) + above.y);
+        __builtin_nontemporal_store(y.x, apj + c);
+        __builtin_nontemporal_store(y.y, apj + c + 1);
+        if constexpr (STEP == 0) {
+            double2 pn;
+            pn.x = theta * (minv * y.x - sigma * ctr.x);
+            pn.y = theta * (minv * y.y - sigma * ctr.y);
+            *reinterpret_cast<double2 *>(pnext + c) = pn;
+        } else if constexpr (STEP == 1) {
+            const double2 pp = *reinterpret_cast<const double2 *>(pprev + c);
+            const double two_theta = 2.0 * theta;
+            double2 pn;
+            pn.x = two_theta * (minv * y.x - sigma * ctr.x) - pp.x;
+            pn.y = two_theta * (minv * y.y - sigma * ctr.y) - pp.y;
+            *reinterpret_cast<double2 *>(pnext + c) = pn;
+        }
+        below = ctr;
+        ctr = above;
+        c += g.nxy;
+    }
+}
+
+// CSR step with the block's rows staged: a block owns kBlock consecutive rows;
+// their column indices and values (when they fit in LDS) are first copied into
+// LDS with coalesced loads, then each thread forms its row's product from LDS.
+template <typename T, int STEP>
+__global__ __launch_bounds__(kBlock) void k_basis_csr(const DevState *__restrict__ st, OpCsr<T> op,
+                                                      const T *__restrict__ pj, const T *__restrict__ pprev,
+                                                      T *__restrict__ apj, T *__restrict__ pnext, T theta, T sigma,
+                                                      int64_t n)
+{
+    constexpr int kCap = kBlock * 8;  // staged entries (up to 8 per row on average)
+    __shared__ T sv[kCap];
+    __shared__ int32_t sc[kCap];
+    if (st->done)
+        return;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kBlock;
+    const int64_t r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    const int32_t kb = op.rp[r0], ke = op.rp[r1];
+    const bool staged = ke - kb <= kCap;
+    if (staged)
+        for (int32_t t = threadIdx.x; t < ke - kb; t += kBlock) {
+            sv[t] = op.val[kb + t];
+            sc[t] = op.ci[kb + t];
+        }
+    __syncthreads();
+    const int64_t c = r0 + threadIdx.x;
+    if (c >= n)
+        return;
+    T acc = T(0);
+    const int32_t a = op.rp[c], b = op.rp[c + 1];
+    if (staged) {
+        for (int32_t k = a; k < b; ++k)
+            acc += sv[k - kb] * pj[sc[k - kb]];
+    } else {
+        for (int32_t k = a; k < b; ++k)
+            acc += op.val[k] * pj[op.ci[k]];
+    }
+    const T pc = pj[c];
+    const T dinv = op.invd[c];
+    __builtin_nontemporal_store(acc, apj + c);
+    if constexpr (STEP == 0) {
+        pnext[c] = theta * (dinv * acc - sigma * pc);
+    } else if constexpr (STEP == 1) {
+        const T two_theta = T(2) * theta;
+        pnext[c] = two_theta * (dinv * acc - sigma * pc) - pprev[c];
     }
 }
 
@@ -295,7 +405,6 @@ __global__ __launch_bounds__(kBlock) void k_invert(const double *__restrict__ sr
         dst[c] = precond ? 1.0 / src[c] : 1.0;
 }
 
-inline uint32_t blocks_for(int64_t n) { return static_cast<uint32_t>((n + kBlock - 1) / kBlock); }
 
 template <typename T>
 OpPoisson7<T> make_poisson(const OpDev &op)
@@ -362,16 +471,67 @@ hipError_t basis_for(const IterArgs &a, const Op &op, int j, hipStream_t st)
     return hipGetLastError();
 }
 
+// FP64 constant Poisson with an even x-extent: pairs of points, two planes.
+hipError_t basis_poisson_pairs(const IterArgs &a, int j, hipStream_t st)
+{
+    const dim3 grid(static_cast<uint32_t>((a.op.g.nxy / 2 + kBlock - 1) / kBlock),
+                    static_cast<uint32_t>((a.op.g.nz + 1) / 2));
+    double *P = static_cast<double *>(a.P);
+    double *AP = static_cast<double *>(a.AP);
+    const double *pj = P + j * a.ld;
+    const double *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
+    double *apj = AP + j * a.ld;
+    double *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
+    const double minv = a.op.precond ? 1.0 / 6.0 : 1.0;
+    if (j + 1 >= a.s)
+        hipLaunchKernelGGL(k_basis_p2<2>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
+                           a.theta, a.sigma);
+    else if (j == 0)
+        hipLaunchKernelGGL(k_basis_p2<0>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
+                           a.theta, a.sigma);
+    else
+        hipLaunchKernelGGL(k_basis_p2<1>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
+                           a.theta, a.sigma);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t basis_csr(const IterArgs &a, int j, hipStream_t st)
+{
+    const uint32_t nb = blocks_for(a.op.n);
+    T *P = static_cast<T *>(a.P);
+    T *AP = static_cast<T *>(a.AP);
+    const T *pj = P + j * a.ld;
+    const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
+    T *apj = AP + j * a.ld;
+    T *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
+    const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
+    const OpCsr<T> op = Ops<T>::csr(a.op);
+    if (j + 1 >= a.s)
+        hipLaunchKernelGGL((k_basis_csr<T, 2>), dim3(nb), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext, theta,
+                           sigma, a.op.n);
+    else if (j == 0)
+        hipLaunchKernelGGL((k_basis_csr<T, 0>), dim3(nb), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext, theta,
+                           sigma, a.op.n);
+    else
+        hipLaunchKernelGGL((k_basis_csr<T, 1>), dim3(nb), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext, theta,
+                           sigma, a.op.n);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t basis_t(const IterArgs &a, int j, hipStream_t st)
 {
     switch (a.op.kind) {
     case kOpPoisson:
+        if constexpr (sizeof(T) == 8)
+            if (a.op.g.nx % 2 == 0)
+                return basis_poisson_pairs(a, j, st);
         return basis_for<OpPoisson7<T>, T>(a, make_poisson<T>(a.op), j, st);
     case kOpFaces:
         return basis_for<OpFaces7<T>, T>(a, Ops<T>::faces(a.op), j, st);
     default:
-        return basis_for<OpCsr<T>, T>(a, Ops<T>::csr(a.op), j, st);
+        return basis_csr<T>(a, j, st);
     }
 }
 

@@ -11,6 +11,11 @@ namespace sstep {
 
 enum OpKind { kOpCsr = 0, kOpPoisson = 1, kOpFaces = 2 };
 
+// Column padding of the basis buffers and of the M-diagonal arrays (rows).
+constexpr int64_t kPad = 256;
+// Largest Gram partial-block count a schedule may use.
+constexpr int kMaxGramBlocks = 2048;
+
 // Device copy of the operator in both precisions (the FP32 arrays exist only
 // in FP32+IR mode).
 struct OpDev {
@@ -41,13 +46,14 @@ struct IterArgs {
     double theta = 0, sigma = 0;
     void *P = nullptr;   // n x s, column-major, leading dimension ld
     void *AP = nullptr;  // n x s
-    int64_t ld = 0;
+    int64_t ld = 0;      // multiple of kPad; rows n..ld-1 of every column stay zero
     double *rpart = nullptr;  // residual-norm partial sums [nbr]
     int nbr = 0;
     int64_t rchunk = 0;
     double *gpart = nullptr;  // Gram partial sums [E][nbg]
     int nbg = 0;
-    int64_t gchunk = 0;
+    int64_t gchunk = 0;  // contiguous schedule: rows per block
+    int64_t gslab = 0;   // strided schedule: rows per slab (0 = contiguous schedule)
     int wdvec = 0;        // Gram right-hand side uses M-diagonal * p_0 (else p_0)
     double cscale = 1.0;  // constant factor applied to c = P^T (W) in the FGS kernel
     double *dbg = nullptr;   // G (s*s), ctil (s), atil (s), d (s), rho: written by the FGS kernel

@@ -124,7 +124,7 @@ class Solver:
 
     def __init__(self, op: Operator, s: int, nu: int, lmin: float, lmax: float, *, precision: str = "fp64",
                  precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
-                 record_history: bool = False, stream=None):
+                 record_history: bool = False, autotune: bool = True, stream=None):
         self._lib = N.load()
         self.op = op
         self.s, self.nu, self.lmin, self.lmax = s, nu, lmin, lmax
@@ -137,6 +137,7 @@ class Solver:
         opt.max_outer = max_outer
         opt.graph_chunk = graph_chunk
         opt.record_history = 1 if record_history else 0
+        opt.autotune = 1 if autotune else 0
         self._stream = stream
         opt.stream = self._stream_ptr()
         self.max_outer = max_outer

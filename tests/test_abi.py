@@ -36,7 +36,8 @@ def test_default_options_and_status_strings(native):
     lib = native.load()
     opt = native.Options()
     lib.sstep_default_options(C.byref(opt))
-    assert (opt.precision, opt.precond, opt.p0_mode, opt.max_outer, opt.graph_chunk) == (0, 1, 0, 10000, 4)
+    assert (opt.precision, opt.precond, opt.p0_mode, opt.max_outer, opt.graph_chunk, opt.record_history,
+            opt.autotune) == (0, 1, 0, 10000, 4, 0, 1)
     for code, name in native.STATUS_NAMES.items():
         assert lib.sstep_status_string(code).decode() == name
 
