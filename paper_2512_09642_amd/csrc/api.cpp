@@ -45,7 +45,25 @@ struct sstep_ctx {
     int chunk = 4;
     int64_t grad_size = 0;
     int *bad_flag = nullptr;       // device flag of the diagonal check
+    struct Batched *batch = nullptr;  // set for contexts made by sstep_setup_batched
     std::string err;
+};
+
+// State of a batched context (see sstep_setup_batched).
+struct Batched {
+    BatchArgs ba;
+    std::vector<BSys> sys;
+    std::vector<int64_t> n;
+    BSys *dsys = nullptr;
+    BTile *dbt = nullptr;
+    PTile *dpt = nullptr;
+    GTile *dgt = nullptr;
+    int64_t gchunk = 8192;
+    int grid_factor = 4;
+    int cus = 256;
+    DevState *pairs_host = nullptr;  // pinned
+    BGlob *gl_host = nullptr;        // pinned
+    int64_t total_n = 0;
 };
 
 namespace {
@@ -464,6 +482,8 @@ sstep_status run_solve(sstep_ctx *ctx, const double *b, double *x, double tol, s
 {
     if (!ctx)
         return SSTEP_E_ARG;
+    if (ctx->batch)
+        return fail(ctx, SSTEP_E_ARG, "this context was made by sstep_setup_batched: use sstep_solve_batched");
     if (!b || !x)
         return fail(ctx, SSTEP_E_ARG, "b and x must not be NULL");
     if (!(tol > 0.0) || !(tol < 1.0))
@@ -585,6 +605,13 @@ void sstep_destroy(sstep_ctx *ctx)
             (void)hipEventDestroy(e);
     if (ctx->stream)
         (void)hipStreamDestroy(ctx->stream);
+    if (ctx->batch) {
+        if (ctx->batch->pairs_host)
+            (void)hipHostFree(ctx->batch->pairs_host);
+        if (ctx->batch->gl_host)
+            (void)hipHostFree(ctx->batch->gl_host);
+        delete ctx->batch;
+    }
     delete ctx;
 }
 
@@ -742,7 +769,7 @@ sstep_status sstep_update_coefficients(sstep_ctx *ctx, const sstep_operator *A)
     return load_coefficients(ctx, A, false);
 }
 
-int64_t sstep_n(const sstep_ctx *ctx) { return ctx ? ctx->it.op.n : 0; }
+int64_t sstep_n(const sstep_ctx *ctx) { return ctx ? (ctx->batch ? ctx->batch->total_n : ctx->it.op.n) : 0; }
 
 int64_t sstep_grad_size(const sstep_ctx *ctx) { return ctx ? ctx->grad_size : 0; }
 
@@ -858,17 +885,398 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
     return SSTEP_OK;
 }
 
-sstep_status sstep_setup_batched(sstep_ctx **out, int32_t, const sstep_operator *, int32_t, int32_t, int32_t,
-                                 const double *, const double *, const sstep_options *)
+static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bool upload)
 {
-    if (out)
-        *out = nullptr;
-    return fail(nullptr, SSTEP_E_UNSUPPORTED, "batched solves are not available");
+    Batched &B = *ctx->batch;
+    BatchArgs &a = B.ba;
+    const int E = gram_entries(a.s);
+    std::vector<BTile> bt;
+    std::vector<PTile> pt;
+    std::vector<GTile> gt;
+    int64_t rofs = 0, gofs = 0;
+    for (int q = 0; q < a.nsys; ++q) {
+        BSys &S = B.sys[size_t(q)];
+        S.gchunk = gchunk;
+        S.nch = int32_t((S.ld + gchunk - 1) / gchunk);
+        S.rofs = rofs;
+        S.gofs = gofs;
+        rofs += int64_t(a.nrhs) * S.nch;
+        gofs += int64_t(a.nrhs) * E * S.nch;
+        for (int c = 0; c < S.nch; ++c) {
+            bt.push_back({q, c});
+            for (int r = 0; r < a.nrhs; ++r)
+                gt.push_back({q, c, r, 0});
+        }
+        for (int64_t b = 0; b < (S.n + kBlock - 1) / kBlock; ++b)
+            pt.push_back({q, int32_t(b)});
+    }
+    a.nbt = int(bt.size());
+    a.npt = int(pt.size());
+    a.ngt = int(gt.size());
+    a.grid_bt = std::max(1, std::min(a.nbt, B.cus * factor));
+    a.grid_pt = std::max(1, std::min(a.npt, B.cus * factor));
+    a.grid_gt = std::max(1, std::min(a.ngt, B.cus * 2));
+    if (upload) {
+        HIPCHK(ctx, hipMemcpy(B.dsys, B.sys.data(), B.sys.size() * sizeof(BSys), hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(B.dbt, bt.data(), bt.size() * sizeof(BTile), hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(B.dpt, pt.data(), pt.size() * sizeof(PTile), hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(B.dgt, gt.data(), gt.size() * sizeof(GTile), hipMemcpyHostToDevice));
+    }
+    B.gchunk = gchunk;
+    B.grid_factor = factor;
+    return SSTEP_OK;
 }
 
-sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *, double *const *, double, sstep_stats *)
+static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
 {
-    return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves are not available");
+    hipError_t e;
+    if ((e = launch_bresidual(a, s, true)) != hipSuccess)
+        return e;
+    for (int j = 0; j < a.s; ++j)
+        if ((e = launch_bbasis(a, j, s)) != hipSuccess)
+            return e;
+    if ((e = launch_bgram(a, s)) != hipSuccess)
+        return e;
+    if ((e = launch_bfgs(a, s)) != hipSuccess)
+        return e;
+    return launch_bupdate(a, s);
+}
+
+// Times the basis step and the Gram reduction (they touch only library
+// buffers) for each tile size and persistent-grid factor; keeps the fastest
+// pair, cached like the single-system Gram schedule.
+static sstep_status tune_batched(sstep_ctx *ctx)
+{
+    Batched &B = *ctx->batch;
+    BatchArgs &a = B.ba;
+    std::ostringstream key;
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t v : B.n)
+        h = (h ^ uint64_t(v)) * 1099511628211ull;
+    key << "gfx950 batched s=" << a.s << " prec=" << (a.fp32 ? "fp32" : "fp64") << " nrhs=" << a.nrhs
+        << " nsys=" << a.nsys << " faces=" << a.faces << " sizes=" << std::hex << h;
+    const std::string path = tune_cache_path();
+    std::map<std::string, GramSchedule> cache;
+    if (!path.empty()) {
+        cache = read_tune_cache(path);
+        auto f = cache.find(key.str());
+        if (f != cache.end() && f->second.nbg > 0)
+            return batched_tiles(ctx, f->second.slab, f->second.nbg, true);
+    }
+    int64_t best_chunk = B.gchunk;
+    int best_factor = B.grid_factor;
+    double best = 1e30;
+    for (int64_t gchunk : {int64_t(2048), int64_t(8192), int64_t(32768)}) {
+        for (int factor : {2, 4, 8}) {
+            OKCHK(batched_tiles(ctx, gchunk, factor, true));
+            HIPCHK(ctx, launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream));
+            HIPCHK(ctx, launch_bgram(a, ctx->stream));
+            HIPCHK(ctx, hipEventRecord(ctx->ev_t0, ctx->stream));
+            for (int r = 0; r < 2; ++r) {
+                HIPCHK(ctx, launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream));
+                HIPCHK(ctx, launch_bgram(a, ctx->stream));
+            }
+            HIPCHK(ctx, hipEventRecord(ctx->ev_t1, ctx->stream));
+            HIPCHK(ctx, hipEventSynchronize(ctx->ev_t1));
+            float ms = 0.f;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+            if (ms < best) {
+                best = ms;
+                best_chunk = gchunk;
+                best_factor = factor;
+            }
+        }
+    }
+    OKCHK(batched_tiles(ctx, best_chunk, best_factor, true));
+    if (!path.empty()) {
+        cache[key.str()] = GramSchedule{best_factor, best_chunk, 1e3 * best / 2};
+        write_tune_cache(path, cache);
+    }
+    return SSTEP_OK;
+}
+
+static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep_operator *A, int32_t nrhs,
+                                       int32_t s, int32_t nu, const double *lmin, const double *lmax,
+                                       const sstep_options *opt)
+{
+    if (opt)
+        ctx->opt = *opt;
+    else
+        sstep_default_options(&ctx->opt);
+    sstep_options &o = ctx->opt;
+    if (nsys < 1 || !A || !lmin || !lmax)
+        return fail(ctx, SSTEP_E_ARG, "nsys >= 1 operators and bounds are required");
+    if (nrhs < 1 || nrhs > 64)
+        return fail(ctx, SSTEP_E_ARG, "nrhs must be in [1, 64]");
+    if (s < 1 || s > kMaxS)
+        return fail(ctx, SSTEP_E_ARG, "s must be in [1, 32]");
+    if (nu < 1)
+        return fail(ctx, SSTEP_E_ARG, "nu must be >= 1");
+    if (o.precision != SSTEP_FP64 && o.precision != SSTEP_FP32_IR)
+        return fail(ctx, SSTEP_E_ARG, "unknown precision");
+    if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0)
+        return fail(ctx, SSTEP_E_ARG, "invalid options");
+    if (o.graph_chunk <= 0)
+        o.graph_chunk = 4;
+    for (int q = 0; q < nsys; ++q) {
+        OKCHK(check_operator(ctx, &A[q]));
+        if (A[q].kind != SSTEP_OP_STENCIL7)
+            return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves take 7-point stencil operators");
+        if ((A[q].kx != nullptr) != (A[0].kx != nullptr))
+            return fail(ctx, SSTEP_E_ARG, "all batched systems must have face coefficients, or none");
+        if (!std::isfinite(lmin[q]) || !std::isfinite(lmax[q]) || lmin[q] < 0.0 || !(lmax[q] > lmin[q]))
+            return fail(ctx, SSTEP_E_ARG, "bounds must be finite with 0 <= lambda_min < lambda_max");
+    }
+    HIPCHK(ctx, hipGetDevice(&ctx->device));
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    ctx->user = static_cast<hipStream_t>(o.stream);
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_poll[0], hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_poll[1], hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreate(&ctx->ev_t0));
+    HIPCHK(ctx, hipEventCreate(&ctx->ev_t1));
+    ctx->batch = new (std::nothrow) Batched();
+    if (!ctx->batch)
+        return fail(ctx, SSTEP_E_NOMEM, "out of host memory");
+    Batched &B = *ctx->batch;
+    BatchArgs &a = B.ba;
+    {
+        int cus = 0;
+        HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        B.cus = cus > 0 ? cus : 256;
+        void *p = nullptr;
+        HIPCHK(ctx, hipHostMalloc(&p, sizeof(DevState) * size_t(nsys) * nrhs, hipHostMallocDefault));
+        B.pairs_host = static_cast<DevState *>(p);
+        HIPCHK(ctx, hipHostMalloc(&p, sizeof(BGlob), hipHostMallocDefault));
+        B.gl_host = static_cast<BGlob *>(p);
+        HIPCHK(ctx, hipHostMalloc(&p, 8 * sizeof(int32_t), hipHostMallocDefault));
+        ctx->poll_host = static_cast<int32_t *>(p);
+    }
+    a.nsys = nsys;
+    a.nrhs = nrhs;
+    a.npairs = nsys * nrhs;
+    a.s = s;
+    a.nu = nu;
+    a.fp32 = o.precision == SSTEP_FP32_IR;
+    a.p0_mode = o.p0_mode;
+    a.precond = o.precond;
+    a.faces = A[0].kx != nullptr;
+    const bool jac_p0 = o.precond == 1 && o.p0_mode == 0;
+    a.wdvec = jac_p0 && a.faces;
+    a.cscale = (jac_p0 && !a.faces) ? 6.0 : 1.0;
+    OKCHK(dalloc(ctx, &ctx->bad_flag, 1));
+    HIPCHK(ctx, hipMemsetAsync(ctx->bad_flag, 0, sizeof(int), ctx->stream));
+    const size_t w = a.fp32 ? sizeof(float) : sizeof(double);
+    int64_t pofs = 0;
+    for (int q = 0; q < nsys; ++q) {
+        const sstep_operator &Aq = A[q];
+        BSys S{};
+        S.g.nx = Aq.nx;
+        S.g.ny = Aq.ny;
+        S.g.nz = Aq.nz;
+        S.g.nxy = int64_t(Aq.nx) * Aq.ny;
+        S.g.dx = make_fastdiv(uint32_t(Aq.nx));
+        S.g.dy = make_fastdiv(uint32_t(Aq.ny));
+        S.n = S.g.nxy * Aq.nz;
+        S.ld = round_up(S.n, kPad);
+        S.pofs = pofs;
+        pofs += int64_t(s) * nrhs * S.ld;
+        S.theta = 2.0 / (lmax[q] - lmin[q]);
+        S.sigma = (lmax[q] + lmin[q]) / 2.0;
+        S.inv_sqrt_n = 1.0 / std::sqrt(double(S.n));
+        S.pair0 = q * nrhs;
+        if (a.faces) {
+            const int64_t nfx = faces_x(&Aq), nfy = faces_y(&Aq), nfz = faces_z(&Aq);
+            double *k = nullptr, *dv = nullptr;
+            OKCHK(dalloc(ctx, &k, size_t(nfx + nfy + nfz)));
+            OKCHK(overwrite_device(ctx, k, Aq.kx, size_t(nfx), Aq.ptr_space));
+            OKCHK(overwrite_device(ctx, k + nfx, Aq.ky, size_t(nfy), Aq.ptr_space));
+            OKCHK(overwrite_device(ctx, k + nfx + nfy, Aq.kz, size_t(nfz), Aq.ptr_space));
+            OKCHK(dalloc(ctx, &dv, size_t(S.ld)));
+            HIPCHK(ctx, hipMemsetAsync(dv, 0, size_t(S.ld) * sizeof(double), ctx->stream));
+            S.kx = k, S.ky = k + nfx, S.kz = k + nfx + nfy, S.dvec = dv;
+            OpDev od;
+            od.kind = kOpFaces;
+            od.n = S.n;
+            od.g = S.g;
+            od.kx = S.kx, od.ky = S.ky, od.kz = S.kz;
+            HIPCHK(ctx, launch_diag_from_faces(od, dv, ctx->bad_flag, ctx->stream));
+            if (a.fp32) {
+                float *k32 = nullptr, *dv32 = nullptr;
+                OKCHK(dalloc(ctx, &k32, size_t(nfx + nfy + nfz)));
+                OKCHK(dalloc(ctx, &dv32, size_t(S.ld)));
+                HIPCHK(ctx, hipMemsetAsync(dv32, 0, size_t(S.ld) * sizeof(float), ctx->stream));
+                HIPCHK(ctx, launch_to_fp32(k, k32, nfx + nfy + nfz, ctx->stream));
+                HIPCHK(ctx, launch_to_fp32(dv, dv32, S.n, ctx->stream));
+                S.kx32 = k32, S.ky32 = k32 + nfx, S.kz32 = k32 + nfx + nfy, S.dvec32 = dv32;
+            }
+        }
+        B.sys.push_back(S);
+        B.n.push_back(S.n);
+        B.total_n += S.n;
+    }
+    {
+        int hbad = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&hbad, ctx->bad_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (hbad)
+            return fail(ctx, SSTEP_E_ARG, "a face operator has a non-positive or non-finite diagonal");
+    }
+    {
+        char *P = nullptr, *AP = nullptr;
+        OKCHK(dalloc(ctx, &P, size_t(pofs) * w));
+        OKCHK(dalloc(ctx, &AP, size_t(pofs) * w));
+        HIPCHK(ctx, hipMemsetAsync(P, 0, size_t(pofs) * w, ctx->stream));
+        HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(pofs) * w, ctx->stream));
+        a.P = P;
+        a.AP = AP;
+    }
+    // tables and partials sized for the smallest tile (2048 rows)
+    int64_t max_nch = 0, max_pt = 0;
+    for (const BSys &S : B.sys) {
+        max_nch += (S.ld + 2047) / 2048;
+        max_pt += (S.n + kBlock - 1) / kBlock;
+    }
+    OKCHK(dalloc(ctx, &B.dsys, size_t(nsys)));
+    OKCHK(dalloc(ctx, &B.dbt, size_t(max_nch)));
+    OKCHK(dalloc(ctx, &B.dpt, size_t(max_pt)));
+    OKCHK(dalloc(ctx, &B.dgt, size_t(max_nch) * nrhs));
+    OKCHK(dalloc(ctx, &a.rpart, size_t(max_nch) * nrhs));
+    OKCHK(dalloc(ctx, &a.gpart, size_t(max_nch) * nrhs * gram_entries(s)));
+    OKCHK(dalloc(ctx, &a.pairs, size_t(a.npairs)));
+    OKCHK(dalloc(ctx, &a.gl, 1));
+    OKCHK(dalloc(ctx, &a.dbg, size_t(a.npairs) * dbg_size(s)));
+    HIPCHK(ctx, hipMemsetAsync(a.pairs, 0, sizeof(DevState) * size_t(a.npairs), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(a.gl, 0, sizeof(BGlob), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    a.sys = B.dsys;
+    a.btiles = B.dbt;
+    a.ptiles = B.dpt;
+    a.gtiles = B.dgt;
+    // a non-zero npairs with ndone = 0 keeps the kernels active while tuning
+    BGlob g0{0, a.npairs};
+    HIPCHK(ctx, hipMemcpy(a.gl, &g0, sizeof(BGlob), hipMemcpyHostToDevice));
+    OKCHK(batched_tiles(ctx, 8192, 4, true));
+    if (o.autotune && B.total_n >= (int64_t(1) << 20))
+        OKCHK(tune_batched(ctx));
+    // graph of graph_chunk outer iterations over all pairs
+    ctx->chunk = o.graph_chunk;
+    HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < ctx->chunk && e == hipSuccess; ++c)
+        e = enqueue_batched_iteration(a, ctx->stream);
+    hipGraph_t gph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ctx->stream, &gph);
+    if (e != hipSuccess)
+        return hip_fail(ctx, "kernel launch during graph capture", e);
+    if (e2 != hipSuccess)
+        return hip_fail(ctx, "hipStreamEndCapture", e2);
+    ctx->graph = gph;
+    HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, gph, nullptr, nullptr, 0));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_operator *A, int32_t nrhs, int32_t s,
+                                 int32_t nu, const double *lmin, const double *lmax, const sstep_options *opt)
+{
+    if (!out)
+        return fail(nullptr, SSTEP_E_ARG, "out is NULL");
+    *out = nullptr;
+    sstep_ctx *ctx = new (std::nothrow) sstep_ctx();
+    if (!ctx)
+        return fail(nullptr, SSTEP_E_NOMEM, "out of host memory");
+    const sstep_status st = setup_batched_impl(ctx, nsys, A, nrhs, s, nu, lmin, lmax, opt);
+    if (st != SSTEP_OK) {
+        g_setup_error = ctx->err;
+        sstep_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return SSTEP_OK;
+}
+
+sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double *const *x, double tol,
+                                 sstep_stats *st)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!ctx->batch)
+        return fail(ctx, SSTEP_E_ARG, "this context was made by sstep_setup: use sstep_solve");
+    Batched &B = *ctx->batch;
+    BatchArgs &a = B.ba;
+    if (!b || !x)
+        return fail(ctx, SSTEP_E_ARG, "b and x must not be NULL");
+    if (!(tol > 0.0) || !(tol < 1.0))
+        return fail(ctx, SSTEP_E_ARG, "tol must be in (0, 1)");
+    for (int q = 0; q < a.nsys; ++q)
+        if (!b[q] || !x[q])
+            return fail(ctx, SSTEP_E_ARG, "b[q] and x[q] must not be NULL");
+    for (int q = 0; q < a.nsys; ++q)
+        for (int r = 0; r < a.nrhs; ++r) {
+            DevState &h = B.pairs_host[q * a.nrhs + r];
+            std::memset(&h, 0, sizeof(DevState));
+            h.b = b[q] + int64_t(r) * B.n[size_t(q)];
+            h.x = x[q] + int64_t(r) * B.n[size_t(q)];
+            h.tol = tol;
+            h.p0scale = 1.0;
+            h.first = 1;
+            h.max_outer = ctx->opt.max_outer;
+        }
+    *B.gl_host = BGlob{0, a.npairs};
+    HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    HIPCHK(ctx, hipMemcpyAsync(a.pairs, B.pairs_host, sizeof(DevState) * size_t(a.npairs), hipMemcpyHostToDevice,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(a.gl, B.gl_host, sizeof(BGlob), hipMemcpyHostToDevice, ctx->stream));
+    if (a.fp32) {
+        HIPCHK(ctx, launch_bresidual(a, ctx->stream, false));
+        HIPCHK(ctx, launch_bp0scale(a, ctx->stream));
+    }
+    const int max_replays = (ctx->opt.max_outer + 1 + ctx->chunk - 1) / ctx->chunk + 1;
+    int launched = 0, checked = 0;
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = hipGraphLaunch(ctx->gexec, ctx->stream);
+        if (e != hipSuccess)
+            return e;
+        int32_t *slot = ctx->poll_host + 4 * (launched % 2);
+        e = hipMemcpyAsync(slot, a.gl, sizeof(BGlob), hipMemcpyDeviceToHost, ctx->stream);
+        if (e != hipSuccess)
+            return e;
+        e = hipEventRecord(ctx->ev_poll[launched % 2], ctx->stream);
+        ++launched;
+        return e;
+    };
+    HIPCHK(ctx, enqueue());
+    for (;;) {
+        if (launched < max_replays)
+            HIPCHK(ctx, enqueue());
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev_poll[checked % 2]));
+        const int32_t ndone = ctx->poll_host[4 * (checked % 2)];
+        ++checked;
+        if (ndone >= a.npairs)
+            break;
+        if (checked >= launched) {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            return fail(ctx, SSTEP_E_HIP, "batched solve did not stop within the replay bound");
+        }
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(B.pairs_host, a.pairs, sizeof(DevState) * size_t(a.npairs), hipMemcpyDeviceToHost));
+    sstep_status first_bad = SSTEP_OK;
+    for (int p = 0; p < a.npairs; ++p) {
+        const DevState &h = B.pairs_host[p];
+        if (st) {
+            st[p].outer_iters = h.iter;
+            st[p].status = h.status;
+            st[p].rel_res = h.relres;
+            st[p].res0 = h.rho0;
+        }
+        if (first_bad == SSTEP_OK && h.status != SSTEP_OK)
+            first_bad = static_cast<sstep_status>(h.status);
+    }
+    if (first_bad != SSTEP_OK)
+        return fail(ctx, first_bad, std::string("a batched pair stopped with ") + sstep_status_string(first_bad));
+    return SSTEP_OK;
 }
 
 }  // extern "C"

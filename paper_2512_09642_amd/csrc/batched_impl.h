@@ -1,0 +1,120 @@
+// Gram and FGS kernels of the batched outer iteration, instantiated per basis
+// width next to the single-system ones.
+#pragma once
+
+#include "fgs_core.h"
+
+namespace sstep {
+
+// Gram partials of every active pair: tile (q, chunk, r) reduces rows
+// [chunk*gchunk, (chunk+1)*gchunk) of pair (q, r)'s basis (column stride
+// nrhs*ld, zero padding past n) into gpart[gofs + r*E*nch + e*nch + chunk].
+template <typename T, int S, bool WD>
+__global__ __launch_bounds__(kWave * GramPlan<S>::NG) void k_bgram(const BGlob *__restrict__ gl,
+                                                                   const BSys *__restrict__ sys,
+                                                                   const GTile *__restrict__ tiles, int ntiles,
+                                                                   const DevState *__restrict__ pairs, int nrhs,
+                                                                   const T *__restrict__ P, const T *__restrict__ AP,
+                                                                   double *__restrict__ gpart)
+{
+    constexpr int E = S * (S + 1) / 2 + S;
+    if (gl->ndone == gl->npairs)
+        return;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const GTile tl = tiles[t];
+        const BSys &Q = sys[tl.q];
+        if (pairs[Q.pair0 + tl.r].done)
+            continue;
+        const int64_t off = Q.pofs + static_cast<int64_t>(tl.r) * Q.ld;
+        const int64_t cs = static_cast<int64_t>(nrhs) * Q.ld;
+        const int64_t beg = static_cast<int64_t>(tl.chunk) * Q.gchunk;
+        const int64_t end = beg + Q.gchunk < Q.ld ? beg + Q.gchunk : Q.ld;
+        const T *dv = nullptr;
+        if constexpr (WD)
+            dv = reinterpret_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(Q.dvec)
+                                                             : static_cast<const void *>(Q.dvec32));
+        gram_tile<T, S, gram_rpl<T, S>(), WD>(P + off, AP + off, dv, cs, beg, end, end - beg, end - beg + 1,
+                                               gpart + Q.gofs + static_cast<int64_t>(tl.r) * E * Q.nch, Q.nch,
+                                               tl.chunk);
+    }
+}
+
+template <typename T, int S>
+hipError_t bgram_launch_s(const BatchArgs &a, hipStream_t st)
+{
+    const dim3 block(kWave * GramPlan<S>::NG);
+    const T *P = static_cast<const T *>(a.P);
+    const T *AP = static_cast<const T *>(a.AP);
+    if (a.wdvec)
+        hipLaunchKernelGGL((k_bgram<T, S, true>), dim3(a.grid_gt), block, 0, st, a.gl, a.sys, a.gtiles, a.ngt,
+                           a.pairs, a.nrhs, P, AP, a.gpart);
+    else
+        hipLaunchKernelGGL((k_bgram<T, S, false>), dim3(a.grid_gt), block, 0, st, a.gl, a.sys, a.gtiles, a.ngt,
+                           a.pairs, a.nrhs, P, AP, a.gpart);
+    return hipGetLastError();
+}
+
+// One block (four waves) per pair: fixed-order sums of the pair's partials,
+// then wave 0 runs the stopping test, scaling and FGS; a pair that stops is
+// counted in the global done counter.
+constexpr int kBFgsThreads = 256;
+
+template <int S>
+__global__ __launch_bounds__(kBFgsThreads) void k_bfgs(BGlob *__restrict__ gl, const BSys *__restrict__ sys,
+                                                       DevState *__restrict__ pairs, int nrhs,
+                                                       const double *__restrict__ rpart,
+                                                       const double *__restrict__ gpart, int nu, double cscale,
+                                                       int fp32, double *__restrict__ dbg)
+{
+    constexpr int E = S * (S + 1) / 2 + S;
+    const int p = blockIdx.x;
+    DevState *ps = pairs + p;
+    if (ps->done)
+        return;
+    const BSys &Q = sys[p / nrhs];
+    const int r = p % nrhs;
+    __shared__ double sg[E + 1];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const double *gp = gpart + Q.gofs + static_cast<int64_t>(r) * E * Q.nch;
+    const double *rp = rpart + Q.rofs + static_cast<int64_t>(r) * Q.nch;
+    for (int t = wave; t <= E; t += kBFgsThreads / kWave) {
+        const double *src = t < E ? gp + static_cast<int64_t>(t) * Q.nch : rp;
+        double a0 = 0.0, a1 = 0.0;
+        int q = lane;
+        for (; q + kWave < Q.nch; q += 2 * kWave) {
+            a0 += src[q];
+            a1 += src[q + kWave];
+        }
+        for (; q < Q.nch; q += kWave)
+            a0 += src[q];
+        const double acc = wave_sum(a0 + a1);
+        if (lane == 0)
+            sg[t] = acc;
+    }
+    __syncthreads();
+    if (wave != 0)
+        return;
+    const int stopped = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, dbg + static_cast<int64_t>(p) * dbg_size(S),
+                                    nullptr, 0);
+    if (stopped && lane == 0)
+        atomicAdd(&gl->ndone, 1);
+}
+
+template <int S>
+hipError_t bfgs_launch_s(const BatchArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bfgs<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs, a.rpart,
+                       a.gpart, a.nu, a.cscale, a.fp32, a.dbg);
+    return hipGetLastError();
+}
+
+hipError_t bgram_launch_1_8(const BatchArgs &a, hipStream_t st);
+hipError_t bgram_launch_9_16(const BatchArgs &a, hipStream_t st);
+hipError_t bgram_launch_17_24(const BatchArgs &a, hipStream_t st);
+hipError_t bgram_launch_25_32(const BatchArgs &a, hipStream_t st);
+hipError_t bfgs_launch_1_8(const BatchArgs &a, hipStream_t st);
+hipError_t bfgs_launch_9_16(const BatchArgs &a, hipStream_t st);
+hipError_t bfgs_launch_17_24(const BatchArgs &a, hipStream_t st);
+hipError_t bfgs_launch_25_32(const BatchArgs &a, hipStream_t st);
+
+}  // namespace sstep

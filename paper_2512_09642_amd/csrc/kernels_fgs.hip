@@ -1,6 +1,6 @@
 // Dispatch of the Gram and FGS launches to the translation unit that holds
 // the instantiation for the basis width s.
-#include "gram_impl.h"
+#include "batched_impl.h"
 
 namespace sstep {
 
@@ -24,6 +24,28 @@ hipError_t launch_fgs(const IterArgs &a, hipStream_t st)
     if (a.s <= 24)
         return fgs_launch_17_24(a, st);
     return fgs_launch_25_32(a, st);
+}
+
+hipError_t launch_bgram(const BatchArgs &a, hipStream_t st)
+{
+    if (a.s <= 8)
+        return bgram_launch_1_8(a, st);
+    if (a.s <= 16)
+        return bgram_launch_9_16(a, st);
+    if (a.s <= 24)
+        return bgram_launch_17_24(a, st);
+    return bgram_launch_25_32(a, st);
+}
+
+hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st)
+{
+    if (a.s <= 8)
+        return bfgs_launch_1_8(a, st);
+    if (a.s <= 16)
+        return bfgs_launch_9_16(a, st);
+    if (a.s <= 24)
+        return bfgs_launch_17_24(a, st);
+    return bfgs_launch_25_32(a, st);
 }
 
 }  // namespace sstep

@@ -72,6 +72,61 @@ __host__ __device__ inline int64_t dbg_size(int s) { return int64_t(s) * s + 3 *
 
 __host__ __device__ inline int gram_entries(int s) { return s * (s + 1) / 2 + s; }
 
+// ---------------------------------------------------------------------------
+// Batched solves: nsys stencil systems x nrhs right-hand sides ("pairs").
+// System q's basis block is laid out [s][nrhs][ld_q] at element offset pofs:
+// column j of pair (q, r) starts at pofs + (j*nrhs + r)*ld_q.
+// ---------------------------------------------------------------------------
+struct BSys {
+    Grid3 g;
+    int64_t n, ld, pofs;
+    const double *kx, *ky, *kz;      // face coefficients (null: constant Poisson)
+    const float *kx32, *ky32, *kz32;
+    const double *dvec;              // M diagonal, zero-padded to ld
+    const float *dvec32;
+    double theta, sigma, inv_sqrt_n;
+    int64_t gchunk;                  // rows per chunk tile (multiple of kPad)
+    int64_t gofs;                    // Gram partials of pair (q, r): gofs + r*E*nch
+    int64_t rofs;                    // residual partials of pair (q, r): rofs + r*nch
+    int32_t pair0, nch;
+};
+struct BTile {  // chunk of one system, all right-hand sides
+    int32_t q, chunk;
+};
+struct PTile {  // kBlock points of one system (basis)
+    int32_t q, blk;
+};
+struct GTile {  // chunk of one pair (Gram)
+    int32_t q, chunk, r, pad;
+};
+struct BGlob {
+    int32_t ndone, npairs;
+};
+
+struct BatchArgs {
+    BGlob *gl = nullptr;
+    const BSys *sys = nullptr;
+    int nsys = 0, nrhs = 0, npairs = 0;
+    int s = 0, nu = 0, fp32 = 0, p0_mode = 0, precond = 1, faces = 0;
+    void *P = nullptr, *AP = nullptr;
+    const BTile *btiles = nullptr;
+    const PTile *ptiles = nullptr;
+    const GTile *gtiles = nullptr;
+    int nbt = 0, npt = 0, ngt = 0;
+    int grid_bt = 0, grid_pt = 0, grid_gt = 0;  // persistent grid sizes
+    DevState *pairs = nullptr;
+    double *rpart = nullptr, *gpart = nullptr, *dbg = nullptr;
+    double cscale = 1.0;
+    int wdvec = 0;
+};
+
+hipError_t launch_bresidual(const BatchArgs &a, hipStream_t st, bool write_p0);
+hipError_t launch_bp0scale(const BatchArgs &a, hipStream_t st);
+hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st);
+hipError_t launch_bgram(const BatchArgs &a, hipStream_t st);
+hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st);
+hipError_t launch_bupdate(const BatchArgs &a, hipStream_t st);
+
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);

@@ -252,3 +252,75 @@ class Solver:
         _check(self._lib.sstep_kernel_times(self._ctx, _dev_ptr(b, self.n, "b"), _dev_ptr(x_scratch, self.n, "x"),
                                             reps, ms.ctypes.data), self._ctx)
         return dict(zip(N.KT_NAMES, ms.tolist()))
+
+
+class BatchedSolver:
+    """Many stencil systems x ``nrhs`` right-hand sides, advanced together: one
+    launch per step of the outer iteration covers every (system, rhs) pair."""
+
+    def __init__(self, ops: list, nrhs: int, s: int, nu: int, lmin, lmax, *, precision: str = "fp64",
+                 precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
+                 autotune: bool = True, stream=None):
+        self._lib = N.load()
+        self.ops = list(ops)
+        self.nsys = len(self.ops)
+        self.nrhs = nrhs
+        self.s, self.nu = s, nu
+        opt = N.Options()
+        self._lib.sstep_default_options(C.byref(opt))
+        opt.precision = {"fp64": N.FP64, "fp32ir": N.FP32_IR}[precision]
+        opt.precond = 1 if precond else 0
+        opt.p0_mode = p0_mode
+        opt.max_outer = max_outer
+        opt.graph_chunk = graph_chunk
+        opt.autotune = 1 if autotune else 0
+        self._stream = stream
+        opt.stream = stream.cuda_stream if stream is not None else (
+            torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None)
+        carr = (N.Operator * self.nsys)(*[op.to_c() for op in self.ops])
+        lo = np.ascontiguousarray(lmin, dtype=np.float64)
+        hi = np.ascontiguousarray(lmax, dtype=np.float64)
+        if lo.size != self.nsys or hi.size != self.nsys:
+            raise ValueError("one (lmin, lmax) pair per system")
+        ctx = C.c_void_p()
+        st = self._lib.sstep_setup_batched(C.byref(ctx), self.nsys, carr, nrhs, s, nu, lo.ctypes.data,
+                                           hi.ctypes.data, C.byref(opt))
+        for op in self.ops:
+            op._keep = []
+        _check(st, None)
+        self._ctx = ctx
+        self.sizes = [op.n for op in self.ops]
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.sstep_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, b: list, x: list | None = None, tol: float = 1e-8, *, raise_on_error: bool = True):
+        """``b[q]``, ``x[q]``: float64 CUDA tensors of n_q * nrhs entries
+        (right-hand side r at offset r * n_q).  Returns (x, stats) with one
+        SolveStats per pair, pair (q, r) at q * nrhs + r."""
+        if len(b) != self.nsys:
+            raise ValueError("one right-hand-side block per system")
+        if x is None:
+            x = [torch.zeros_like(bq) for bq in b]
+        bp = (C.c_void_p * self.nsys)(*[_dev_ptr(bq, n * self.nrhs, "b") for bq, n in zip(b, self.sizes)])
+        xp = (C.c_void_p * self.nsys)(*[_dev_ptr(xq, n * self.nrhs, "x") for xq, n in zip(x, self.sizes)])
+        stats = (N.Stats * (self.nsys * self.nrhs))()
+        st = self._lib.sstep_solve_batched(self._ctx, bp, xp, tol, stats)
+        out = [SolveStats(v.outer_iters, v.status, v.rel_res, v.res0) for v in stats]
+        if raise_on_error:
+            _check(st, self._ctx)
+        return x, out
