@@ -21,6 +21,7 @@ JSON line on stdout (progress on stderr).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -67,6 +68,22 @@ def basis_bytes_per_launch(n: int, s: int, w: int) -> float:
     """Average algorithmic bytes of one basis launch: the s launches of an
     outer iteration move w(4s - 3) bytes per unknown in total."""
     return float(n) * w * (4 * s - 3) / s
+
+
+def measured_traffic(N: int, s: int, nu: int):
+    """HBM bytes per basis launch recorded from hardware counters for the
+    224^3, s = 16, nu = 25 FP64 workload, or None when the workload differs or
+    the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_poisson224_s16_fp64.json")
+    if (N, s, nu) != (224, 16, 25) or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in rec["source_files"]:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(f.read())
+    return rec["basis_avg_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
 def cpu_baseline(N: int, s: int, nu: int, gpu_iters: int, sample_outer: int) -> dict:
@@ -363,7 +380,8 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.N, args.s, args.nu),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": per_launch,
             "avg_launch_ms": kt["basis"],
         }
