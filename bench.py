@@ -42,9 +42,13 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stencil_bytes_per_outer(n: int, s: int, w: int) -> float:
-    """Bytes an outer iteration must move, constant-coefficient stencil:
-    residual 16 + w, basis w(4s - 3), Gram 2sw, update sw + 16."""
+def stencil_bytes_per_outer(n: int, s: int, w: int, fused: bool = False) -> float:
+    """Bytes an outer iteration must move, constant-coefficient stencil.
+    Stored AP: residual 16 + w, basis w(4s - 3), Gram 2sw, update sw + 16.
+    Gram forming A p_j itself (fused): the s - 1 basis launches move
+    w(3s - 4) (no AP), the Gram reads P only (sw)."""
+    if fused:
+        return float(n) * (32 + w * (1 + max(0, 3 * s - 4) + 2 * s))
     return float(n) * (32 + w * (7 * s - 2))
 
 
@@ -57,16 +61,20 @@ def csr_bytes_per_outer(n: int, nnz: int, s: int, w: int) -> float:
     return stencil_bytes_per_outer(n, s, w) + s * mat_w + mat_64 + float(n) * w
 
 
-def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1) -> float:
+def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, fused: bool = False) -> float:
     """Stencil figure per right-hand side plus the three face arrays read by the
-    FP64 residual and the s basis steps (shared by nrhs right-hand sides) and
-    the M-diagonal read by the Gram right-hand side."""
-    return nrhs * (stencil_bytes_per_outer(n, s, w) + float(n) * w) + float(n) * 3 * (8 + s * w)
+    FP64 residual and s more times (the s basis steps, or the s - 1 basis
+    steps and the Gram when it forms A p_j itself), shared by nrhs right-hand
+    sides, and the M-diagonal read by the Gram right-hand side."""
+    return nrhs * (stencil_bytes_per_outer(n, s, w, fused) + float(n) * w) + float(n) * 3 * (8 + s * w)
 
 
-def basis_bytes_per_launch(n: int, s: int, w: int) -> float:
+def basis_bytes_per_launch(n: int, s: int, w: int, fused: bool = False) -> float:
     """Average algorithmic bytes of one basis launch: the s launches of an
-    outer iteration move w(4s - 3) bytes per unknown in total."""
+    outer iteration move w(4s - 3) bytes per unknown in total; without AP
+    (fused Gram) the s - 1 launches move w(3s - 4)."""
+    if fused:
+        return float(n) * w * (3 * s - 4) / (s - 1)
     return float(n) * w * (4 * s - 3) / s
 
 
@@ -155,7 +163,8 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
                 return st.outer_iters
 
             leg.run = run
-            leg.bytes_per_outer = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4)
+            leg.bytes_per_outer = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4,
+                                                          leg.solver.gram_applies_operator)
             leg.n = pr.n
             out[name] = leg
         if "c2_csr_fp64" in legs:
@@ -218,7 +227,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
             return None
 
         leg.run = run
-        leg.bytes_per_outer = faces_bytes_per_outer(pr.n, pr.s, 8)
+        leg.bytes_per_outer = faces_bytes_per_outer(pr.n, pr.s, 8, fused=leg.solver.gram_applies_operator)
         leg.n = pr.n
         out["c5_adjoint"] = leg
 
@@ -371,11 +380,13 @@ def main():
         if "c2_fp32ir" in legs:
             results["c2_fp32ir"]["kernel_ms"] = legs["c2_fp32ir"].solver.kernel_times(
                 main_leg.b, torch.zeros_like(main_leg.b), reps=args.kernel_reps)
-        per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8)
+        fused = main_leg.solver.gram_applies_operator
+        per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8, fused)
         achieved = per_launch / (kt["basis"] * 1e-3) / 1e9
         out["roofline"] = {
             "bound": "hbm",
-            "kernel": "k_basis_p2 (7-point stencil + Jacobi + Chebyshev step, FP64), average of the s launches",
+            "kernel": "k_basis_p2 (7-point stencil + Jacobi + Chebyshev step, FP64), average of the "
+                      + ("s - 1 launches (AP not written)" if fused else "s launches"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

@@ -86,6 +86,14 @@ typedef struct {
     const double *kx, *ky, *kz;
 } sstep_operator;
 
+/* Gram formation.  STORED_AP: the basis steps write A p_j to an n x s array
+ * AP and the Gram kernel reads P and AP.  APPLY_OP (stencil operators,
+ * s <= 16): the Gram kernel forms A p_j from P itself, so AP is neither
+ * written nor allocated and the basis makes s - 1 launches per outer
+ * iteration; asking for it with a CSR operator or s > 16 gives
+ * SSTEP_E_UNSUPPORTED. */
+typedef enum { SSTEP_GRAM_AUTO = 0, SSTEP_GRAM_STORED_AP = 1, SSTEP_GRAM_APPLY_OP = 2 } sstep_gram_kind;
+
 typedef struct {
     int32_t precision;      /* sstep_precision, default SSTEP_FP64 */
     int32_t precond;        /* 1 = Jacobi M = diag(A) (default), 0 = none */
@@ -97,6 +105,9 @@ typedef struct {
                                slabs) on the context's buffers and keep the fastest, cached in
                                $SSTEP_TUNE_CACHE or ~/.cache/sstep/tune.json; systems under 2^20
                                unknowns use the defaults; 0 = defaults */
+    int32_t gram;           /* sstep_gram_kind: how G = P^T A P (Sec. 2) is formed.  SSTEP_GRAM_AUTO
+                               (default) = SSTEP_GRAM_APPLY_OP for FP64 stencil operators with
+                               s <= 16, SSTEP_GRAM_STORED_AP otherwise */
     void *stream;           /* hipStream_t the caller's data is ordered on (NULL = default) */
 } sstep_options;
 
@@ -116,7 +127,8 @@ void sstep_default_options(sstep_options *opt);
 /* Creates a context for operator A, basis width s in [1, 32], nu >= 1 FGS sweeps
  * (Sec. 2), and Chebyshev bounds 0 <= lambda_min < lambda_max enclosing the
  * spectrum of M^{-1} A (Sec. 2, Definition).  Copies A to the device,
- * allocates every workspace (basis P and products AP, n x s each, column-major,
+ * allocates every workspace (basis P and, unless the Gram kernel forms the
+ * products itself, AP: n x s each, column-major,
  * partial sums, device state) and captures the outer-iteration graph.
  * opt may be NULL (defaults).  Returns SSTEP_E_ARG for invalid sizes, bounds,
  * a malformed CSR pattern or, with Jacobi, a non-positive diagonal. */
@@ -160,8 +172,10 @@ int64_t sstep_n(const sstep_ctx *ctx);
  * Host outputs (each may be NULL): alpha_tilde[s] (scaled FGS solution),
  * G[s*s] (scaled Gram matrix, row-major), ctil[s] (scaled right-hand side),
  * rnorm[1] (||b - A x|| before the update).  Device outputs (may be NULL):
- * P_out, AP_out: n x s FP64 column-major (leading dimension n).  Used by the
- * lockstep parity tests. */
+ * P_out, AP_out: n x s FP64 column-major (leading dimension n).  When AP is
+ * not kept (SSTEP_GRAM_APPLY_OP), AP_out is formed by the basis kernels' product
+ * step into a buffer allocated on the first such call.  Used by the lockstep
+ * parity tests. */
 sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alpha_tilde, double *G, double *ctil,
                         double *rnorm, double *P_out, double *AP_out);
 
@@ -172,9 +186,14 @@ enum { SSTEP_KT_RESIDUAL = 0, SSTEP_KT_BASIS = 1, SSTEP_KT_GRAM = 2, SSTEP_KT_FG
 /* Average duration in milliseconds of one launch of each kernel class of the
  * outer iteration (the same kernels, grids and arguments a solve uses),
  * measured with HIP events on the library stream over reps repetitions of
- * the class; the basis figure is the average over the s launches of one basis
- * (positions 0..s-1).  b is read; x is used as scratch and overwritten. */
+ * the class; the basis figure is the average over the launches of one basis
+ * (s launches, or s - 1 with SSTEP_GRAM_APPLY_OP).  b is read; x is used as
+ * scratch and overwritten. */
 sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int32_t reps, double *ms_out);
+
+/* The sstep_gram_kind a context uses (SSTEP_GRAM_STORED_AP or
+ * SSTEP_GRAM_APPLY_OP), -1 for a NULL context. */
+int32_t sstep_gram_mode(const sstep_ctx *ctx);
 
 /* Batched solves: nsys independent operators (each its own size), nrhs
  * right-hand sides per operator, one shared s and nu, per-system bounds

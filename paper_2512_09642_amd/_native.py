@@ -13,13 +13,14 @@ STATUS_NAMES = {0: "SSTEP_OK", 1: "SSTEP_E_ARG", 2: "SSTEP_E_HIP", 3: "SSTEP_E_N
                 5: "SSTEP_E_NOCONV", 6: "SSTEP_E_NONFINITE", 7: "SSTEP_E_UNSUPPORTED"}
 OP_CSR, OP_STENCIL7 = 0, 1
 FP64, FP32_IR = 0, 1
+GRAM_KINDS = {"auto": 0, "stored": 1, "apply": 2}
 KT_NAMES = ("residual", "basis", "gram", "fgs", "update")
 
 # every symbol the header declares
 EXPORTS = (
     "sstep_default_options", "sstep_setup", "sstep_update_coefficients", "sstep_apply", "sstep_solve",
     "sstep_solve_adjoint", "sstep_grad_operator", "sstep_grad_size", "sstep_n", "sstep_step",
-    "sstep_kernel_times", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
+    "sstep_kernel_times", "sstep_gram_mode", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
     "sstep_status_string", "sstep_destroy",
 )
 
@@ -34,7 +35,7 @@ class Operator(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("p0_mode", C.c_int32),
                 ("max_outer", C.c_int32), ("graph_chunk", C.c_int32), ("record_history", C.c_int32),
-                ("autotune", C.c_int32), ("stream", C.c_void_p)]
+                ("autotune", C.c_int32), ("gram", C.c_int32), ("stream", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -90,6 +91,8 @@ def load():
     lib.sstep_step.restype = st
     lib.sstep_kernel_times.argtypes = [P, P, P, C.c_int32, P]
     lib.sstep_kernel_times.restype = st
+    lib.sstep_gram_mode.argtypes = [P]
+    lib.sstep_gram_mode.restype = C.c_int32
     lib.sstep_setup_batched.argtypes = [C.POINTER(P), C.c_int32, C.POINTER(Operator), C.c_int32, C.c_int32,
                                         C.c_int32, P, P, C.POINTER(Options)]
     lib.sstep_setup_batched.restype = st

@@ -45,6 +45,7 @@ struct sstep_ctx {
     int chunk = 4;
     int64_t grad_size = 0;
     int *bad_flag = nullptr;       // device flag of the diagonal check
+    char *ap_step = nullptr;       // A P of sstep_step when AP is not kept (allocated on first use)
     struct Batched *batch = nullptr;  // set for contexts made by sstep_setup_batched
     std::string err;
 };
@@ -287,14 +288,18 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
     return SSTEP_OK;
 }
 
-// Enqueues one outer iteration: residual + p_0, s basis steps, Gram partials,
-// FGS, update.
+// Basis launches per outer iteration: s, or s - 1 when the Gram kernel forms
+// the products itself (the last launch would only compute A p_{s-1}).
+int basis_launches(const IterArgs &a) { return a.gram_op ? a.s - 1 : a.s; }
+
+// Enqueues one outer iteration: residual + p_0, the basis steps, Gram
+// partials, FGS, update.
 hipError_t enqueue_iteration(const IterArgs &a, hipStream_t s)
 {
     hipError_t e;
     if ((e = launch_residual(a, s, true)) != hipSuccess)
         return e;
-    for (int j = 0; j < a.s; ++j)
+    for (int j = 0; j < basis_launches(a); ++j)
         if ((e = launch_basis(a, j, s)) != hipSuccess)
             return e;
     if ((e = launch_gram(a, s)) != hipSuccess)
@@ -332,8 +337,9 @@ sstep_status start_state(sstep_ctx *ctx, const double *b, double *x, double tol,
 // Gram schedule and its autotuner.
 // ---------------------------------------------------------------------------
 struct GramSchedule {
-    int nbg;       // partial blocks
-    int64_t slab;  // 0: contiguous chunks; > 0: strided slabs of this many rows
+    int nbg;       // stored-AP kernel: partial blocks; operator-applying kernel: block cap
+    int64_t slab;  // stored-AP kernel: 0 contiguous chunks, > 0 strided slabs of this many rows
+    int txl;       // operator-applying kernel: tile width log2 (-1 = least padding)
     double us;     // measured time per launch (0 = not measured)
 };
 
@@ -341,11 +347,39 @@ GramSchedule default_gram_schedule(const IterArgs &it)
 {
     // Measured on MI355X at 224^3, s = 16: FP64 prefers one contiguous chunk
     // per CU, FP32 prefers grid-strided 2048-row slabs.
-    return it.fp32 ? GramSchedule{256, 2048, 0.0} : GramSchedule{256, 0, 0.0};
+    if (it.gram_op)
+        return GramSchedule{1024, 0, -1, 0.0};
+    return it.fp32 ? GramSchedule{256, 2048, -1, 0.0} : GramSchedule{256, 0, -1, 0.0};
+}
+
+// Geometry of the operator-applying Gram kernel: 32 x 8 in-plane tiles, the
+// z-extent cut into ranges so that the (tile, range) items number about
+// `cap`; one block per item up to `cap` blocks (a block loops over several
+// items beyond that).  One partial slot per block.
+void set_go_geometry(IterArgs &it, int cap)
+{
+    const Grid3 &g = it.op.g;
+    const int64_t tx = 32, ty = 8;
+    cap = std::max(1, std::min(cap, kMaxGramBlocks));
+    const int64_t tiles = ((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+    const int64_t nzb_t = std::max<int64_t>(1, std::min<int64_t>(g.nz, cap / tiles));
+    const int64_t zr = (g.nz + nzb_t - 1) / nzb_t;
+    const int64_t nzb = (g.nz + zr - 1) / zr;
+    it.go_tiles_x = int((g.nx + tx - 1) / tx);
+    it.go_tiles_y = int((g.ny + ty - 1) / ty);
+    it.go_zr = int(zr);
+    it.go_nzb = int(nzb);
+    it.go_items = int(tiles * nzb);
+    it.go_blocks = int(std::min<int64_t>(tiles * nzb, cap));
+    it.nbg = it.go_blocks;  // one partial slot per block
 }
 
 void set_gram_schedule(IterArgs &it, const GramSchedule &g)
 {
+    if (it.gram_op) {
+        set_go_geometry(it, g.nbg);
+        return;
+    }
     const int64_t blocks_needed = (it.ld + kPad - 1) / kPad;
     it.nbg = int(std::max<int64_t>(1, std::min<int64_t>(g.nbg, blocks_needed)));
     it.gslab = g.slab;
@@ -371,11 +405,13 @@ std::string tune_key(const IterArgs &it)
     std::ostringstream k;
     k << "gfx950 gram s=" << it.s << " prec=" << (it.fp32 ? "fp32" : "fp64") << " rows=" << it.ld
       << " wd=" << it.wdvec;
+    if (it.gram_op)
+        k << " op2=" << it.op.kind << " grid=" << it.op.g.nx << "x" << it.op.g.ny << "x" << it.op.g.nz;
     return k.str();
 }
 
 // The cache is a JSON object written one entry per line:
-//   "key": {"nbg": 256, "slab": 0, "us": 507.3},
+//   "key": {"nbg": 256, "slab": 0, "txl": -1, "us": 507.3},
 std::map<std::string, GramSchedule> read_tune_cache(const std::string &path)
 {
     std::map<std::string, GramSchedule> m;
@@ -385,9 +421,10 @@ std::map<std::string, GramSchedule> read_tune_cache(const std::string &path)
         const size_t a = line.find('"'), b = line.find("\": {");
         if (a == std::string::npos || b == std::string::npos || b <= a)
             continue;
-        GramSchedule g{0, 0, 0.0};
+        GramSchedule g{0, 0, -1, 0.0};
         long long slab = 0;
-        if (std::sscanf(line.c_str() + b, "\": {\"nbg\": %d, \"slab\": %lld, \"us\": %lf", &g.nbg, &slab, &g.us) == 3) {
+        if (std::sscanf(line.c_str() + b, "\": {\"nbg\": %d, \"slab\": %lld, \"txl\": %d, \"us\": %lf", &g.nbg,
+                        &slab, &g.txl, &g.us) == 4) {
             g.slab = slab;
             m[line.substr(a + 1, b - a - 1)] = g;
         }
@@ -406,7 +443,8 @@ void write_tune_cache(const std::string &path, const std::map<std::string, GramS
         size_t q = 0;
         for (const auto &kv : m) {
             f << "  \"" << kv.first << "\": {\"nbg\": " << kv.second.nbg << ", \"slab\": " << kv.second.slab
-              << ", \"us\": " << kv.second.us << "}" << (++q < m.size() ? "," : "") << "\n";
+              << ", \"txl\": " << kv.second.txl << ", \"us\": " << kv.second.us << "}"
+              << (++q < m.size() ? "," : "") << "\n";
         }
         f << "}\n";
     }
@@ -431,11 +469,18 @@ sstep_status tune_gram(sstep_ctx *ctx)
         }
     }
     std::vector<GramSchedule> cand;
-    for (int nbg : {256, 384, 512, 1024, 2048})
-        cand.push_back({nbg, 0, 0.0});
-    for (int64_t slab : {int64_t(1024), int64_t(2048), int64_t(4096)})
-        for (int nbg : {256, 512, 1024, 2048})
-            cand.push_back({nbg, slab, 0.0});
+    if (it.gram_op) {
+        // at most 1024 partial slots: the FGS kernel's reduction of the
+        // partials grows with their number and is not part of this timing
+        for (int cap : {256, 384, 512, 768, 1024})
+            cand.push_back({cap, 0, -1, 0.0});
+    } else {
+        for (int nbg : {256, 384, 512, 1024, 2048})
+            cand.push_back({nbg, 0, -1, 0.0});
+        for (int64_t slab : {int64_t(1024), int64_t(2048), int64_t(4096)})
+            for (int nbg : {256, 512, 1024, 2048})
+                cand.push_back({nbg, slab, -1, 0.0});
+    }
     GramSchedule best = default_gram_schedule(it);
     best.us = 1e30;
     for (GramSchedule &c : cand) {
@@ -556,6 +601,7 @@ void sstep_default_options(sstep_options *opt)
     opt->graph_chunk = 4;
     opt->record_history = 0;
     opt->autotune = 1;
+    opt->gram = SSTEP_GRAM_AUTO;
     opt->stream = nullptr;
 }
 
@@ -642,6 +688,22 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     OKCHK(check_operator(ctx, A));
     if (A->kind == SSTEP_OP_CSR)
         OKCHK(check_csr_pattern(ctx, A));
+    if (o.gram != SSTEP_GRAM_AUTO && o.gram != SSTEP_GRAM_STORED_AP && o.gram != SSTEP_GRAM_APPLY_OP)
+        return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
+    // The operator-applying Gram kernel: stencil operators, s <= 16, columns
+    // under 4 GiB (32-bit byte offsets); by default for FP64 only (in FP32+IR
+    // the stored-AP kernel is as fast).
+    bool gram_op = false;
+    {
+        const int64_t n = A->kind == SSTEP_OP_STENCIL7 ? int64_t(A->nx) * A->ny * A->nz : A->n;
+        const uint64_t wbytes = o.precision == SSTEP_FP32_IR ? sizeof(float) : sizeof(double);
+        const bool op_ok = A->kind == SSTEP_OP_STENCIL7 && s <= kGoMaxS &&
+                           uint64_t(round_up(n, kPad)) * wbytes < (uint64_t(1) << 32);
+        if (o.gram == SSTEP_GRAM_APPLY_OP && !op_ok)
+            return fail(ctx, SSTEP_E_UNSUPPORTED,
+                        "the operator-applying Gram kernel needs a stencil operator and s <= 16");
+        gram_op = o.gram == SSTEP_GRAM_APPLY_OP || (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
+    }
 
     HIPCHK(ctx, hipGetDevice(&ctx->device));
     HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -698,15 +760,20 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     it.wdvec = jac_p0 && op.kind != kOpPoisson;
     it.cscale = (jac_p0 && op.kind == kOpPoisson) ? 6.0 : 1.0;
 
-    // workspace: P and AP zero-filled, so the padding rows n..ld-1 read as 0
+    // workspace: P and AP zero-filled, so the padding rows n..ld-1 read as 0;
+    // stencil operators with s <= 16 use the Gram kernel that applies the
+    // operator itself, and AP is not kept
     const int64_t n = op.n;
     const size_t w = it.fp32 ? sizeof(float) : sizeof(double);
+    it.gram_op = gram_op;
     {
         char *P = nullptr, *AP = nullptr;
         OKCHK(dalloc(ctx, &P, size_t(it.ld) * s * w));
-        OKCHK(dalloc(ctx, &AP, size_t(it.ld) * s * w));
         HIPCHK(ctx, hipMemsetAsync(P, 0, size_t(it.ld) * s * w, ctx->stream));
-        HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(it.ld) * s * w, ctx->stream));
+        if (!it.gram_op) {
+            OKCHK(dalloc(ctx, &AP, size_t(it.ld) * s * w));
+            HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(it.ld) * s * w, ctx->stream));
+        }
         it.P = P;
         it.AP = AP;
     }
@@ -786,6 +853,11 @@ sstep_status sstep_apply(sstep_ctx *ctx, const double *x, double *y)
     return SSTEP_OK;
 }
 
+int32_t sstep_gram_mode(const sstep_ctx *ctx)
+{
+    return ctx ? (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP) : -1;
+}
+
 sstep_status sstep_solve(sstep_ctx *ctx, const double *b, double *x, double tol, sstep_stats *st)
 {
     return run_solve(ctx, b, x, tol, st);
@@ -824,8 +896,26 @@ sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alph
     HIPCHK(ctx, enqueue_iteration(it, ctx->stream));
     if (P_out)
         HIPCHK(ctx, launch_copy_cols(it.P, it.ld, it.fp32, s, it.op.n, P_out, ctx->stream));
-    if (AP_out)
-        HIPCHK(ctx, launch_copy_cols(it.AP, it.ld, it.fp32, s, it.op.n, AP_out, ctx->stream));
+    if (AP_out) {
+        if (it.gram_op) {
+            // AP is not kept: form A p_j with the basis kernels' product step
+            // into a buffer allocated on first use.
+            if (!ctx->ap_step) {
+                char *buf = nullptr;
+                const size_t bytes = size_t(it.ld) * s * (it.fp32 ? sizeof(float) : sizeof(double));
+                OKCHK(dalloc(ctx, &buf, bytes));
+                HIPCHK(ctx, hipMemsetAsync(buf, 0, bytes, ctx->stream));
+                ctx->ap_step = buf;
+            }
+            IterArgs t = it;
+            t.AP = ctx->ap_step;
+            for (int j = 0; j < s; ++j)
+                HIPCHK(ctx, launch_product(t, j, ctx->stream));
+            HIPCHK(ctx, launch_copy_cols(t.AP, it.ld, it.fp32, s, it.op.n, AP_out, ctx->stream));
+        } else {
+            HIPCHK(ctx, launch_copy_cols(it.AP, it.ld, it.fp32, s, it.op.n, AP_out, ctx->stream));
+        }
+    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<double> dbg(size_t(dbg_size(s)));
     HIPCHK(ctx, hipMemcpy(dbg.data(), it.dbg, dbg.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -862,7 +952,7 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
                 HIPCHK(ctx, launch_residual(it, s, true));
                 break;
             case SSTEP_KT_BASIS:
-                for (int j = 0; j < it.s; ++j)
+                for (int j = 0; j < basis_launches(it); ++j)
                     HIPCHK(ctx, launch_basis(it, j, s));
                 break;
             case SSTEP_KT_GRAM:
@@ -879,7 +969,8 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
         HIPCHK(ctx, hipEventSynchronize(ctx->ev_t1));
         float ms = 0.f;
         HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
-        ms_out[cls] = double(ms) / (cls == SSTEP_KT_BASIS ? double(reps) * it.s : double(reps));
+        const int per = cls == SSTEP_KT_BASIS ? basis_launches(it) : 1;
+        ms_out[cls] = per > 0 ? double(ms) / (double(reps) * per) : 0.0;
     }
     HIPCHK(ctx, hipStreamSynchronize(s));
     return SSTEP_OK;
@@ -989,7 +1080,7 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     }
     OKCHK(batched_tiles(ctx, best_chunk, best_factor, true));
     if (!path.empty()) {
-        cache[key.str()] = GramSchedule{best_factor, best_chunk, 1e3 * best / 2};
+        cache[key.str()] = GramSchedule{best_factor, best_chunk, -1, 1e3 * best / 2};
         write_tune_cache(path, cache);
     }
     return SSTEP_OK;

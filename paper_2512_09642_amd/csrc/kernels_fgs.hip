@@ -1,11 +1,14 @@
 // Dispatch of the Gram and FGS launches to the translation unit that holds
 // the instantiation for the basis width s.
 #include "batched_impl.h"
+#include "gram_op_impl.h"
 
 namespace sstep {
 
 hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 {
+    if (a.gram_op)
+        return a.s <= 8 ? gram_op_launch_1_8(a, st) : gram_op_launch_9_16(a, st);
     if (a.s <= 8)
         return gram_launch_1_8(a, st);
     if (a.s <= 16)

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_basis(const DevState *__restrict__ s
         return;
     T pc, y, dinv;
     op.apply(pj, c, pc, y, dinv);
-    __builtin_nontemporal_store(y, apj + c);
+    if (apj)
+        __builtin_nontemporal_store(y, apj + c);
     if constexpr (STEP == 0) {
         pnext[c] = theta * (dinv * y - sigma * pc);
     } else if constexpr (STEP == 1) {
@@ -141,8 +142,10 @@ __global__ __launch_bounds__(kBlock) void k_basis_p2(const DevState *__restrict_
         double2 y;
         y.x = 6.0 * ctr.x - (((((w + ctr.y) + s.x) + nn.x) + below.x) + above.x);
         y.y = 6.0 * ctr.y - (((((ctr.x + e) + s.y) + nn.y) + below.y) + above.y);
-        __builtin_nontemporal_store(y.x, apj + c);
-        __builtin_nontemporal_store(y.y, apj + c + 1);
+        if (apj) {
+            __builtin_nontemporal_store(y.x, apj + c);
+            __builtin_nontemporal_store(y.y, apj + c + 1);
+        }
         if constexpr (STEP == 0) {
             double2 pn;
             pn.x = theta * (minv * y.x - sigma * ctr.x);
@@ -449,20 +452,20 @@ hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
 }
 
 template <class Op, typename T>
-hipError_t basis_for(const IterArgs &a, const Op &op, int j, hipStream_t st)
+hipError_t basis_for(const IterArgs &a, const Op &op, int j, int step, hipStream_t st)
 {
     const Launch1D l = plan_points(a.op.n);
     T *P = static_cast<T *>(a.P);
     T *AP = static_cast<T *>(a.AP);
     const T *pj = P + j * a.ld;
     const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
-    T *apj = AP + j * a.ld;
+    T *apj = AP ? AP + j * a.ld : nullptr;
     T *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
     const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
-    if (j + 1 >= a.s)
+    if (step == 2)
         hipLaunchKernelGGL((k_basis<Op, T, 2>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
                            theta, sigma, a.op.n, l.per, l.nbl);
-    else if (j == 0)
+    else if (step == 0)
         hipLaunchKernelGGL((k_basis<Op, T, 0>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
                            theta, sigma, a.op.n, l.per, l.nbl);
     else
@@ -472,7 +475,7 @@ hipError_t basis_for(const IterArgs &a, const Op &op, int j, hipStream_t st)
 }
 
 // FP64 constant Poisson with an even x-extent: pairs of points, two planes.
-hipError_t basis_poisson_pairs(const IterArgs &a, int j, hipStream_t st)
+hipError_t basis_poisson_pairs(const IterArgs &a, int j, int step, hipStream_t st)
 {
     const dim3 grid(static_cast<uint32_t>((a.op.g.nxy / 2 + kBlock - 1) / kBlock),
                     static_cast<uint32_t>((a.op.g.nz + 1) / 2));
@@ -480,13 +483,13 @@ hipError_t basis_poisson_pairs(const IterArgs &a, int j, hipStream_t st)
     double *AP = static_cast<double *>(a.AP);
     const double *pj = P + j * a.ld;
     const double *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
-    double *apj = AP + j * a.ld;
+    double *apj = AP ? AP + j * a.ld : nullptr;
     double *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
     const double minv = a.op.precond ? 1.0 / 6.0 : 1.0;
-    if (j + 1 >= a.s)
+    if (step == 2)
         hipLaunchKernelGGL(k_basis_p2<2>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
                            a.theta, a.sigma);
-    else if (j == 0)
+    else if (step == 0)
         hipLaunchKernelGGL(k_basis_p2<0>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
                            a.theta, a.sigma);
     else
@@ -496,21 +499,21 @@ hipError_t basis_poisson_pairs(const IterArgs &a, int j, hipStream_t st)
 }
 
 template <typename T>
-hipError_t basis_csr(const IterArgs &a, int j, hipStream_t st)
+hipError_t basis_csr(const IterArgs &a, int j, int step, hipStream_t st)
 {
     const uint32_t nb = blocks_for(a.op.n);
     T *P = static_cast<T *>(a.P);
     T *AP = static_cast<T *>(a.AP);
     const T *pj = P + j * a.ld;
     const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
-    T *apj = AP + j * a.ld;
+    T *apj = AP ? AP + j * a.ld : nullptr;
     T *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
     const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
     const OpCsr<T> op = Ops<T>::csr(a.op);
-    if (j + 1 >= a.s)
+    if (step == 2)
         hipLaunchKernelGGL((k_basis_csr<T, 2>), dim3(nb), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext, theta,
                            sigma, a.op.n);
-    else if (j == 0)
+    else if (step == 0)
         hipLaunchKernelGGL((k_basis_csr<T, 0>), dim3(nb), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext, theta,
                            sigma, a.op.n);
     else
@@ -519,19 +522,20 @@ hipError_t basis_csr(const IterArgs &a, int j, hipStream_t st)
     return hipGetLastError();
 }
 
+// step 0: p_1 from p_0; 1: p_{j+1} from p_j, p_{j-1}; 2: the product A p_j only.
 template <typename T>
-hipError_t basis_t(const IterArgs &a, int j, hipStream_t st)
+hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
 {
     switch (a.op.kind) {
     case kOpPoisson:
         if constexpr (sizeof(T) == 8)
             if (a.op.g.nx % 2 == 0)
-                return basis_poisson_pairs(a, j, st);
-        return basis_for<OpPoisson7<T>, T>(a, make_poisson<T>(a.op), j, st);
+                return basis_poisson_pairs(a, j, step, st);
+        return basis_for<OpPoisson7<T>, T>(a, make_poisson<T>(a.op), j, step, st);
     case kOpFaces:
-        return basis_for<OpFaces7<T>, T>(a, Ops<T>::faces(a.op), j, st);
+        return basis_for<OpFaces7<T>, T>(a, Ops<T>::faces(a.op), j, step, st);
     default:
-        return basis_csr<T>(a, j, st);
+        return basis_csr<T>(a, j, step, st);
     }
 }
 
@@ -550,7 +554,13 @@ hipError_t launch_p0scale(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st)
 {
-    return a.fp32 ? basis_t<float>(a, j, st) : basis_t<double>(a, j, st);
+    const int step = j + 1 >= a.s ? 2 : (j == 0 ? 0 : 1);
+    return a.fp32 ? basis_t<float>(a, j, step, st) : basis_t<double>(a, j, step, st);
+}
+
+hipError_t launch_product(const IterArgs &a, int j, hipStream_t st)
+{
+    return a.fp32 ? basis_t<float>(a, j, 2, st) : basis_t<double>(a, j, 2, st);
 }
 
 hipError_t launch_update(const IterArgs &a, hipStream_t st)

@@ -15,6 +15,8 @@ enum OpKind { kOpCsr = 0, kOpPoisson = 1, kOpFaces = 2 };
 constexpr int64_t kPad = 256;
 // Largest Gram partial-block count a schedule may use.
 constexpr int kMaxGramBlocks = 2048;
+// Widest basis served by the Gram kernel that applies a stencil operator itself.
+constexpr int kGoMaxS = 16;
 
 // Device copy of the operator in both precisions (the FP32 arrays exist only
 // in FP32+IR mode).
@@ -60,6 +62,12 @@ struct IterArgs {
     double *hist = nullptr;  // [2 * hist_cap]: relres then delta
     int hist_cap = 0;
     double inv_sqrt_n = 1.0;
+    // Gram kernel that applies the stencil operator itself (AP not stored;
+    // the basis steps skip the AP write and the last product):
+    int gram_op = 0;
+    int go_tiles_x = 0, go_tiles_y = 0;  // 32 x 8 tiles per plane
+    int go_zr = 0, go_nzb = 0;          // planes per z-range, z-ranges
+    int go_items = 0, go_blocks = 0;    // work items (tile, z-range) and blocks
 };
 
 // Debug block layout written by the FGS kernel.
@@ -130,6 +138,8 @@ hipError_t launch_bupdate(const BatchArgs &a, hipStream_t st);
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);
+// AP[:, j] = A p_j alone (into a.AP, which must be set).
+hipError_t launch_product(const IterArgs &a, int j, hipStream_t st);
 hipError_t launch_gram(const IterArgs &a, hipStream_t st);
 hipError_t launch_fgs(const IterArgs &a, hipStream_t st);
 hipError_t launch_update(const IterArgs &a, hipStream_t st);

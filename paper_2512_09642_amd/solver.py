@@ -124,7 +124,7 @@ class Solver:
 
     def __init__(self, op: Operator, s: int, nu: int, lmin: float, lmax: float, *, precision: str = "fp64",
                  precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
-                 record_history: bool = False, autotune: bool = True, stream=None):
+                 record_history: bool = False, autotune: bool = True, gram: str = "auto", stream=None):
         self._lib = N.load()
         self.op = op
         self.s, self.nu, self.lmin, self.lmax = s, nu, lmin, lmax
@@ -138,6 +138,7 @@ class Solver:
         opt.graph_chunk = graph_chunk
         opt.record_history = 1 if record_history else 0
         opt.autotune = 1 if autotune else 0
+        opt.gram = N.GRAM_KINDS[gram]
         self._stream = stream
         opt.stream = self._stream_ptr()
         self.max_outer = max_outer
@@ -150,6 +151,8 @@ class Solver:
         self._ctx = ctx
         self.n = int(self._lib.sstep_n(ctx))
         self.grad_size = int(self._lib.sstep_grad_size(ctx))
+        # True when the Gram kernel forms A p_j itself (AP not kept, s - 1 basis launches)
+        self.gram_applies_operator = bool(self._lib.sstep_gram_mode(ctx) == N.GRAM_KINDS["apply"])
 
     def _stream_ptr(self):
         if self._stream is not None:

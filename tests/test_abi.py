@@ -37,7 +37,8 @@ def test_default_options_and_status_strings(native):
     opt = native.Options()
     lib.sstep_default_options(C.byref(opt))
     assert (opt.precision, opt.precond, opt.p0_mode, opt.max_outer, opt.graph_chunk, opt.record_history,
-            opt.autotune) == (0, 1, 0, 10000, 4, 0, 1)
+            opt.autotune, opt.gram) == (0, 1, 0, 10000, 4, 0, 1, 0)
+    assert lib.sstep_gram_mode(None) == -1
     for code, name in native.STATUS_NAMES.items():
         assert lib.sstep_status_string(code).decode() == name
 
@@ -117,3 +118,27 @@ def test_batched_entry_points_report_status(native):
     ctx = C.c_void_p()
     st = lib.sstep_setup_batched(C.byref(ctx), 0, None, 1, 4, 5, None, None, None)
     assert st != 0
+
+
+def test_setup_rejects_unavailable_gram_kinds(native):
+    """The operator-applying Gram kernel needs a stencil operator and s <= 16;
+    asking for it otherwise is unsupported, an unknown kind is an argument
+    error.  Checked before any device work."""
+    lib = native.load()
+
+    def setup(op, s, gram):
+        opt = native.Options()
+        lib.sstep_default_options(C.byref(opt))
+        opt.gram = gram
+        ctx = C.c_void_p()
+        return lib.sstep_setup(C.byref(ctx), C.byref(op), s, 5, 0.1, 1.9, C.byref(opt)), ctx
+
+    apply_op = native.GRAM_KINDS["apply"]
+    st, ctx = setup(_poisson(native), 17, apply_op)
+    assert st == 7 and not ctx.value
+    rp = np.array([0, 1, 2]); ci = np.array([0, 1]); v = np.array([2.0, 2.0])
+    op, keep = _csr(native, rp, ci, v)
+    st, ctx = setup(op, 4, apply_op)
+    assert st == 7 and not ctx.value
+    st, ctx = setup(_poisson(native), 4, 3)
+    assert st == 1 and not ctx.value
