@@ -363,7 +363,7 @@ void set_go_geometry(IterArgs &it, int cap)
     cap = std::max(1, std::min(cap, kMaxGramBlocks));
     const int64_t tiles = ((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
     const int64_t nzb_t = std::max<int64_t>(1, std::min<int64_t>(g.nz, cap / tiles));
-    const int64_t zr = (g.nz + nzb_t - 1) / nzb_t;
+    const int64_t zr = round_up((g.nz + nzb_t - 1) / nzb_t, 2);  // even: the kernel runs z-steps in pairs
     const int64_t nzb = (g.nz + zr - 1) / zr;
     it.go_tiles_x = int((g.nx + tx - 1) / tx);
     it.go_tiles_y = int((g.ny + ty - 1) / ty);

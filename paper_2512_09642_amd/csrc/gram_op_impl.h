@@ -29,6 +29,8 @@
 //    stored-AP Gram, so results are bitwise reproducible from run to run.
 #pragma once
 
+#include <type_traits>
+
 #include "gram_impl.h"
 
 namespace sstep {
@@ -45,6 +47,7 @@ constexpr int kGoRing = 2 * (kGoTx + kGoTy);       // halo ring: 80 points
 // the same order of operations as the basis kernels.
 template <typename T>
 struct GoPoisson {
+    static constexpr bool kHasCoef = false;
     struct Coef {};
     __device__ __forceinline__ Coef load(const Grid3 &, uint32_t, uint32_t, int64_t) const { return {}; }
     __device__ __forceinline__ static T y(const Coef &, T pc, T w, T e, T s, T n, T b, T t)
@@ -58,6 +61,7 @@ struct GoPoisson {
 // kx (nx+1) x ny x nz, ky nx x (ny+1) x nz, kz nx x ny x (nz+1), x fastest.
 template <typename T>
 struct GoFaces {
+    static constexpr bool kHasCoef = true;
     const T *__restrict__ kx;
     const T *__restrict__ ky;
     const T *__restrict__ kz;
@@ -130,159 +134,219 @@ __global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restri
     static_assert(S >= 1 && S <= kGoMaxS, "the 16 x 16 matrix-core tile holds at most 16 columns");
     constexpr int E = S * (S + 1) / 2 + S;                             // Gram entries + right-hand side
     constexpr int NH = (kGoRing * S + kGoThreads - 1) / kGoThreads;  // halo entries per thread
+    constexpr int KC = kWave / 4;                                      // points per lane per plane
     constexpr uint32_t W = sizeof(T);
-    constexpr int txw = kGoTx, tyh = kGoTy, tx2 = kGoTx2, pitch = kGoPitch, ring = kGoRing;
+    constexpr int txw = kGoTx, tyh = kGoTy, tx2 = kGoTx2, ring = kGoRing;
+    constexpr int CS = kGoPitch + 1;  // LDS stride of a column's padded tile (odd: spreads the banks)
+    constexpr bool HAS_COEF = Rule::kHasCoef;
     using M = GoMfma<T>;
-    __shared__ T Pt[S * kGoPitch];
-    __shared__ T APt[S][kGoThreads];
-    static_assert(sizeof(APt) >= sizeof(double) * (kGoThreads / kWave) * E, "reduction buffer fits in APt");
+    using Coef = typename Rule::Coef;
+    __shared__ T Pt[S * CS];
+    __shared__ T Dt[WD ? kGoThreads : 1];
+    __shared__ Coef Ct[HAS_COEF ? kGoThreads : 1];
+    __shared__ double red[kGoThreads / kWave][E];
     if (st->done)
         return;
     const int t = threadIdx.x;
     const int lane = t % kWave, wv = t / kWave;
-    const int lx = t & (txw - 1), ly = t >> kGoTxl;
-    const int pos = (ly + 1) * tx2 + lx + 1;  // this thread's point in the padded tile
+    // Thread t as a grid point (halo, diagonal and coefficient staging).
+    const int tlx = t & (txw - 1), tly = t >> kGoTxl;
+    // Lane as matrix-core operand: column n at the points p(kc) = 64 wv + 4 kc + gq,
+    // kc = 0..15, i.e. tile row 2 wv + kc / 8, tile column 4 (kc % 8) + gq.
+    const int n = lane & 15, gq = lane >> 4;
+    const bool ncol = n < S;
+    const int nc = ncol ? n : 0;  // column actually read (unused lanes reread column 0)
     const uint32_t pb = static_cast<uint32_t>(g.nxy) * W;  // bytes per plane
-    // matrix-core operands of this lane: column mc of P / AP at point 4 kc + lane / 16
-    const int mc = lane & 15;
-    const bool mcol = mc < S;
 
     typename M::acc_t gacc = {};  // this wave's share of G_raw
-    T cacc[S];                    // this thread's share of c' = P^T W
-#pragma unroll
-    for (int c = 0; c < S; ++c)
-        cacc[c] = T(0);
+    T cacc = T(0);                // this lane's share of c'_n
 
     const int tiles = geo.tiles_x * geo.tiles_y;
     for (int item = blockIdx.x; item < geo.items; item += gridDim.x) {
         const int tile = item % tiles, zb = item / tiles;
         const int i0 = (tile % geo.tiles_x) * txw, j0 = (tile / geo.tiles_x) * tyh;
-        const uint32_t i = static_cast<uint32_t>(i0 + lx), j = static_cast<uint32_t>(j0 + ly);
-        const bool valid = i < static_cast<uint32_t>(g.nx) && j < static_cast<uint32_t>(g.ny);
         const int z0 = zb * geo.zr;
         const int z1 = z0 + geo.zr < g.nz ? z0 + geo.zr : g.nz;
-        // points outside the grid address point (0, 0, k): in range, values unused
-        const uint32_t q = valid ? i + static_cast<uint32_t>(g.nx) * j : 0u;
-        const uint32_t jr = valid ? j : 0u;
-
-        // Loads for z-step kk, issued one step ahead: plane kk+1 of the point
-        // (zp), the halo ring of plane kk (hv; entry h < ring * S of the
-        // block: column h / ring, ring position h % ring = bottom row, top
-        // row, left column, right column), the operator coefficients (f) and
-        // the M-diagonal (dv) of the point.
-        T zm[S], zc[S], zp[S];
-        T hv[NH];
-        typename Rule::Coef f{};
-        T dv = T(0);
-        auto issue = [&](int kk) {
-            const int64_t cidx = static_cast<int64_t>(q) + static_cast<int64_t>(kk) * g.nxy;
-            const uint32_t o = static_cast<uint32_t>(cidx) * W;
-            const uint32_t op = valid && kk + 1 < g.nz ? o + pb : o;
+        // this thread's staging point
+        const uint32_t ti = static_cast<uint32_t>(i0 + tlx), tj = static_cast<uint32_t>(j0 + tly);
+        const bool tvalid = ti < static_cast<uint32_t>(g.nx) && tj < static_cast<uint32_t>(g.ny);
+        const uint32_t tq = tvalid ? ti + static_cast<uint32_t>(g.nx) * tj : 0u;
+        const uint32_t tjr = tvalid ? tj : 0u;
+        // this lane's points: validity mask and in-plane offset of point kc = 0
+        const int li = i0 + gq, lj = j0 + 2 * wv;
+        uint32_t vmask = 0;
 #pragma unroll
-            for (int m = 0; m < NH; ++m) {
-                const int h = t + m * kGoThreads;
-                const int c = h / ring, r = h - c * ring;
-                const int hx = r < txw ? r : r < 2 * txw ? r - txw : r < 2 * txw + tyh ? -1 : txw;
-                const int hy = r < txw ? -1 : r < 2 * txw ? tyh : r < 2 * txw + tyh ? r - 2 * txw : r - 2 * txw - tyh;
-                const int gi = i0 + hx, gj = j0 + hy;
-                const bool in = c < S && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-                const int64_t e = in ? static_cast<int64_t>(c) * ld + gi + static_cast<int64_t>(g.nx) * gj +
-                                           static_cast<int64_t>(kk) * g.nxy
-                                     : 0;
-                hv[m] = P[e];
-            }
-            // keep the halo loads first: loads complete in issue order, so the
-            // halo can be stored while the plane loads are still in flight
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int c = 0; c < S; ++c)
-                zp[c] = go_ld(P + c * ld, op);
-            f = rule.load(g, jr + static_cast<uint32_t>(g.ny) * static_cast<uint32_t>(kk), static_cast<uint32_t>(kk),
-                          cidx);
-            if constexpr (WD)
-                dv = go_ld(dvec, o);
+        for (int kc = 0; kc < KC; ++kc)
+            if (li + 4 * (kc % 8) < g.nx && lj + kc / 8 < g.ny)
+                vmask |= 1u << kc;
+        const uint32_t lq = static_cast<uint32_t>(li + g.nx * lj);
+        const uint32_t rowb = static_cast<uint32_t>(g.nx) * W;  // bytes per grid row
+        auto lofsb = [&](int kc) -> uint32_t {  // in-plane byte offset of point kc (valid points)
+            return (lq + static_cast<uint32_t>(4 * (kc % 8))) * W + (kc / 8 ? rowb : 0u);
         };
-        {
-            const uint32_t o = (q + static_cast<uint32_t>(z0) * static_cast<uint32_t>(g.nxy)) * W;
-            const uint32_t om = valid && z0 > 0 ? o - pb : o;
+        const int pbase = (2 * wv + 1) * tx2 + gq + 1;  // padded-tile index of point kc = 0
+        const T *colp = P + nc * ld;
+
+        // Halo ring of the tile: wave wv loads columns 4 wv .. 4 wv + 3.
+        // Entries m = 0..3: column 4 wv + m, lane < 32 the row below the tile,
+        // lane >= 32 the row above, x = lane % 32.  Entry 4: column
+        // 4 wv + lane / 16, the column left (lane % 16 < 8) or right of the
+        // tile, y = lane % 8.  Offsets without the plane term, the in-grid
+        // flags and LDS indices do not change along z.
+        int64_t hoff[5];
+        int hpos[5];
+        uint32_t hin = 0;
 #pragma unroll
-            for (int c = 0; c < S; ++c) {
-                const T *col = P + c * ld;
-                const T vm = go_ld(col, om), vc = go_ld(col, o);
-                zm[c] = valid && z0 > 0 ? vm : T(0);
-                zc[c] = valid ? vc : T(0);
-            }
+        for (int m = 0; m < 5; ++m) {
+            const int c = m < 4 ? 4 * wv + m : 4 * wv + (lane >> 4);
+            const int hx = m < 4 ? (lane & 31) : (((lane >> 3) & 1) ? txw : -1);
+            const int hy = m < 4 ? ((lane >> 5) ? tyh : -1) : (lane & 7);
+            const int gi = i0 + hx, gj = j0 + hy;
+            const bool in = c < S && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+            hin |= in ? (1u << m) : 0u;
+            hoff[m] = in ? static_cast<int64_t>(c) * ld + gi + static_cast<int64_t>(g.nx) * gj : 0;
+            hpos[m] = c < S ? c * CS + (hy + 1) * tx2 + hx + 1 : -1;
         }
-        issue(z0);
-        for (int k = z0; k < z1; ++k) {
-            const bool ht = valid && k + 1 < g.nz;
-            // (1) plane k: interior and halo ring into the padded tiles.
+
+        // Both paths below run the same steps; FULL (tile inside the grid in
+        // x and y) drops the per-point validity selects.
+        auto run = [&](auto full_c) {
+            constexpr bool FULL = decltype(full_c)::value;
+            auto pv = [&](int kc) -> bool { return FULL || ((vmask >> kc) & 1u); };
+            // Loads for z-step kk, issued one step ahead (before the products
+            // of step kk - 1): the halo ring of plane kk, plane kk+1 at the
+            // lane's points, the coefficients and M-diagonal of the staging
+            // point.  kk may run one plane past the range (the second step of
+            // the last pair): addresses are then clamped and values unused.
+            T zm[KC], zc[KC], qa[KC], qb[KC];
+            T hv[5];
+            Coef f{};
+            T dv = T(0);
+            auto issue = [&](int kk_, T(&dst)[KC]) {
+                const int kk = kk_ < g.nz ? kk_ : g.nz - 1;
+                const int64_t poff = static_cast<int64_t>(kk) * g.nxy;
 #pragma unroll
-            for (int c = 0; c < S; ++c)
-                Pt[c * pitch + pos] = zc[c];
+                for (int m = 0; m < 5; ++m)
+                    hv[m] = P[hoff[m] + ((hin >> m) & 1u ? poff : 0)];
+                // keep the halo loads first: loads complete in issue order, so
+                // the halo can be stored while the plane loads are in flight
+                __builtin_amdgcn_sched_barrier(0);
+                const uint32_t base = static_cast<uint32_t>(kk) * static_cast<uint32_t>(g.nxy) * W;
+                const uint32_t up = kk + 1 < g.nz ? pb : 0u;
 #pragma unroll
-            for (int m = 0; m < NH; ++m) {
-                const int h = t + m * kGoThreads;
-                const int c = h / ring, r = h - c * ring;
-                const int hx = r < txw ? r : r < 2 * txw ? r - txw : r < 2 * txw + tyh ? -1 : txw;
-                const int hy = r < txw ? -1 : r < 2 * txw ? tyh : r < 2 * txw + tyh ? r - 2 * txw : r - 2 * txw - tyh;
-                const int gi = i0 + hx, gj = j0 + hy;
-                const bool in = gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-                if (c < S)
-                    Pt[c * pitch + (hy + 1) * tx2 + hx + 1] = in ? hv[m] : T(0);
-            }
-            __syncthreads();
-            // (2) right-hand side c'_i += p_i w at this point, products
-            // y_j = (A p_j)(k) into LDS, then the loads of step k + 1.
-            const T w = WD ? zc[0] * dv : zc[0];
-            const typename Rule::Coef fk = f;
+                for (int kc = 0; kc < KC; ++kc)
+                    dst[kc] = go_ld(colp, base + (pv(kc) ? lofsb(kc) + up : 0u));
+                const int64_t tc = static_cast<int64_t>(tq) + poff;
+                if constexpr (HAS_COEF)
+                    f = rule.load(g, tjr + static_cast<uint32_t>(g.ny) * static_cast<uint32_t>(kk),
+                                  static_cast<uint32_t>(kk), tc);
+                if constexpr (WD)
+                    dv = go_ld(dvec, static_cast<uint32_t>(tc) * W);
+            };
+            // One z-step k: zq holds plane k+1 of the lane's points (loaded one
+            // step earlier), zl receives plane k+2.  A step past the range
+            // (k >= z1) adds nothing.  No branch surrounds the loads, so the
+            // waits for them are exact.
+            auto zstep = [&](int k, T(&zq)[KC], T(&zl)[KC]) {
+                const bool ht = k + 1 < g.nz;
+                const bool active = k < z1;
+                // (1) plane k into the padded tiles: the lane's points of
+                // column n, the halo ring, the staging point's diagonal and
+                // coefficients.
+                if (ncol) {
 #pragma unroll
-            for (int c = 0; c < S; ++c) {
-                cacc[c] += zc[c] * w;
-                const T *L = Pt + c * pitch + pos;
-                const T zpv = ht ? zp[c] : T(0);
-                const T y = Rule::y(fk, zc[c], L[-1], L[1], L[-tx2], L[tx2], zm[c], zpv);
-                APt[c][t] = valid ? y : T(0);
-                zm[c] = zc[c];
-                zc[c] = zpv;
-                if ((c & 3) == 3)
-                    __builtin_amdgcn_sched_barrier(0);  // bounds the LDS reads in flight (registers)
+                    for (int kc = 0; kc < KC; ++kc)
+                        Pt[n * CS + pbase + (kc / 8) * tx2 + 4 * (kc % 8)] = zc[kc];
+                }
+#pragma unroll
+                for (int m = 0; m < 5; ++m)
+                    if (hpos[m] >= 0)
+                        Pt[hpos[m]] = (hin >> m) & 1u ? hv[m] : T(0);
+                if constexpr (WD)
+                    Dt[t] = tvalid ? dv : T(0);
+                if constexpr (HAS_COEF)
+                    Ct[t] = f;
+                __syncthreads();
+                // loads of step k + 1, in flight during the products of step k
+                issue(k + 1, zl);
+                // the plane above the grid is zero
+                if (!ht) {
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc)
+                        zq[kc] = T(0);
+                }
+                // (2) per point: y = (A p_n)(k) from the tile and the
+                // z-registers, G_raw += p y^T on the matrix cores,
+                // c'_n += p_n w.  Skipped past the range (block-uniform; the
+                // loads in flight are the same on both sides).
+                if (active) {
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    const int pp = pbase + (kc / 8) * tx2 + 4 * (kc % 8);
+                    const T *L = Pt + nc * CS + pp;
+                    Coef fk{};
+                    if constexpr (HAS_COEF)
+                        fk = Ct[64 * wv + 4 * kc + gq];
+                    const T zpv = pv(kc) ? zq[kc] : T(0);  // zero outside the grid
+                    const T y = Rule::y(fk, zc[kc], L[-1], L[1], L[-tx2], L[tx2], zm[kc], zpv);
+                    T w = Pt[pp];  // p_0 at the point
+                    if constexpr (WD)
+                        w *= Dt[64 * wv + 4 * kc + gq];
+                    const bool v = ncol && pv(kc);
+                    const T a = (S == 16 && FULL) || v ? zc[kc] : T(0);
+                    gacc = M::step(a, (S == 16 && FULL) || v ? y : T(0), gacc);
+                    cacc += a * w;
+                    zm[kc] = zc[kc];
+                    zc[kc] = zpv;
+                    if ((kc & 3) == 3)
+                        __builtin_amdgcn_sched_barrier(0);  // bounds the LDS reads in flight (registers)
+                }
+                }
+                __syncthreads();
+            };
+            {
+                const uint32_t base = static_cast<uint32_t>(z0) * static_cast<uint32_t>(g.nxy) * W;
+                const bool down = z0 > 0;
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    const uint32_t o = base + (pv(kc) ? lofsb(kc) : 0u);
+                    const T a = go_ld(colp, down && pv(kc) ? o - pb : o), b = go_ld(colp, o);
+                    zm[kc] = down && pv(kc) ? a : T(0);
+                    zc[kc] = pv(kc) ? b : T(0);
+                }
             }
-            if (k + 1 < z1)
-                issue(k + 1);
-            __syncthreads();
-            // (3) G_raw += P^T (A P) over this wave's 64 points, 4 at a time.
-#pragma unroll 4
-            for (int kc = 0; kc < kWave / 4; ++kc) {
-                const int pt = wv * kWave + 4 * kc + (lane >> 4);
-                const int ppos = ((pt >> kGoTxl) + 1) * tx2 + (pt & (txw - 1)) + 1;
-                const int cc = mcol ? mc : 0;
-                const T a = Pt[cc * pitch + ppos];
-                const T b = APt[cc][pt];
-                gacc = M::step(mcol ? a : T(0), mcol ? b : T(0), gacc);
+            issue(z0, qa);
+            // the two next-plane buffers alternate, so no in-flight value is copied
+            for (int k = z0; k < z1; k += 2) {
+                zstep(k, qa, qb);
+                zstep(k + 1, qb, qa);
             }
-            __syncthreads();
-        }
+        };
+        if (i0 + txw <= g.nx && j0 + tyh <= g.ny)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
     }
 
-    // Block reduction in a fixed order: wave partials into LDS (reusing APt),
-    // then entry e of the block = sum over the four waves.
-    double *red = reinterpret_cast<double *>(&APt[0][0]);
+    // Block reduction in a fixed order: wave partials into LDS, then entry e
+    // of the block = sum over the four waves.
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int m = M::row(lane, r), n = mc;
+        const int m = M::row(lane, r);
         if (m < S && n <= m)
-            red[wv * E + tri_index(m, n)] = static_cast<double>(gacc[r]);
+            red[wv][tri_index(m, n)] = static_cast<double>(gacc[r]);
     }
-#pragma unroll
-    for (int c = 0; c < S; ++c) {
-        const T v = wave_sum(cacc[c]);
-        if (lane == c)
-            red[wv * E + S * (S + 1) / 2 + c] = static_cast<double>(v);
+    {
+        // c'_n of the wave: the four lanes n, n + 16, n + 32, n + 48
+        T v = cacc + __shfl_xor(cacc, 16, kWave);
+        v += __shfl_xor(v, 32, kWave);
+        if (lane < S)
+            red[wv][S * (S + 1) / 2 + lane] = static_cast<double>(v);
     }
     __syncthreads();
     for (int e = t; e < E; e += kGoThreads)
-        gpart[static_cast<int64_t>(e) * estride + blockIdx.x] = ((red[e] + red[E + e]) + red[2 * E + e]) + red[3 * E + e];
+        gpart[static_cast<int64_t>(e) * estride + blockIdx.x] =
+            ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
 template <typename T, int S>

@@ -96,6 +96,26 @@ def test_grid_strided_blocks_match_oracle(hip):
     assert rel(host(g["x"]), o["x"]) <= 1e-10
 
 
+@pytest.mark.parametrize("faces", [False, True])
+def test_ragged_tiles_with_multiplane_ranges(hip, faces):
+    """Partial tiles in x and y (203 = 6 x 32 + 11, 101 = 12 x 8 + 5) with
+    z-ranges of several planes: points outside the grid stay zero while the
+    block marches through the range."""
+    pr = gen.small_faces3d(203, 101, 60, seed=8, sigma=0.5) if faces else gen.small_poisson3d(203, 101, 60, seed=8)
+    s, nu = 16, 25
+    A, b = oracle_rhs(pr)
+    x = np.zeros(pr.n)
+    with hip.Solver(make_operator(hip, pr, "stencil"), s, nu, pr.lmin, pr.lmax, autotune=False) as sv:
+        assert sv.gram_applies_operator
+        for k in range(2):
+            g = sv.step(t64(b), t64(x))
+            o = oracle.step(A, b, x, s, nu, pr.lmin, pr.lmax)
+            for key in ("G", "ctil", "atil"):
+                assert rel(g[key], o[key]) <= 1e-10, (k, key, rel(g[key], o[key]))
+            x = host(g["x"])
+            assert rel(x, o["x"]) <= 1e-10, k
+
+
 @pytest.mark.parametrize("gram", ["apply", "stored"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32ir"])
 @pytest.mark.parametrize("name", ["poisson_ragged", "faces_23x17x13"])
