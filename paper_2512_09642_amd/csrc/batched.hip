@@ -193,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const BGlob *__restrict__ gl
             const int64_t step = static_cast<int64_t>(nrhs) * S.ld;
             for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
                 double acc = 0.0;
-                for (int i = 0; i < s; ++i)
-                    acc += static_cast<double>(Pr[i * step + c]) * ps.alpha[i];
+                for (int i = 0; i < s; ++i)  // P is read once: non-temporal loads
+                    acc += static_cast<double>(__builtin_nontemporal_load(Pr + i * step + c)) * ps.alpha[i];
                 x[c] += acc;
             }
         }

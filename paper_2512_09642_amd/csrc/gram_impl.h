@@ -83,6 +83,26 @@ struct VecT<float, 4> {
     using t = float4;
 };
 
+// Non-temporal load of RPL consecutive values (data read once per launch).
+template <typename T, int RPL>
+__device__ __forceinline__ typename VecT<T, RPL>::t nt_load(const T *p)
+{
+    if constexpr (RPL == 1) {
+        return __builtin_nontemporal_load(p);
+    } else {
+        using NV = T __attribute__((ext_vector_type(RPL)));
+        const NV v = __builtin_nontemporal_load(reinterpret_cast<const NV *>(p));
+        typename VecT<T, RPL>::t r;
+        r.x = v[0];
+        r.y = v[1];
+        if constexpr (RPL == 4) {
+            r.z = v[2];
+            r.w = v[3];
+        }
+        return r;
+    }
+}
+
 template <typename T, int RPL>
 __device__ __forceinline__ T lanepart(const typename VecT<T, RPL>::t &v, int r)
 {
@@ -106,8 +126,8 @@ __device__ __forceinline__ void gram_rows(const T *__restrict__ P, const T *__re
     constexpr bool HC = pl.hasc[G];
     V ap[C1 - C0];
 #pragma unroll
-    for (int j = C0; j < C1; ++j)
-        ap[j - C0] = *reinterpret_cast<const V *>(AP + j * cs + m);
+    for (int j = C0; j < C1; ++j)  // P and AP are read once per launch: non-temporal loads
+        ap[j - C0] = nt_load<T, RPL>(AP + j * cs + m);
     V w{};
     if constexpr (HC) {
         w = *reinterpret_cast<const V *>(P + m);
@@ -128,7 +148,7 @@ __device__ __forceinline__ void gram_rows(const T *__restrict__ P, const T *__re
     int a = 0;
 #pragma unroll
     for (int i = R0; i < R1; ++i) {
-        const V p = *reinterpret_cast<const V *>(P + i * cs + m);
+        const V p = nt_load<T, RPL>(P + i * cs + m);
 #pragma unroll
         for (int j = C0; j < C1; ++j) {
             if (j <= i) {

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict_
     for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
         double pc, y, dinv;
         op.apply(x, c, pc, y, dinv);
-        const double r = b[c] - y;
+        const double r = __builtin_nontemporal_load(b + c) - y;  // b is read once
         acc += r * r;
         if (write_p0)
             p0[c] = static_cast<TP>(scale * (p0_mode ? r : dinv * r));
@@ -98,28 +98,33 @@ __global__ __launch_bounds__(kBlock) void k_basis(const DevState *__restrict__ s
         pnext[c] = theta * (dinv * y - sigma * pc);
     } else if constexpr (STEP == 1) {
         const T two_theta = T(2) * theta;
-        pnext[c] = two_theta * (dinv * y - sigma * pc) - pprev[c];
+        pnext[c] = two_theta * (dinv * y - sigma * pc) - __builtin_nontemporal_load(pprev + c);
     }
 }
 
 // The same step for the constant Poisson operator in FP64 (nx even): a thread
-// owns two consecutive x-points and KZ = 2 consecutive z-planes, so the +-z
-// neighbours of the two planes come from registers (three 16-byte loads for
-// four z-values instead of six); south/north/centre/previous column are read
-// as 16-byte pairs, west/east of the pair as single values, AP and p_{j+1}
-// written as pairs.  Blocks run in-plane fastest (blockIdx.x over x-y pairs,
-// blockIdx.y over plane pairs): measured faster than an XCD-contiguous block
-// order for this access pattern.
+// owns two consecutive x-points and KZ = 8 consecutive z-planes, so the +-z
+// neighbours come from registers (one 16-byte load per plane instead of
+// three); south/north/centre/previous column are read as 16-byte pairs,
+// west/east of the pair as single values, AP and p_{j+1} written as pairs.
+// p_{j-1} is read once and not reused: non-temporal loads.  1024-thread
+// blocks run in-plane fastest (blockIdx.x over x-y pairs, blockIdx.y over
+// plane groups), so a block spans several grid rows and its +-y neighbours
+// are mostly its own loads.  Shape measured fastest on MI355X among 1/2/4
+// points x 1..16 planes x 128..1024 threads (224^3, in the solve's column
+// rotation).
+constexpr int kP2Kz = 8;
+constexpr int kP2Block = 1024;
 template <int STEP>
-__global__ __launch_bounds__(kBlock) void k_basis_p2(const DevState *__restrict__ st, Grid3 g, double minv,
-                                                     const double *__restrict__ pj, const double *__restrict__ pprev,
-                                                     double *__restrict__ apj, double *__restrict__ pnext,
-                                                     double theta, double sigma)
+__global__ __launch_bounds__(kP2Block) void k_basis_p2(const DevState *__restrict__ st, Grid3 g, double minv,
+                                                       const double *__restrict__ pj, const double *__restrict__ pprev,
+                                                       double *__restrict__ apj, double *__restrict__ pnext,
+                                                       double theta, double sigma)
 {
-    constexpr int KZ = 2;
+    constexpr int KZ = kP2Kz;
     if (st->done)
         return;
-    const uint32_t pl = (blockIdx.x * kBlock + threadIdx.x) * 2;  // in-plane index of the pair
+    const uint32_t pl = (blockIdx.x * kP2Block + threadIdx.x) * 2;  // in-plane index of the pair
     if (pl >= static_cast<uint32_t>(g.nxy))
         return;
     const uint32_t j = fdiv(pl, g.dx);
@@ -152,7 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_basis_p2(const DevState *__restrict_
             pn.y = theta * (minv * y.y - sigma * ctr.y);
             *reinterpret_cast<double2 *>(pnext + c) = pn;
         } else if constexpr (STEP == 1) {
-            const double2 pp = *reinterpret_cast<const double2 *>(pprev + c);
+            double2 pp;
+            pp.x = __builtin_nontemporal_load(pprev + c);
+            pp.y = __builtin_nontemporal_load(pprev + c + 1);
             const double two_theta = 2.0 * theta;
             double2 pn;
             pn.x = two_theta * (minv * y.x - sigma * ctr.x) - pp.x;
@@ -213,33 +220,32 @@ __global__ __launch_bounds__(kBlock) void k_basis_csr(const DevState *__restrict
 }
 
 // x += P alpha, alpha = S atil from the FGS kernel (FP64; P in FP64 or FP32).
+// P is read once: non-temporal loads, plain block order (both measured
+// faster on MI355X than cached loads and an XCD-contiguous order).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update(const DevState *__restrict__ st, const T *__restrict__ P,
-                                                   int64_t ld, int s, int64_t n, uint32_t per, uint32_t nbl)
+                                                   int64_t ld, int s, int64_t n)
 {
     if (st->done)
         return;
-    const uint32_t lb = xcd_block(blockIdx.x, per);
-    if (lb >= nbl)
-        return;
-    const int64_t c = static_cast<int64_t>(lb) * kBlock + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (c >= n)
         return;
     double *__restrict__ x = st->x;
     double acc = 0.0;
     int i = 0;
     for (; i + 4 <= s; i += 4) {
-        const T v0 = P[(i + 0) * ld + c];
-        const T v1 = P[(i + 1) * ld + c];
-        const T v2 = P[(i + 2) * ld + c];
-        const T v3 = P[(i + 3) * ld + c];
+        const T v0 = __builtin_nontemporal_load(P + (i + 0) * ld + c);
+        const T v1 = __builtin_nontemporal_load(P + (i + 1) * ld + c);
+        const T v2 = __builtin_nontemporal_load(P + (i + 2) * ld + c);
+        const T v3 = __builtin_nontemporal_load(P + (i + 3) * ld + c);
         acc += static_cast<double>(v0) * st->alpha[i + 0];
         acc += static_cast<double>(v1) * st->alpha[i + 1];
         acc += static_cast<double>(v2) * st->alpha[i + 2];
         acc += static_cast<double>(v3) * st->alpha[i + 3];
     }
     for (; i < s; ++i)
-        acc += static_cast<double>(P[i * ld + c]) * st->alpha[i];
+        acc += static_cast<double>(__builtin_nontemporal_load(P + i * ld + c)) * st->alpha[i];
     x[c] += acc;
 }
 
@@ -477,8 +483,8 @@ hipError_t basis_for(const IterArgs &a, const Op &op, int j, int step, hipStream
 // FP64 constant Poisson with an even x-extent: pairs of points, two planes.
 hipError_t basis_poisson_pairs(const IterArgs &a, int j, int step, hipStream_t st)
 {
-    const dim3 grid(static_cast<uint32_t>((a.op.g.nxy / 2 + kBlock - 1) / kBlock),
-                    static_cast<uint32_t>((a.op.g.nz + 1) / 2));
+    const dim3 grid(static_cast<uint32_t>((a.op.g.nxy / 2 + kP2Block - 1) / kP2Block),
+                    static_cast<uint32_t>((a.op.g.nz + kP2Kz - 1) / kP2Kz));
     double *P = static_cast<double *>(a.P);
     double *AP = static_cast<double *>(a.AP);
     const double *pj = P + j * a.ld;
@@ -487,13 +493,13 @@ hipError_t basis_poisson_pairs(const IterArgs &a, int j, int step, hipStream_t s
     double *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
     const double minv = a.op.precond ? 1.0 / 6.0 : 1.0;
     if (step == 2)
-        hipLaunchKernelGGL(k_basis_p2<2>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
+        hipLaunchKernelGGL(k_basis_p2<2>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
                            a.theta, a.sigma);
     else if (step == 0)
-        hipLaunchKernelGGL(k_basis_p2<0>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
+        hipLaunchKernelGGL(k_basis_p2<0>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
                            a.theta, a.sigma);
     else
-        hipLaunchKernelGGL(k_basis_p2<1>, grid, dim3(kBlock), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
+        hipLaunchKernelGGL(k_basis_p2<1>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
                            a.theta, a.sigma);
     return hipGetLastError();
 }
@@ -565,13 +571,13 @@ hipError_t launch_product(const IterArgs &a, int j, hipStream_t st)
 
 hipError_t launch_update(const IterArgs &a, hipStream_t st)
 {
-    const Launch1D l = plan_points(a.op.n);
+    const dim3 grid(blocks_for(a.op.n));
     if (a.fp32)
-        hipLaunchKernelGGL(k_update<float>, dim3(l.grid), dim3(kBlock), 0, st, a.st, static_cast<const float *>(a.P),
-                           a.ld, a.s, a.op.n, l.per, l.nbl);
+        hipLaunchKernelGGL(k_update<float>, grid, dim3(kBlock), 0, st, a.st, static_cast<const float *>(a.P), a.ld,
+                           a.s, a.op.n);
     else
-        hipLaunchKernelGGL(k_update<double>, dim3(l.grid), dim3(kBlock), 0, st, a.st,
-                           static_cast<const double *>(a.P), a.ld, a.s, a.op.n, l.per, l.nbl);
+        hipLaunchKernelGGL(k_update<double>, grid, dim3(kBlock), 0, st, a.st, static_cast<const double *>(a.P), a.ld,
+                           a.s, a.op.n);
     return hipGetLastError();
 }
 
