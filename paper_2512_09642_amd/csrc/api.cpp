@@ -779,6 +779,14 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     }
     it.nbr = int(std::min<int64_t>(1024, (n + kBlock - 1) / kBlock));
     it.rchunk = round_up((n + it.nbr - 1) / it.nbr, kBlock);
+    if (op.kind == kOpPoisson && op.g.nx % 2 == 0) {
+        // 1024-thread blocks of 2 x-points x 8 planes, one partial each
+        const int64_t blocks = ((op.g.nxy / 2 + 1023) / 1024) * ((op.g.nz + 7) / 8);
+        if (blocks <= 1024) {
+            it.res_p2 = 1;
+            it.nbr = int(blocks);
+        }
+    }
     OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
     OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * kMaxGramBlocks));
     OKCHK(dalloc(ctx, &it.st, 1));

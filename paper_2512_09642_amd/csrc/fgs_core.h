@@ -176,24 +176,35 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     constexpr int nw = kFgsThreads / kWave;
-    for (int t = wave; t <= E; t += nw) {
-        const double *src = t < E ? gpart + static_cast<int64_t>(t) * nbg : rpart;
-        const int cnt = t < E ? nbg : nbr;
-        // four independent loads per pass keep several memory requests in
-        // flight per lane; the summation order is fixed by cnt alone
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int q = lane;
-        for (; q + 3 * kWave < cnt; q += 4 * kWave) {
-            a0 += src[q];
-            a1 += src[q + kWave];
-            a2 += src[q + 2 * kWave];
-            a3 += src[q + 3 * kWave];
+    // Wave w sums entries t = w, w + nw, ... (t = E is the residual norm):
+    // one pass over the partial index with one accumulator per entry, so a
+    // lane has one independent load per entry in flight; the summation
+    // order of each entry is fixed by its count alone.
+    constexpr int EPW = (E + 1 + nw - 1) / nw;
+    double acc[EPW];
+#pragma unroll
+    for (int m = 0; m < EPW; ++m)
+        acc[m] = 0.0;
+    const int cmax = nbg > nbr ? nbg : nbr;
+    for (int q = lane; q < cmax; q += kWave) {
+#pragma unroll
+        for (int m = 0; m < EPW; ++m) {
+            // no branch around the loads (clamped index, unused values
+            // selected away), so the compiler keeps them all in flight
+            const int t = wave + m * nw;
+            const int tc = t < E ? t : E;
+            const double *src = tc < E ? gpart + static_cast<int64_t>(tc) * nbg : rpart;
+            const int cnt = tc < E ? nbg : nbr;
+            const double v = src[q < cnt ? q : cnt - 1];
+            acc[m] += t <= E && q < cnt ? v : 0.0;
         }
-        for (; q < cnt; q += kWave)
-            a0 += src[q];
-        const double acc = wave_sum((a0 + a1) + (a2 + a3));
-        if (lane == 0)
-            sg[t] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < EPW; ++m) {
+        const int t = wave + m * nw;
+        const double v = wave_sum(acc[m]);
+        if (t <= E && lane == 0)
+            sg[t] = v;
     }
     __syncthreads();
     if (wave != 0)

@@ -70,6 +70,70 @@ __global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict_
     block_sum_store(acc, rpart + lb);
 }
 
+// The residual for the constant Poisson operator in FP64 (nx even) in the
+// basis kernel's shape: two x-points and kP2Kz planes per thread, 1024-thread
+// blocks, +-z neighbours of x from registers, b read once (non-temporal).
+// One partial sum of r^2 per block, blocks numbered blockIdx.x + gridDim.x *
+// blockIdx.y (the launch keeps their number within the partial buffer).
+template <typename TP>
+__global__ __launch_bounds__(1024) void k_residual_p2(const DevState *__restrict__ st, Grid3 g, double minv,
+                                                      TP *__restrict__ p0, double *__restrict__ rpart, int p0_mode,
+                                                      int write_p0)
+{
+    constexpr int KZ = 8;
+    __shared__ double part[1024 / kWave];
+    if (st->done)
+        return;
+    const double *__restrict__ x = st->x;
+    const double *__restrict__ b = st->b;
+    const double scale = st->p0scale;
+    const uint32_t pl = (blockIdx.x * 1024 + threadIdx.x) * 2;  // in-plane index of the pair
+    double acc = 0.0;
+    if (pl < static_cast<uint32_t>(g.nxy)) {
+        const uint32_t j = fdiv(pl, g.dx);
+        const uint32_t i = pl - j * g.nx;
+        const int k0 = blockIdx.y * KZ;
+        const double2 z = {0.0, 0.0};
+        int64_t c = pl + static_cast<int64_t>(k0) * g.nxy;
+        double2 below = k0 > 0 ? *reinterpret_cast<const double2 *>(x + c - g.nxy) : z;
+        double2 ctr = *reinterpret_cast<const double2 *>(x + c);
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            const int k = k0 + kk;
+            if (k >= g.nz)
+                break;
+            const double2 above = k + 1 < g.nz ? *reinterpret_cast<const double2 *>(x + c + g.nxy) : z;
+            const double w = i > 0 ? x[c - 1] : 0.0;
+            const double e = i + 2 < static_cast<uint32_t>(g.nx) ? x[c + 2] : 0.0;
+            const double2 s = j > 0 ? *reinterpret_cast<const double2 *>(x + c - g.nx) : z;
+            const double2 nn = j + 1 < static_cast<uint32_t>(g.ny) ? *reinterpret_cast<const double2 *>(x + c + g.nx) : z;
+            const double bx = __builtin_nontemporal_load(b + c), by = __builtin_nontemporal_load(b + c + 1);
+            const double yx = 6.0 * ctr.x - (((((w + ctr.y) + s.x) + nn.x) + below.x) + above.x);
+            const double yy = 6.0 * ctr.y - (((((ctr.x + e) + s.y) + nn.y) + below.y) + above.y);
+            const double rx = bx - yx, ry = by - yy;
+            acc += rx * rx;
+            acc += ry * ry;
+            if (write_p0) {
+                p0[c] = static_cast<TP>(scale * (p0_mode ? rx : minv * rx));
+                p0[c + 1] = static_cast<TP>(scale * (p0_mode ? ry : minv * ry));
+            }
+            below = ctr;
+            ctr = above;
+            c += g.nxy;
+        }
+    }
+    acc = wave_sum(acc);
+    if (threadIdx.x % kWave == 0)
+        part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < 1024 / kWave; ++w)
+            sum += part[w];
+        rpart[blockIdx.x + gridDim.x * blockIdx.y] = sum;
+    }
+}
+
 // One step of the Chebyshev recurrence fused with the operator apply
 // (Sec. 2, Definition), for column j of the basis:
 //   y = A p_j                                   -> AP[:, j]
@@ -449,6 +513,14 @@ hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
 {
     switch (a.op.kind) {
     case kOpPoisson:
+        if (a.res_p2) {
+            const dim3 grid(static_cast<uint32_t>((a.op.g.nxy / 2 + 1023) / 1024),
+                            static_cast<uint32_t>((a.op.g.nz + 7) / 8));
+            hipLaunchKernelGGL(k_residual_p2<TP>, grid, dim3(1024), 0, st, a.st, a.op.g,
+                               a.op.precond ? 1.0 / 6.0 : 1.0, static_cast<TP *>(a.P), a.rpart, a.p0_mode,
+                               write_p0 ? 1 : 0);
+            return hipGetLastError();
+        }
         return residual_for<OpPoisson7<double>, TP>(a, make_poisson<double>(a.op), st, write_p0);
     case kOpFaces:
         return residual_for<OpFaces7<double>, TP>(a, Ops<double>::faces(a.op), st, write_p0);

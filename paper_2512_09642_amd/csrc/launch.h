@@ -52,6 +52,7 @@ struct IterArgs {
     double *rpart = nullptr;  // residual-norm partial sums [nbr]
     int nbr = 0;
     int64_t rchunk = 0;
+    int res_p2 = 0;  // constant Poisson, nx even: residual in the basis kernel's shape (nbr = its blocks)
     double *gpart = nullptr;  // Gram partial sums [E][nbg]
     int nbg = 0;
     int64_t gchunk = 0;  // contiguous schedule: rows per block
