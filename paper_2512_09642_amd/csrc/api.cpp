@@ -353,25 +353,41 @@ GramSchedule default_gram_schedule(const IterArgs &it)
 }
 
 // Geometry of the operator-applying Gram kernel: 32 x 8 in-plane tiles, the
-// z-extent cut into ranges so that the (tile, range) items number about
-// `cap`; one block per item up to `cap` blocks (a block loops over several
-// items beyond that).  One partial slot per block.
+// full ones taken by one launch and the edge ones (partial in x or y) by a
+// second; the z-extent cut into even ranges so that the (tile, range) items
+// number about `cap`; one block per item up to the cap (a block loops over
+// several items beyond that).  One partial slot per block, the edge launch's
+// after the full launch's.
 void set_go_geometry(IterArgs &it, int cap)
 {
     const Grid3 &g = it.op.g;
     const int64_t tx = 32, ty = 8;
-    cap = std::max(1, std::min(cap, kMaxGramBlocks));
-    const int64_t tiles = ((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+    cap = std::max(2, std::min(cap, kMaxGramBlocks));
+    const int64_t tiles_x = (g.nx + tx - 1) / tx, tiles_y = (g.ny + ty - 1) / ty;
+    const int64_t tiles = tiles_x * tiles_y;
+    it.go_fx = int(g.nx / tx);
+    it.go_fy = int(g.ny / ty);
+    it.go_tiles_y = int(tiles_y);
+    it.go_rx = g.nx % tx != 0;
+    it.go_ry = g.ny % ty != 0;
     const int64_t nzb_t = std::max<int64_t>(1, std::min<int64_t>(g.nz, cap / tiles));
     const int64_t zr = round_up((g.nz + nzb_t - 1) / nzb_t, 2);  // even: the kernel runs z-steps in pairs
     const int64_t nzb = (g.nz + zr - 1) / zr;
-    it.go_tiles_x = int((g.nx + tx - 1) / tx);
-    it.go_tiles_y = int((g.ny + ty - 1) / ty);
     it.go_zr = int(zr);
     it.go_nzb = int(nzb);
-    it.go_items = int(tiles * nzb);
-    it.go_blocks = int(std::min<int64_t>(tiles * nzb, cap));
-    it.nbg = it.go_blocks;  // one partial slot per block
+    const int64_t tf = int64_t(it.go_fx) * it.go_fy;
+    const int64_t te = tiles - tf;  // = rx * tiles_y + ry * fx
+    it.go_tiles[0] = int(tf);
+    it.go_tiles[1] = int(te);
+    it.go_items[0] = int(tf * nzb);
+    it.go_items[1] = int(te * nzb);
+    // blocks in proportion to the items, within the cap in total
+    const int64_t items = tiles * nzb;
+    int64_t bf = std::min<int64_t>(tf * nzb, std::max<int64_t>(tf > 0, (int64_t(cap) * tf * nzb) / items));
+    int64_t be = std::min<int64_t>(te * nzb, std::max<int64_t>(te > 0, int64_t(cap) - bf));
+    it.go_blocks[0] = int(bf);
+    it.go_blocks[1] = int(be);
+    it.nbg = int(bf + be);
 }
 
 void set_gram_schedule(IterArgs &it, const GramSchedule &g)

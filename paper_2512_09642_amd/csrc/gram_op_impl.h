@@ -29,8 +29,6 @@
 //    stored-AP Gram, so results are bitwise reproducible from run to run.
 #pragma once
 
-#include <type_traits>
-
 #include "gram_impl.h"
 
 namespace sstep {
@@ -82,13 +80,22 @@ struct GoFaces {
     }
 };
 
-// Launch geometry: 32 x 8 tiles, nzb z-ranges of zr planes; items =
-// tiles_x * tiles_y * nzb, distributed over the blocks item = blockIdx.x +
-// k * gridDim.x.
+// Launch geometry.  The 32 x 8 tiles of a plane split into the full tiles
+// (tx < fx, ty < fy with fx = nx / 32, fy = ny / 8), taken by one launch,
+// and the edge tiles (the column strip tx = fx when nx % 32 != 0, then the
+// row strip ty = fy, tx < fx, when ny % 8 != 0), taken by another.  nzb
+// z-ranges of zr planes; items = tiles * nzb (tile fastest), distributed over
+// the logical blocks item = lb + k * blocks; partial slots slot0 + lb.
 struct GoGeom {
-    int32_t tiles_x, tiles_y;
+    int32_t fx, fy;        // full tiles per row / column
+    int32_t tiles_y;       // tile rows (full and edge)
+    int32_t rx, ry;        // 1 when the column / row edge strip exists
+    int32_t tiles;         // tiles of this launch
     int32_t zr, nzb;
     int32_t items;
+    int32_t blocks;  // logical blocks (partial slots)
+    int32_t per;     // logical blocks per XCD
+    int32_t slot0;   // first partial slot of this launch
 };
 
 // Load at a wave-uniform base plus a 32-bit per-lane byte offset, which maps
@@ -125,8 +132,19 @@ struct GoMfma<float> {
     __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <class Rule, typename T, int S, bool WD>
-__global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restrict__ st, Grid3 g, Rule rule,
+// FULL: the launch over the full tiles; without the edge-tile selects its
+// registers fit two waves per SIMD (constant Poisson, or FP32), which lets
+// the two blocks on a CU hide each other's memory waits.  Otherwise the edge
+// tiles, and FP64 face operators (their per-point coefficients would spill).
+template <class Rule, typename T, int S, bool WD, bool FULL>
+constexpr int go_waves_per_simd()
+{
+    return FULL && (sizeof(T) == 4 || !Rule::kHasCoef) ? 2 : 1;
+}
+
+template <class Rule, typename T, int S, bool WD, bool FULL>
+__global__ __launch_bounds__(kGoThreads, (go_waves_per_simd<Rule, T, S, WD, FULL>())) void k_gram_op(
+    const DevState *__restrict__ st, Grid3 g, Rule rule,
                                                         const T *__restrict__ P, int64_t ld,
                                                         const T *__restrict__ dvec, GoGeom geo,
                                                         double *__restrict__ gpart, int estride)
@@ -147,6 +165,12 @@ __global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restri
     __shared__ double red[kGoThreads / kWave][E];
     if (st->done)
         return;
+    // Logical block: each XCD takes a contiguous range, so the tiles next to
+    // a tile (same z-range, item numbers +-1 and +-tiles_x) run at the same
+    // time on the same XCD and its halo lines are hits in that XCD's L2.
+    const int lb = static_cast<int>(xcd_block(blockIdx.x, static_cast<uint32_t>(geo.per)));
+    if (lb >= geo.blocks)
+        return;
     const int t = threadIdx.x;
     const int lane = t % kWave, wv = t / kWave;
     // Thread t as a grid point (halo, diagonal and coefficient staging).
@@ -161,10 +185,18 @@ __global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restri
     typename M::acc_t gacc = {};  // this wave's share of G_raw
     T cacc = T(0);                // this lane's share of c'_n
 
-    const int tiles = geo.tiles_x * geo.tiles_y;
-    for (int item = blockIdx.x; item < geo.items; item += gridDim.x) {
+    const int tiles = geo.tiles;
+    for (int item = lb; item < geo.items; item += geo.blocks) {
         const int tile = item % tiles, zb = item / tiles;
-        const int i0 = (tile % geo.tiles_x) * txw, j0 = (tile / geo.tiles_x) * tyh;
+        int tx_, ty_;
+        if constexpr (FULL) {
+            tx_ = tile % geo.fx, ty_ = tile / geo.fx;
+        } else if (geo.rx && tile < geo.tiles_y) {
+            tx_ = geo.fx, ty_ = tile;
+        } else {
+            tx_ = tile - (geo.rx ? geo.tiles_y : 0), ty_ = geo.fy;
+        }
+        const int i0 = tx_ * txw, j0 = ty_ * tyh;
         const int z0 = zb * geo.zr;
         const int z1 = z0 + geo.zr < g.nz ? z0 + geo.zr : g.nz;
         // this thread's staging point
@@ -208,10 +240,9 @@ __global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restri
             hpos[m] = c < S ? c * CS + (hy + 1) * tx2 + hx + 1 : -1;
         }
 
-        // Both paths below run the same steps; FULL (tile inside the grid in
-        // x and y) drops the per-point validity selects.
-        auto run = [&](auto full_c) {
-            constexpr bool FULL = decltype(full_c)::value;
+        // FULL (tile inside the grid in x and y) drops the per-point validity
+        // selects.
+        auto run = [&]() {
             auto pv = [&](int kc) -> bool { return FULL || ((vmask >> kc) & 1u); };
             // Loads for z-step kk, issued one step ahead (before the products
             // of step kk - 1): the halo ring of plane kk, plane kk+1 at the
@@ -322,10 +353,7 @@ __global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restri
                 zstep(k + 1, qb, qa);
             }
         };
-        if (i0 + txw <= g.nx && j0 + tyh <= g.ny)
-            run(std::true_type{});
-        else
-            run(std::false_type{});
+        run();
     }
 
     // Block reduction in a fixed order: wave partials into LDS, then entry e
@@ -345,20 +373,38 @@ __global__ __launch_bounds__(kGoThreads) void k_gram_op(const DevState *__restri
     }
     __syncthreads();
     for (int e = t; e < E; e += kGoThreads)
-        gpart[static_cast<int64_t>(e) * estride + blockIdx.x] =
+        gpart[static_cast<int64_t>(e) * estride + geo.slot0 + lb] =
             ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
+template <class Rule, typename T, int S, bool WD>
+void gram_op_launch_rule(const IterArgs &a, const Rule &rule, const T *dv, hipStream_t st)
+{
+    const T *P = static_cast<const T *>(a.P);
+    int slot0 = 0;
+    for (int part = 0; part < 2; ++part) {
+        const int blocks = a.go_blocks[part];
+        if (blocks == 0)
+            continue;
+        const int per = (blocks + static_cast<int>(kNumXcd) - 1) / static_cast<int>(kNumXcd);
+        const GoGeom geo{a.go_fx, a.go_fy, a.go_tiles_y, a.go_rx,  a.go_ry,  a.go_tiles[part],
+                         a.go_zr, a.go_nzb, a.go_items[part], blocks, per, slot0};
+        const dim3 grid(static_cast<uint32_t>(per) * kNumXcd), block(kGoThreads);
+        if (part == 0)
+            hipLaunchKernelGGL((k_gram_op<Rule, T, S, WD, true>), grid, block, 0, st, a.st, a.op.g, rule, P, a.ld, dv,
+                               geo, a.gpart, a.nbg);
+        else
+            hipLaunchKernelGGL((k_gram_op<Rule, T, S, WD, false>), grid, block, 0, st, a.st, a.op.g, rule, P, a.ld,
+                               dv, geo, a.gpart, a.nbg);
+        slot0 += blocks;
+    }
 }
 
 template <typename T, int S>
 hipError_t gram_op_launch_s(const IterArgs &a, hipStream_t st)
 {
-    const GoGeom geo{a.go_tiles_x, a.go_tiles_y, a.go_zr, a.go_nzb, a.go_items};
-    const dim3 grid(static_cast<uint32_t>(a.go_blocks)), block(kGoThreads);
-    const T *P = static_cast<const T *>(a.P);
-    const int estride = a.nbg;
     if (a.op.kind == kOpPoisson) {
-        hipLaunchKernelGGL((k_gram_op<GoPoisson<T>, T, S, false>), grid, block, 0, st, a.st, a.op.g, GoPoisson<T>{},
-                           P, a.ld, static_cast<const T *>(nullptr), geo, a.gpart, estride);
+        gram_op_launch_rule<GoPoisson<T>, T, S, false>(a, GoPoisson<T>{}, static_cast<const T *>(nullptr), st);
     } else {
         GoFaces<T> rule;
         const T *dv;
@@ -370,11 +416,9 @@ hipError_t gram_op_launch_s(const IterArgs &a, hipStream_t st)
             dv = a.op.dvec32;
         }
         if (a.wdvec)
-            hipLaunchKernelGGL((k_gram_op<GoFaces<T>, T, S, true>), grid, block, 0, st, a.st, a.op.g, rule, P, a.ld,
-                               dv, geo, a.gpart, estride);
+            gram_op_launch_rule<GoFaces<T>, T, S, true>(a, rule, dv, st);
         else
-            hipLaunchKernelGGL((k_gram_op<GoFaces<T>, T, S, false>), grid, block, 0, st, a.st, a.op.g, rule, P, a.ld,
-                               dv, geo, a.gpart, estride);
+            gram_op_launch_rule<GoFaces<T>, T, S, false>(a, rule, dv, st);
     }
     return hipGetLastError();
 }

@@ -66,9 +66,13 @@ struct IterArgs {
     // Gram kernel that applies the stencil operator itself (AP not stored;
     // the basis steps skip the AP write and the last product):
     int gram_op = 0;
-    int go_tiles_x = 0, go_tiles_y = 0;  // 32 x 8 tiles per plane
+    int go_fx = 0, go_fy = 0;           // full 32 x 8 tiles per row / column of tiles
+    int go_tiles_y = 0;                 // tile rows, full and edge
+    int go_rx = 0, go_ry = 0;           // column / row strip of edge tiles present
     int go_zr = 0, go_nzb = 0;          // planes per z-range, z-ranges
-    int go_items = 0, go_blocks = 0;    // work items (tile, z-range) and blocks
+    int go_tiles[2] = {0, 0};           // tiles of the full-tile and edge-tile launches
+    int go_items[2] = {0, 0};           // work items (tile, z-range) of each launch
+    int go_blocks[2] = {0, 0};          // blocks (= partial slots) of each launch
 };
 
 // Debug block layout written by the FGS kernel.
