@@ -392,7 +392,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": measured_traffic(args.N, args.s, args.nu),
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_unit": "HBM bytes per launch (rocprofv3 read requests by size + WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": per_launch,
             "avg_launch_ms": kt["basis"],
         }
@@ -435,9 +435,10 @@ def sweep(lib, torch, args):
                         ts.append(1e3 * (time.perf_counter() - t0))
                     w = 8 if prec == "fp64" else 4
                     t = float(np.median(ts))
+                    bpo = stencil_bytes_per_outer(pr.n, s, w, sv.gram_applies_operator)
                     row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "rel_res": st.rel_res,
-                                 "gbps_effective": stencil_bytes_per_outer(pr.n, s, w) * st.outer_iters / (t * 1e-3)
-                                 / 1e9}
+                                 "gram": "apply_op" if sv.gram_applies_operator else "stored_ap",
+                                 "gbps_effective": bpo * st.outer_iters / (t * 1e-3) / 1e9}
             row["fp32ir_speedup"] = row["fp64"]["time_ms"] / row["fp32ir"]["time_ms"]
             rows.append(row)
             log(f"s={s} nu={nu}: {row}")
