@@ -339,7 +339,6 @@ sstep_status start_state(sstep_ctx *ctx, const double *b, double *x, double tol,
 struct GramSchedule {
     int nbg;       // stored-AP kernel: partial blocks; operator-applying kernel: block cap
     int64_t slab;  // stored-AP kernel: 0 contiguous chunks, > 0 strided slabs of this many rows
-    int txl;       // operator-applying kernel: tile width log2 (-1 = least padding)
     double us;     // measured time per launch (0 = not measured)
 };
 
@@ -348,8 +347,8 @@ GramSchedule default_gram_schedule(const IterArgs &it)
     // Measured on MI355X at 224^3, s = 16: FP64 prefers one contiguous chunk
     // per CU, FP32 prefers grid-strided 2048-row slabs.
     if (it.gram_op)
-        return GramSchedule{1024, 0, -1, 0.0};
-    return it.fp32 ? GramSchedule{256, 2048, -1, 0.0} : GramSchedule{256, 0, -1, 0.0};
+        return GramSchedule{1024, 0, 0.0};
+    return it.fp32 ? GramSchedule{256, 2048, 0.0} : GramSchedule{256, 0, 0.0};
 }
 
 // Geometry of the operator-applying Gram kernel: 32 x 8 in-plane tiles, the
@@ -427,7 +426,7 @@ std::string tune_key(const IterArgs &it)
 }
 
 // The cache is a JSON object written one entry per line:
-//   "key": {"nbg": 256, "slab": 0, "txl": -1, "us": 507.3},
+//   "key": {"nbg": 256, "slab": 0, "us": 507.3},
 std::map<std::string, GramSchedule> read_tune_cache(const std::string &path)
 {
     std::map<std::string, GramSchedule> m;
@@ -437,10 +436,10 @@ std::map<std::string, GramSchedule> read_tune_cache(const std::string &path)
         const size_t a = line.find('"'), b = line.find("\": {");
         if (a == std::string::npos || b == std::string::npos || b <= a)
             continue;
-        GramSchedule g{0, 0, -1, 0.0};
+        GramSchedule g{0, 0, 0.0};
         long long slab = 0;
-        if (std::sscanf(line.c_str() + b, "\": {\"nbg\": %d, \"slab\": %lld, \"txl\": %d, \"us\": %lf", &g.nbg,
-                        &slab, &g.txl, &g.us) == 4) {
+        if (std::sscanf(line.c_str() + b, "\": {\"nbg\": %d, \"slab\": %lld, \"us\": %lf", &g.nbg, &slab, &g.us) ==
+            3) {
             g.slab = slab;
             m[line.substr(a + 1, b - a - 1)] = g;
         }
@@ -459,7 +458,7 @@ void write_tune_cache(const std::string &path, const std::map<std::string, GramS
         size_t q = 0;
         for (const auto &kv : m) {
             f << "  \"" << kv.first << "\": {\"nbg\": " << kv.second.nbg << ", \"slab\": " << kv.second.slab
-              << ", \"txl\": " << kv.second.txl << ", \"us\": " << kv.second.us << "}"
+              << ", \"us\": " << kv.second.us << "}"
               << (++q < m.size() ? "," : "") << "\n";
         }
         f << "}\n";
@@ -489,13 +488,13 @@ sstep_status tune_gram(sstep_ctx *ctx)
         // at most 1024 partial slots: the FGS kernel's reduction of the
         // partials grows with their number and is not part of this timing
         for (int cap : {256, 384, 512, 768, 1024})
-            cand.push_back({cap, 0, -1, 0.0});
+            cand.push_back({cap, 0, 0.0});
     } else {
         for (int nbg : {256, 384, 512, 1024, 2048})
-            cand.push_back({nbg, 0, -1, 0.0});
+            cand.push_back({nbg, 0, 0.0});
         for (int64_t slab : {int64_t(1024), int64_t(2048), int64_t(4096)})
             for (int nbg : {256, 512, 1024, 2048})
-                cand.push_back({nbg, slab, -1, 0.0});
+                cand.push_back({nbg, slab, 0.0});
     }
     GramSchedule best = default_gram_schedule(it);
     best.us = 1e30;
@@ -1104,7 +1103,7 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     }
     OKCHK(batched_tiles(ctx, best_chunk, best_factor, true));
     if (!path.empty()) {
-        cache[key.str()] = GramSchedule{best_factor, best_chunk, -1, 1e3 * best / 2};
+        cache[key.str()] = GramSchedule{best_factor, best_chunk, 1e3 * best / 2};
         write_tune_cache(path, cache);
     }
     return SSTEP_OK;

@@ -11,22 +11,22 @@
 //    planes of the range.  Planes z-1, z and z+1 of every column of the
 //    thread's point are kept in registers, so the interior of each plane of P
 //    is read from HBM once per range (plus two planes of priming).
-//  * Each z-step is branch-free: at its start every thread issues the loads
-//    of plane z+1 of its point for all columns and its share of the tile's
-//    halo ring of plane z (the 2(TX + TY) in-plane neighbours outside the
-//    tile, zero outside the grid); addresses are clamped in range and unused
-//    values selected away.  Then (1) the plane-z interior and halo ring go to a
-//    padded (TX + 2) x (TY + 2) LDS tile per column; (2) every thread forms
-//    y_j = (A p_j)(z) from the LDS tile and its registers and writes it to LDS;
-//    (3) each wave accumulates its Gram group (the block decomposition of
-//    gram_impl.h) over the 256 points from LDS.
-//  * s <= 8 has a single group: every wave takes it over its own 64 points
-//    and stores its own partial (four slots per block).  9 <= s <= 16 has four
-//    groups, one per wave, each over all 256 points.
-//  * The per-wave body is a template on the group, entered once through a
-//    wave-uniform branch; every wave executes the same number of barriers.
-//  * Partials are reduced in a fixed order by the FGS kernel, as for the
-//    stored-AP Gram, so results are bitwise reproducible from run to run.
+//  * Lane l of a wave owns column l % 16 at 16 points of the tile and keeps
+//    planes z-1, z (and z+1, loaded one step ahead into alternating buffers)
+//    of those points in registers.  Each z-step: (1) plane z of every column
+//    (lane points plus the tile's halo ring, the 2(TX + TY) in-plane
+//    neighbours outside the tile, zero outside the grid) goes into a padded
+//    (TX + 2) x (TY + 2) LDS tile; (2) each lane forms (A p_n)(z) at its points
+//    from the tile and its registers and feeds p_n and (A p_n) to the 16 x 16
+//    x 4 matrix-core step, which accumulates the wave's P^T (A P) over its 64
+//    points; c'_n = p_n^T W accumulates with vector FMAs.  No branch surrounds
+//    the loads, so the compiler's waits for them are exact.
+//  * Full tiles and edge tiles go to two launches; the full-tile kernel has no
+//    per-point selects and fits two waves per SIMD.  Blocks take tiles in an
+//    XCD-contiguous order, so neighbouring tiles share an L2.
+//  * The four wave partials are summed in a fixed order in LDS, one slot per
+//    block, and the slots by the FGS kernel, so results are bitwise
+//    reproducible from run to run.
 #pragma once
 
 #include "gram_impl.h"
@@ -39,7 +39,6 @@ constexpr int kGoTx = 1 << kGoTxl;                 // 32
 constexpr int kGoTy = kGoThreads >> kGoTxl;        // 8
 constexpr int kGoTx2 = kGoTx + 2;                  // padded row pitch
 constexpr int kGoPitch = kGoTx2 * (kGoTy + 2);     // padded tile: 340 points
-constexpr int kGoRing = 2 * (kGoTx + kGoTy);       // halo ring: 80 points
 
 // 7-point constant Poisson: (A p)_c = 6 p_c - sum of the six neighbours, in
 // the same order of operations as the basis kernels.
@@ -151,10 +150,9 @@ __global__ __launch_bounds__(kGoThreads, (go_waves_per_simd<Rule, T, S, WD, FULL
 {
     static_assert(S >= 1 && S <= kGoMaxS, "the 16 x 16 matrix-core tile holds at most 16 columns");
     constexpr int E = S * (S + 1) / 2 + S;                             // Gram entries + right-hand side
-    constexpr int NH = (kGoRing * S + kGoThreads - 1) / kGoThreads;  // halo entries per thread
     constexpr int KC = kWave / 4;                                      // points per lane per plane
     constexpr uint32_t W = sizeof(T);
-    constexpr int txw = kGoTx, tyh = kGoTy, tx2 = kGoTx2, ring = kGoRing;
+    constexpr int txw = kGoTx, tyh = kGoTy, tx2 = kGoTx2;
     constexpr int CS = kGoPitch + 1;  // LDS stride of a column's padded tile (odd: spreads the banks)
     constexpr bool HAS_COEF = Rule::kHasCoef;
     using M = GoMfma<T>;
