@@ -804,6 +804,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     }
     OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
     OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * kMaxGramBlocks));
+    OKCHK(dalloc(ctx, &it.gsum, size_t(gram_entries(s)) + 1));
     OKCHK(dalloc(ctx, &it.st, 1));
     OKCHK(dalloc(ctx, &it.dbg, size_t(dbg_size(s))));
     it.hist_cap = o.record_history ? o.max_outer + 1 : 0;

@@ -157,14 +157,47 @@ __device__ __forceinline__ int fgs_wave(DevState *__restrict__ st, const double 
     return 0;
 }
 
-constexpr int kFgsThreads = 1024;
+constexpr int kFgsThreads = 256;
+constexpr int kSumThreads = 256;
 
-// One outer iteration's Gram solve for a single system: the 1024 threads sum
-// the per-block partials of ||r||^2 and of the E Gram entries in a fixed order
-// (each wave owns whole entries), then wave 0 runs fgs_wave.
+// Sum of the block partials of one Gram entry (blocks e < E) or of the
+// residual norm (block E), in a fixed order: thread t takes partials t,
+// t + 256, ..., the waves combine by butterfly and the four wave sums in order.
+// One block per entry keeps every partial load of the reduction in flight at
+// once across the chip.
 template <int s>
-__global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, const double *__restrict__ rpart,
-                                                     int nbr, const double *__restrict__ gpart, int nbg, int nu,
+__global__ __launch_bounds__(kSumThreads) void k_partial_sums(const DevState *__restrict__ st,
+                                                              const double *__restrict__ gpart, int nbg,
+                                                              const double *__restrict__ rpart, int nbr,
+                                                              double *__restrict__ sums)
+{
+    constexpr int E = s * (s + 1) / 2 + s;
+    __shared__ double part[kSumThreads / kWave];
+    if (st->done)
+        return;
+    const int e = blockIdx.x;
+    const double *src = e < E ? gpart + static_cast<int64_t>(e) * nbg : rpart;
+    const int cnt = e < E ? nbg : nbr;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < cnt; q += kSumThreads)
+        acc += src[q];
+    acc = wave_sum(acc);
+    if (threadIdx.x % kWave == 0)
+        part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int w = 0; w < kSumThreads / kWave; ++w)
+            v += part[w];
+        sums[e] = v;
+    }
+}
+
+// One outer iteration's Gram solve for a single system: the block loads the
+// totals of the E Gram entries and of ||r||^2 (k_partial_sums) into LDS, then
+// wave 0 runs fgs_wave.
+template <int s>
+__global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, const double *__restrict__ sums, int nu,
                                                      double cscale, int fp32, double inv_sqrt_n,
                                                      double *__restrict__ dbg, double *__restrict__ hist,
                                                      int hist_cap)
@@ -174,38 +207,8 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
     __shared__ double sg[s * (s + 1) / 2 + s + 1];
     constexpr int E = s * (s + 1) / 2 + s;
     const int wave = threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    constexpr int nw = kFgsThreads / kWave;
-    // Wave w sums entries t = w, w + nw, ... (t = E is the residual norm):
-    // one pass over the partial index with one accumulator per entry, so a
-    // lane has one independent load per entry in flight; the summation
-    // order of each entry is fixed by its count alone.
-    constexpr int EPW = (E + 1 + nw - 1) / nw;
-    double acc[EPW];
-#pragma unroll
-    for (int m = 0; m < EPW; ++m)
-        acc[m] = 0.0;
-    const int cmax = nbg > nbr ? nbg : nbr;
-    for (int q = lane; q < cmax; q += kWave) {
-#pragma unroll
-        for (int m = 0; m < EPW; ++m) {
-            // no branch around the loads (clamped index, unused values
-            // selected away), so the compiler keeps them all in flight
-            const int t = wave + m * nw;
-            const int tc = t < E ? t : E;
-            const double *src = tc < E ? gpart + static_cast<int64_t>(tc) * nbg : rpart;
-            const int cnt = tc < E ? nbg : nbr;
-            const double v = src[q < cnt ? q : cnt - 1];
-            acc[m] += t <= E && q < cnt ? v : 0.0;
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < EPW; ++m) {
-        const int t = wave + m * nw;
-        const double v = wave_sum(acc[m]);
-        if (t <= E && lane == 0)
-            sg[t] = v;
-    }
+    for (int t = threadIdx.x; t <= E; t += kFgsThreads)
+        sg[t] = sums[t];
     __syncthreads();
     if (wave != 0)
         return;
@@ -215,8 +218,11 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
 template <int s>
 hipError_t fgs_launch_s(const IterArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fgs<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.rpart, a.nbr, a.gpart, a.nbg, a.nu,
-                       a.cscale, a.fp32, a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap);
+    constexpr int E = s * (s + 1) / 2 + s;
+    hipLaunchKernelGGL(k_partial_sums<s>, dim3(E + 1), dim3(kSumThreads), 0, st, a.st, a.gpart, a.nbg, a.rpart, a.nbr,
+                       a.gsum);
+    hipLaunchKernelGGL(k_fgs<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.gsum, a.nu, a.cscale, a.fp32,
+                       a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap);
     return hipGetLastError();
 }
 

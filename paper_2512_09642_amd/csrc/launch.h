@@ -54,6 +54,7 @@ struct IterArgs {
     int64_t rchunk = 0;
     int res_p2 = 0;  // constant Poisson, nx even: residual in the basis kernel's shape (nbr = its blocks)
     double *gpart = nullptr;  // Gram partial sums [E][nbg]
+    double *gsum = nullptr;   // totals: the E Gram entries, then ||r||^2 (E + 1 doubles)
     int nbg = 0;
     int64_t gchunk = 0;  // contiguous schedule: rows per block
     int64_t gslab = 0;   // strided schedule: rows per slab (0 = contiguous schedule)

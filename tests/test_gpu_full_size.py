@@ -1,0 +1,82 @@
+"""The headline workload at its full size: 224^3 Poisson (11,239,424 unknowns),
+s = 16, nu = 25, matrix-free stencil, FP64, with the solver built exactly as
+the benchmark builds it (default options, so the Gram kernel that applies the
+operator itself, the autotuned schedule and the graph-chunked solve).
+
+Two checks against the oracle:
+- lockstep: two outer iterations from the same x_k, each compared entry by
+  entry with the oracle's outer iteration (a few seconds each on the host),
+  G, ctil, atil and x_{k+1} within 1e-10 relative, ||r_k|| within 1e-12;
+- free-running: the solve stops within 5% (at least one) of the oracle's
+  outer-iteration count for the same problem (tests/golden/c2_oracle.json,
+  written by tests/golden/make_golden.py --c2 from the oracle alone), its
+  first relative residuals follow the oracle's history, and the true relative
+  residual ||b - A x|| / ||b||, recomputed by the oracle, is <= 1e-8.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+N, S, NU = 224, 16, 25
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle.json")
+
+
+def t64(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    pr = gen.config2(0, N=N, s=S, nu=NU)
+    A = oracle.assemble_stencil7(N, N, N)
+    b = oracle.spmv(A, pr.xstar)
+    return pr, A, b
+
+
+def test_full_size_lockstep_matches_oracle(hip, c2):
+    pr, A, b = c2
+    bt = t64(b)
+    x = np.zeros(pr.n)
+    with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax) as sv:
+        assert sv.gram_applies_operator
+        for k in range(2):
+            g = sv.step(bt, t64(x))
+            o = oracle.step(A, b, x, S, NU, pr.lmin, pr.lmax)
+            assert o["status"] == 0
+            assert abs(g["rnorm"] - o["rnorm"]) <= 1e-12 * o["rnorm"], k
+            for key in ("G", "ctil", "atil"):
+                assert rel(g[key], o[key]) <= 1e-10, (k, key, rel(g[key], o[key]))
+            x = host(g["x"])
+            assert rel(x, o["x"]) <= 1e-10, k
+
+
+def test_full_size_solve_follows_oracle(hip, c2):
+    pr, A, b = c2
+    with open(GOLDEN) as f:
+        ref = json.load(f)
+    assert ref["status"] == 0
+    with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax, record_history=True) as sv:
+        assert sv.gram_applies_operator
+        x, st = sv.solve(t64(b), None, 1e-8, history=True)
+    assert st.status == 0
+    assert abs(st.outer_iters - ref["iters"]) <= max(1, int(0.05 * ref["iters"])), (st.outer_iters, ref["iters"])
+    hist = np.asarray(ref["hist_relres"])
+    k = min(6, st.outer_iters + 1, hist.size)
+    assert np.all(np.abs(st.hist_relres[:k] - hist[:k]) <= 1e-8 * hist[:k]), (st.hist_relres[:k], hist[:k])
+    true_rel = np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b)
+    assert true_rel <= 1e-8
+    assert abs(st.rel_res - true_rel) <= 1e-12
