@@ -88,10 +88,10 @@ typedef struct {
 
 /* Gram formation.  STORED_AP: the basis steps write A p_j to an n x s array
  * AP and the Gram kernel reads P and AP.  APPLY_OP (stencil operators,
- * s <= 16): the Gram kernel forms A p_j from P itself, so AP is neither
- * written nor allocated and the basis makes s - 1 launches per outer
- * iteration; asking for it with a CSR operator or s > 16 gives
- * SSTEP_E_UNSUPPORTED. */
+ * s <= 16, a basis column under 4 GiB, i.e. n < 2^29 in FP64): the Gram
+ * kernel forms A p_j from P itself, so AP is neither written nor allocated
+ * and the basis makes s - 1 launches per outer iteration; asking for it
+ * otherwise gives SSTEP_E_UNSUPPORTED. */
 typedef enum { SSTEP_GRAM_AUTO = 0, SSTEP_GRAM_STORED_AP = 1, SSTEP_GRAM_APPLY_OP = 2 } sstep_gram_kind;
 
 typedef struct {
@@ -107,7 +107,7 @@ typedef struct {
                                unknowns use the defaults; 0 = defaults */
     int32_t gram;           /* sstep_gram_kind: how G = P^T A P (Sec. 2) is formed.  SSTEP_GRAM_AUTO
                                (default) = SSTEP_GRAM_APPLY_OP for FP64 stencil operators with
-                               s <= 16, SSTEP_GRAM_STORED_AP otherwise */
+                               s <= 16 and n < 2^29, SSTEP_GRAM_STORED_AP otherwise */
     void *stream;           /* hipStream_t the caller's data is ordered on (NULL = default) */
 } sstep_options;
 

@@ -716,7 +716,8 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
                            uint64_t(round_up(n, kPad)) * wbytes < (uint64_t(1) << 32);
         if (o.gram == SSTEP_GRAM_APPLY_OP && !op_ok)
             return fail(ctx, SSTEP_E_UNSUPPORTED,
-                        "the operator-applying Gram kernel needs a stencil operator and s <= 16");
+                        "the operator-applying Gram kernel needs a stencil operator, s <= 16 and columns under "
+                        "4 GiB");
         gram_op = o.gram == SSTEP_GRAM_APPLY_OP || (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
     }
 
