@@ -19,8 +19,11 @@
 //    (TX + 2) x (TY + 2) LDS tile; (2) each lane forms (A p_n)(z) at its points
 //    from the tile and its registers and feeds p_n and (A p_n) to the 16 x 16
 //    x 4 matrix-core step, which accumulates the wave's P^T (A P) over its 64
-//    points; c'_n = p_n^T W accumulates with vector FMAs.  No branch surrounds
-//    the loads, so the compiler's waits for them are exact.
+//    points; c'_n = p_n^T W accumulates with vector FMAs.  A lane's points
+//    come in vertical pairs, so one y-neighbour is in its own registers, and
+//    p_0 at a point comes from the column-0 lane of the same row by a DPP
+//    broadcast: three LDS reads per point.  No branch surrounds the loads, so
+//    the compiler's waits for them are exact.
 //  * Full tiles and edge tiles go to two launches; the full-tile kernel has no
 //    per-point selects and fits two waves per SIMD.  Blocks take tiles in an
 //    XCD-contiguous order, so neighbouring tiles share an L2.
@@ -104,6 +107,24 @@ template <typename T>
 __device__ __forceinline__ T go_ld(const T *base, uint32_t byte_off)
 {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// Value of lane 16 (l / 16) (the first lane of l's row of 16), by a DPP row
+// broadcast: two 32-bit moves for a double, no LDS traffic.
+constexpr int kDppRowNewBcast0 = 0x150;  // DPP control: row_newbcast:0
+__device__ __forceinline__ float go_row_bcast0(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppRowNewBcast0, 0xf, 0xf,
+                                                              true));
+}
+__device__ __forceinline__ double go_row_bcast0(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(u)), kDppRowNewBcast0, 0xf, 0xf, true));
+    const uint32_t hi = static_cast<uint32_t>(
+        __builtin_amdgcn_mov_dpp(static_cast<int>(static_cast<uint32_t>(u >> 32)), kDppRowNewBcast0, 0xf, 0xf, true));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 // 16 x 16 x 4 matrix-core step, D += A B: lane l supplies A[l % 16][l / 16]
@@ -317,18 +338,27 @@ __global__ __launch_bounds__(kGoThreads, (go_waves_per_simd<Rule, T, S, WD, FULL
                     if constexpr (HAS_COEF)
                         fk = Ct[64 * wv + 4 * kc + gq];
                     const T zpv = pv(kc) ? zq[kc] : T(0);  // zero outside the grid
-                    const T y = Rule::y(fk, zc[kc], L[-1], L[1], L[-tx2], L[tx2], zm[kc], zpv);
-                    T w = Pt[pp];  // p_0 at the point
+                    // the lane's points kc and kc + 8 are vertical neighbours:
+                    // one of the two y-neighbours comes from the registers
+                    const T ys = kc >= 8 ? zc[kc - 8] : L[-tx2];
+                    const T yn = kc < 8 ? zc[kc + 8] : L[tx2];
+                    const T y = Rule::y(fk, zc[kc], L[-1], L[1], ys, yn, zm[kc], zpv);
+                    // p_0 at the point: held by the column-0 lane of this row
+                    T w = go_row_bcast0(zc[kc]);
                     if constexpr (WD)
                         w *= Dt[64 * wv + 4 * kc + gq];
                     const bool v = ncol && pv(kc);
                     const T a = (S == 16 && FULL) || v ? zc[kc] : T(0);
                     gacc = M::step(a, (S == 16 && FULL) || v ? y : T(0), gacc);
                     cacc += a * w;
-                    zm[kc] = zc[kc];
-                    zc[kc] = zpv;
                     if ((kc & 3) == 3)
                         __builtin_amdgcn_sched_barrier(0);  // bounds the LDS reads in flight (registers)
+                }
+                // planes move down once every point has used its neighbours
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc) {
+                    zm[kc] = zc[kc];
+                    zc[kc] = pv(kc) ? zq[kc] : T(0);
                 }
                 }
                 __syncthreads();
