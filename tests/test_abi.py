@@ -145,3 +145,11 @@ def test_setup_rejects_unavailable_gram_kinds(native):
     # 820^3 doubles per column exceed the kernel's 32-bit byte offsets
     st, ctx = setup(_poisson(native, 820, 820, 820), 4, apply_op)
     assert st == 7 and not ctx.value
+
+
+def test_missing_library_fails_loudly(native, monkeypatch, tmp_path):
+    """Without the built library the binding raises; there is no fallback."""
+    monkeypatch.setattr(native, "_lib", None)
+    monkeypatch.setattr(native, "LIB_PATH", str(tmp_path / "libsstep.so"))
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        native.load()
