@@ -152,19 +152,38 @@ __global__ __launch_bounds__(kBlock) void k_bbasis(const BGlob *__restrict__ gl,
         PointStencil<T, FACES> op;
         op.init(S, c, precond, kx, ky, kz);
         const T theta = static_cast<T>(S.theta), sigma = static_cast<T>(S.sigma);
-        for (int r = 0; r < nrhs; ++r) {
-            if (pairs[S.pair0 + r].done)
-                continue;
-            const int64_t col = S.pofs + (static_cast<int64_t>(j) * nrhs + r) * S.ld;
-            const int64_t step = static_cast<int64_t>(nrhs) * S.ld;
-            T pc;
-            const T y = op.apply(P + col, pc);
-            __builtin_nontemporal_store(y, AP + col + c);
-            if constexpr (STEP == 0) {
-                P[col + step + c] = theta * (op.dinv * y - sigma * pc);
-            } else if constexpr (STEP == 1) {
-                const T two_theta = T(2) * theta;
-                P[col + step + c] = two_theta * (op.dinv * y - sigma * pc) - P[col - step + c];
+        const int64_t step = static_cast<int64_t>(nrhs) * S.ld;
+        // Right-hand sides in groups of kRg: every load of a group is issued
+        // before its stores (P is read and written through one pointer, so
+        // the compiler keeps loads after earlier stores).
+        constexpr int kRg = 4;
+        for (int r0 = 0; r0 < nrhs; r0 += kRg) {
+            T y[kRg], pc[kRg], pp[kRg];
+            bool act[kRg];
+#pragma unroll
+            for (int u = 0; u < kRg; ++u) {
+                const int r = r0 + u;
+                act[u] = r < nrhs && !pairs[S.pair0 + r].done;
+                y[u] = pc[u] = pp[u] = T(0);
+                if (act[u]) {
+                    const int64_t col = S.pofs + (static_cast<int64_t>(j) * nrhs + r) * S.ld;
+                    y[u] = op.apply(P + col, pc[u]);
+                    if constexpr (STEP == 1)
+                        pp[u] = P[col - step + c];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRg; ++u) {
+                if (!act[u])
+                    continue;
+                const int64_t col = S.pofs + (static_cast<int64_t>(j) * nrhs + r0 + u) * S.ld;
+                __builtin_nontemporal_store(y[u], AP + col + c);
+                if constexpr (STEP == 0) {
+                    P[col + step + c] = theta * (op.dinv * y[u] - sigma * pc[u]);
+                } else if constexpr (STEP == 1) {
+                    const T two_theta = T(2) * theta;
+                    P[col + step + c] = two_theta * (op.dinv * y[u] - sigma * pc[u]) - pp[u];
+                }
             }
         }
     }
@@ -192,8 +211,20 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(const BGlob *__restrict__ gl
             const T *Pr = P + S.pofs + static_cast<int64_t>(r) * S.ld;
             const int64_t step = static_cast<int64_t>(nrhs) * S.ld;
             for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+                // P is read once: non-temporal loads, eight columns in flight
+                // at a time, summed in column order
                 double acc = 0.0;
-                for (int i = 0; i < s; ++i)  // P is read once: non-temporal loads
+                int i = 0;
+                for (; i + 8 <= s; i += 8) {
+                    T v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        v[u] = __builtin_nontemporal_load(Pr + (i + u) * step + c);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        acc += static_cast<double>(v[u]) * ps.alpha[i + u];
+                }
+                for (; i < s; ++i)
                     acc += static_cast<double>(__builtin_nontemporal_load(Pr + i * step + c)) * ps.alpha[i];
                 x[c] += acc;
             }
