@@ -12,6 +12,10 @@ Two checks against the oracle:
   written by tests/golden/make_golden.py --c2 from the oracle alone), its
   first relative residuals follow the oracle's history, and the true relative
   residual ||b - A x|| / ||b||, recomputed by the oracle, is <= 1e-8.
+
+The same problem in FP32+IR, and the 128^3 face-coefficient workload of the
+differentiable solve (forward, adjoint, gradient scatter), are checked at
+their full sizes too.
 """
 import json
 import os
@@ -80,3 +84,49 @@ def test_full_size_solve_follows_oracle(hip, c2):
     true_rel = np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b)
     assert true_rel <= 1e-8
     assert abs(st.rel_res - true_rel) <= 1e-12
+
+
+def test_full_size_fp32ir_reaches_tolerance(hip, c2):
+    """The mixed-precision leg of the benchmark at full size: FP64 residual
+    and update around an FP32 basis and Gram; the true relative residual,
+    recomputed by the oracle in FP64, reaches 1e-8."""
+    pr, A, b = c2
+    with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax, precision="fp32ir") as sv:
+        x, st = sv.solve(t64(b), None, 1e-8)
+    assert st.status == 0
+    true_rel = np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b)
+    assert true_rel <= 1e-8
+
+
+def test_full_size_faces_forward_and_adjoint(hip):
+    """The differentiable workload at its full size (128^3 log-normal face
+    coefficients, sigma 0.5, s = 16, nu = 25): two lockstep outer iterations
+    against the oracle (1e-10), the forward and the adjoint solve to a true
+    relative residual <= 1e-8 (recomputed by the oracle), and the face
+    gradient scatter bit-identical to the oracle's."""
+    pr = gen.config5(0)
+    nx, ny, nz = pr.dims
+    A = oracle.problem_csr(pr)
+    b = pr.rhs[0]
+    x = np.zeros(pr.n)
+    with hip.Solver(hip.Operator.stencil(nx, ny, nz, pr.kx, pr.ky, pr.kz), pr.s, pr.nu, pr.lmin, pr.lmax) as sv:
+        bt = t64(b)
+        for k in range(2):
+            g = sv.step(bt, t64(x))
+            o = oracle.step(A, b, x, pr.s, pr.nu, pr.lmin, pr.lmax)
+            assert o["status"] == 0
+            for key in ("G", "ctil", "atil"):
+                assert rel(g[key], o[key]) <= 1e-10, (k, key, rel(g[key], o[key]))
+            x = host(g["x"])
+            assert rel(x, o["x"]) <= 1e-10, k
+        xs, st = sv.solve(bt, None, 1e-8)
+        assert st.status == 0
+        xh = host(xs)
+        assert np.linalg.norm(b - oracle.spmv(A, xh)) / np.linalg.norm(b) <= 1e-8
+        gvec = xh - pr.xtarget
+        lam, sta = sv.solve_adjoint(t64(gvec), None, 1e-8)
+        assert sta.status == 0
+        lh = host(lam)
+        assert np.linalg.norm(gvec - oracle.spmv(A, lh)) / np.linalg.norm(gvec) <= 1e-8
+        dA = host(sv.grad_operator(lam, xs))
+    assert np.array_equal(dA, np.concatenate(oracle.grad_faces(nx, ny, nz, lh, xh)))
