@@ -14,8 +14,9 @@ Two checks against the oracle:
   residual ||b - A x|| / ||b||, recomputed by the oracle, is <= 1e-8.
 
 The same problem in FP32+IR, the 128^3 face-coefficient workload of the
-differentiable solve (forward, adjoint, gradient scatter) and the batched
-workload (64 systems x 8 right-hand sides) are checked at their full sizes too.
+differentiable solve (forward, adjoint, gradient scatter), the batched
+workload (64 systems x 8 right-hand sides) and the CSR form of the 224^3
+problem are checked at their full sizes too.
 """
 import json
 import os
@@ -158,3 +159,22 @@ def test_full_size_batched_pairs_reach_tolerance(hip, precision):
             assert abs(pst.rel_res - true_rel) <= 1e-10, (q, r, pst.rel_res, true_rel)
             worst = max(worst, true_rel)
     assert worst > 0.0
+
+
+def test_full_size_csr_matches_oracle(hip, c2):
+    """The headline problem given as a CSR matrix (the benchmark's CSR leg):
+    one lockstep outer iteration against the oracle (1e-10) and the solve to a
+    true relative residual <= 1e-8."""
+    pr, A, b = c2
+    rp, ci, v = gen.poisson3d_csr(N, N, N)
+    with hip.Solver(hip.Operator.csr(rp, ci, v), S, NU, pr.lmin, pr.lmax) as sv:
+        assert not sv.gram_applies_operator
+        bt = t64(b)
+        g = sv.step(bt, t64(np.zeros(pr.n)))
+        o = oracle.step(A, b, np.zeros(pr.n), S, NU, pr.lmin, pr.lmax)
+        for key in ("G", "ctil", "atil"):
+            assert rel(g[key], o[key]) <= 1e-10, (key, rel(g[key], o[key]))
+        assert rel(host(g["x"]), o["x"]) <= 1e-10
+        x, st = sv.solve(bt, None, 1e-8)
+    assert st.status == 0
+    assert np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b) <= 1e-8
