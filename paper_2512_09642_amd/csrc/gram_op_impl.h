@@ -28,8 +28,9 @@
 //    per-point selects and fits two waves per SIMD.  Blocks take tiles in an
 //    XCD-contiguous order, so neighbouring tiles share an L2.
 //  * The four wave partials are summed in a fixed order in LDS, one slot per
-//    block, and the slots by the FGS kernel, so results are bitwise
-//    reproducible from run to run.
+//    block, and the slots in a fixed order by the partial-sum kernel that
+//    precedes the FGS solve, so results are bitwise reproducible from run to
+//    run.
 #pragma once
 
 #include "gram_impl.h"
