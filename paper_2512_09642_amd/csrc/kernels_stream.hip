@@ -172,28 +172,36 @@ __global__ __launch_bounds__(kBlock) void k_basis(const DevState *__restrict__ s
 // three); south/north/centre/previous column are read as 16-byte pairs,
 // west/east of the pair as single values, AP and p_{j+1} written as pairs.
 // p_{j-1} is read once and not reused: non-temporal loads.  1024-thread
-// blocks run in-plane fastest (blockIdx.x over x-y pairs, blockIdx.y over
-// plane groups), so a block spans several grid rows and its +-y neighbours
-// are mostly its own loads.  Shape measured fastest on MI355X among 1/2/4
-// points x 1..16 planes x 128..1024 threads (224^3, in the solve's column
-// rotation).
+// blocks are numbered in-plane fastest (x-y pairs, then plane groups), so a
+// block spans several grid rows and its +-y neighbours are mostly its own
+// loads; each XCD takes a contiguous range of those numbers, so the rows
+// and planes a block shares with its neighbours are mostly L2 hits.  Shape
+// measured fastest on MI355X among 1/2/4 points x 1..16 planes x 128..1024
+// threads (224^3, in the solve's column rotation).
 constexpr int kP2Kz = 8;
 constexpr int kP2Block = 1024;
 template <int STEP>
 __global__ __launch_bounds__(kP2Block) void k_basis_p2(const DevState *__restrict__ st, Grid3 g, double minv,
                                                        const double *__restrict__ pj, const double *__restrict__ pprev,
                                                        double *__restrict__ apj, double *__restrict__ pnext,
-                                                       double theta, double sigma)
+                                                       double theta, double sigma, uint32_t gx, uint32_t per,
+                                                       uint32_t nbl)
 {
     constexpr int KZ = kP2Kz;
     if (st->done)
         return;
-    const uint32_t pl = (blockIdx.x * kP2Block + threadIdx.x) * 2;  // in-plane index of the pair
+    // logical block (in-plane fastest) in XCD-contiguous order: the blocks
+    // holding a block's +-y rows and +-z planes run on the same XCD
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;
+    const uint32_t bz = lb / gx, bx = lb - bz * gx;
+    const uint32_t pl = (bx * kP2Block + threadIdx.x) * 2;  // in-plane index of the pair
     if (pl >= static_cast<uint32_t>(g.nxy))
         return;
     const uint32_t j = fdiv(pl, g.dx);
     const uint32_t i = pl - j * g.nx;
-    const int k0 = blockIdx.y * KZ;
+    const int k0 = static_cast<int>(bz) * KZ;
     const double2 z = {0.0, 0.0};
     int64_t c = pl + static_cast<int64_t>(k0) * g.nxy;
     double2 below = k0 > 0 ? *reinterpret_cast<const double2 *>(pj + c - g.nxy) : z;
@@ -555,8 +563,10 @@ hipError_t basis_for(const IterArgs &a, const Op &op, int j, int step, hipStream
 // FP64 constant Poisson with an even x-extent: pairs of points, two planes.
 hipError_t basis_poisson_pairs(const IterArgs &a, int j, int step, hipStream_t st)
 {
-    const dim3 grid(static_cast<uint32_t>((a.op.g.nxy / 2 + kP2Block - 1) / kP2Block),
-                    static_cast<uint32_t>((a.op.g.nz + kP2Kz - 1) / kP2Kz));
+    const uint32_t gx = static_cast<uint32_t>((a.op.g.nxy / 2 + kP2Block - 1) / kP2Block);
+    const uint32_t nbl = gx * static_cast<uint32_t>((a.op.g.nz + kP2Kz - 1) / kP2Kz);
+    const uint32_t per = (nbl + kNumXcd - 1) / kNumXcd;
+    const dim3 grid(per * kNumXcd);
     double *P = static_cast<double *>(a.P);
     double *AP = static_cast<double *>(a.AP);
     const double *pj = P + j * a.ld;
@@ -566,13 +576,13 @@ hipError_t basis_poisson_pairs(const IterArgs &a, int j, int step, hipStream_t s
     const double minv = a.op.precond ? 1.0 / 6.0 : 1.0;
     if (step == 2)
         hipLaunchKernelGGL(k_basis_p2<2>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
-                           a.theta, a.sigma);
+                           a.theta, a.sigma, gx, per, nbl);
     else if (step == 0)
         hipLaunchKernelGGL(k_basis_p2<0>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
-                           a.theta, a.sigma);
+                           a.theta, a.sigma, gx, per, nbl);
     else
         hipLaunchKernelGGL(k_basis_p2<1>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
-                           a.theta, a.sigma);
+                           a.theta, a.sigma, gx, per, nbl);
     return hipGetLastError();
 }
 
