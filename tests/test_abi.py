@@ -153,3 +153,21 @@ def test_missing_library_fails_loudly(native, monkeypatch, tmp_path):
     monkeypatch.setattr(native, "LIB_PATH", str(tmp_path / "libsstep.so"))
     with pytest.raises(ImportError, match="no CPU fallback"):
         native.load()
+
+
+def test_entry_point_build_runs(monkeypatch):
+    """``__graft_entry__.build()`` reaches every step: the HIP build (stubbed
+    here, it takes minutes), the oracle build and the package import."""
+    import importlib
+    import sys
+
+    sys.path.insert(0, ROOT)
+    entry = importlib.import_module("__graft_entry__")
+    from paper_2512_09642_amd import build as hipbuild
+
+    calls = []
+    monkeypatch.setattr(hipbuild, "build", lambda *a, **k: calls.append("hip"))
+    entry.build()
+    assert calls == ["hip"]
+    from oracle.build import LIB
+    assert os.path.exists(LIB)
