@@ -12,9 +12,12 @@
  *   4. column scaling d_i = (p_i^T A p_i)^{-1/2}, G <- S G S   (Sec. 2, column scaling)
  *      and nu forward Gauss-Seidel sweeps from alpha = 0      (Sec. 2, FGS iteration)
  *   5. x <- x + P alpha                                       (Sec. 2)
- * Every step runs in hand-written HIP kernels; one outer iteration is captured
- * in a HIP graph, so a solve performs no host synchronisation between outer
- * iterations (the host polls a device flag between graph replays).
+ * Every step runs in hand-written HIP kernels.  graph_chunk outer iterations
+ * are captured in one HIP graph; the stopping test runs on the device inside
+ * the residual kernel and, once it fires, every later kernel returns at once.
+ * The host synchronises once per graph replay: it waits for the copy of the
+ * device's stop flag that follows replay r (replay r + 1 already queued
+ * behind it) before deciding whether to queue replay r + 2.
  *
  * Conventions for every function below:
  *   - Vector arguments (b, x, g, lam, dA, P_out, AP_out, y) are DEVICE pointers
@@ -118,7 +121,9 @@ typedef struct {
     double res0;          /* ||b - A x_0|| */
     double *hist_relres;  /* (host, optional) relative residual for k = 0..outer_iters */
     double *hist_delta;   /* (host, optional) ||ctil - G atil|| / ||ctil|| per update (Sec. 7) */
-    int32_t hist_cap;     /* capacity of both history arrays (0 = none) */
+    int32_t hist_cap;     /* capacity of each history array (0 = none) */
+    double *hist_lnorm;   /* (host, optional) ||L||_F per update, L the strictly lower part of the
+                             scaled Gram matrix G = I + L + L^T (Sec. 4) */
 } sstep_stats;
 
 /* Fills *opt with the defaults listed above. */
@@ -179,6 +184,14 @@ int64_t sstep_n(const sstep_ctx *ctx);
 sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alpha_tilde, double *G, double *ctil,
                         double *rnorm, double *P_out, double *AP_out);
 
+/* Diagnostics of the last outer iteration of the last sstep_step or solve on
+ * ctx (host outputs, each may be NULL): rnorm = ||b - A x_k|| of its residual,
+ * delta = ||ctil - G atil|| / ||ctil|| of its Gram solve (Sec. 7), lnorm =
+ * ||L||_F of its scaled Gram matrix G = I + L + L^T (Sec. 4).  After a solve
+ * that stopped, rnorm is the final residual and delta, lnorm belong to the
+ * last update. */
+sstep_status sstep_last_iteration(sstep_ctx *ctx, double *rnorm, double *delta, double *lnorm);
+
 /* Kernel classes timed by sstep_kernel_times, in this order. */
 enum { SSTEP_KT_RESIDUAL = 0, SSTEP_KT_BASIS = 1, SSTEP_KT_GRAM = 2, SSTEP_KT_FGS = 3, SSTEP_KT_UPDATE = 4,
        SSTEP_KT_COUNT = 5 };
@@ -198,7 +211,10 @@ int32_t sstep_gram_mode(const sstep_ctx *ctx);
 /* Batched solves: nsys independent operators (each its own size), nrhs
  * right-hand sides per operator, one shared s and nu, per-system bounds
  * lmin[q] < lmax[q] (host arrays).  The outer iteration of every
- * (system, rhs) pair advances in one launch per step over all pairs. */
+ * (system, rhs) pair advances together: each step of it (residual, each of
+ * the s basis steps, Gram, FGS, update) is one persistent launch over all
+ * pairs, s + 4 launches per outer iteration, graph_chunk outer iterations per
+ * graph replay; a pair that has stopped is skipped by every launch. */
 sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_operator *A, int32_t nrhs, int32_t s,
                                  int32_t nu, const double *lmin, const double *lmax, const sstep_options *opt);
 

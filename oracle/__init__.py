@@ -52,7 +52,7 @@ def _load():
         _lib.oracle_fgs.argtypes = [C.c_int, pd, pd, C.c_int, pd]
         _lib.oracle_sstep_step.restype = C.c_int
         _lib.oracle_sstep_step.argtypes = [i64, pi, pi, pd, pd, pd, pd, C.c_int, C.c_int, d, d, C.c_int, C.c_int,
-                                           pd, pd, pd, pd, pd, pd, pd, pd]
+                                           pd, pd, pd, pd, pd, pd, pd, pd, pd, pd]
         _lib.oracle_sstep_solve.restype = C.c_int
         _lib.oracle_sstep_solve.argtypes = [i64, pi, pi, pd, pd, pd, C.c_int, C.c_int, d, d, d, C.c_int, C.c_int,
                                             C.c_int, C.POINTER(C.c_int), pd, pd, pd, pd, pd, C.c_int]
@@ -169,20 +169,23 @@ def fgs(G, ctil, nu):
 
 def step(A, b, xk, s, nu, lmin, lmax, precond=1, p0_mode=0, want_basis=False):
     """One outer iteration from ``xk``.  Returns a dict with ``status``,
-    ``x`` (x_{k+1}), ``atil``, ``G``, ``ctil``, ``Graw``, ``d``, ``rnorm`` and,
+    ``x`` (x_{k+1}), ``atil``, ``G``, ``ctil``, ``Graw``, ``d``, ``rnorm``,
+    ``delta`` (Gram-solve residual, Sec. 7), ``lnorm`` (||L||_F, Sec. 4) and,
     with ``want_basis``, ``P`` / ``AP`` of shape (s, n)."""
     rp, ci, v = _csr(A)
     n = rp.size - 1
     b, xk = _f64(b), _f64(xk)
     xn = np.empty(n)
     out = dict(atil=np.zeros(s), G=np.zeros((s, s)), ctil=np.zeros(s), Graw=np.zeros((s, s)), d=np.zeros(s),
-               rnorm=np.zeros(1))
+               rnorm=np.zeros(1), delta=np.zeros(1), lnorm=np.zeros(1))
     P = np.zeros((s, n)) if want_basis else None
     AP = np.zeros((s, n)) if want_basis else None
     st = _load().oracle_sstep_step(n, _pi(rp), _pi(ci), _pd(v), _pd(b), _pd(xk), _pd(xn), s, nu, lmin, lmax,
                                    precond, p0_mode, _pd(out["atil"]), _pd(out["G"]), _pd(out["ctil"]),
-                                   _pd(out["Graw"]), _pd(out["d"]), _pd(out["rnorm"]), _pd(P), _pd(AP))
-    out.update(status=st, x=xn, rnorm=float(out["rnorm"][0]))
+                                   _pd(out["Graw"]), _pd(out["d"]), _pd(out["rnorm"]), _pd(out["delta"]),
+                                   _pd(out["lnorm"]), _pd(P), _pd(AP))
+    out.update(status=st, x=xn, rnorm=float(out["rnorm"][0]), delta=float(out["delta"][0]),
+               lnorm=float(out["lnorm"][0]))
     if want_basis:
         out.update(P=P, AP=AP)
     return out
@@ -209,6 +212,15 @@ def solve(A, b, x0, s, nu, lmin, lmax, tol, max_outer=10000, precond=1, p0_mode=
         k = min(it.value, hist_cap)
         out.update(hist_relres=hr[:min(it.value + 1, hist_cap)], hist_delta=hd[:k], hist_lnorm=hl[:k])
     return out
+
+
+def gram_condition(G) -> float:
+    """2-norm condition number of a symmetric positive definite Gram matrix
+    (Sec. 4 and the measured values of Sec. 8), from its extreme eigenvalues
+    (LAPACK's symmetric eigensolver as the step); inf when G is singular or
+    indefinite in working precision."""
+    w = np.linalg.eigvalsh(np.asarray(G, dtype=np.float64))
+    return float(w[-1] / w[0]) if w[0] > 0 else float("inf")
 
 
 def grad_csr(A, lam, x):

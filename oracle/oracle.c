@@ -414,12 +414,13 @@ static void ws_free(oracle_ws *w, double *invd)
 
 /* One outer iteration from x_k (no stopping test): xnext = x_k + P alpha.
  * Outputs: atil (s), G (s*s scaled), ctil (s), Graw (s*s), d (s), rnorm
- * (||b - A x_k||), and optionally the basis P and AP (n*s each, column-major);
- * any output pointer may be NULL. */
+ * (||b - A x_k||), delta (the Gram-solve residual of Sec. 7), lnorm (||L||_F
+ * of Sec. 4), and optionally the basis P and AP (n*s each, column-major); any
+ * output pointer may be NULL. */
 int oracle_sstep_step(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                       const double *b, const double *xk, double *xnext, int s, int nu, double lmin, double lmax,
                       int precond, int p0_mode, double *atil, double *G, double *ctil, double *Graw, double *d,
-                      double *rnorm, double *P_out, double *AP_out)
+                      double *rnorm, double *delta, double *lnorm, double *P_out, double *AP_out)
 {
     int st = check_common(n, row_ptr, col_idx, val, s, nu, lmin, lmax);
     if (st != ORACLE_OK || !b || !xk || !xnext)
@@ -433,7 +434,7 @@ int oracle_sstep_step(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
             *rnorm = rho;
         if (xnext != xk)
             memcpy(xnext, xk, sizeof(double) * n);
-        st = outer_update(&w, xnext, atil, G, ctil, Graw, d, NULL, NULL);
+        st = outer_update(&w, xnext, atil, G, ctil, Graw, d, delta, lnorm);
         if (P_out)
             memcpy(P_out, w.P, sizeof(double) * n * s);
         if (AP_out)

@@ -20,7 +20,7 @@ KT_NAMES = ("residual", "basis", "gram", "fgs", "update")
 EXPORTS = (
     "sstep_default_options", "sstep_setup", "sstep_update_coefficients", "sstep_apply", "sstep_solve",
     "sstep_solve_adjoint", "sstep_grad_operator", "sstep_grad_size", "sstep_n", "sstep_step",
-    "sstep_kernel_times", "sstep_gram_mode", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
+    "sstep_last_iteration", "sstep_kernel_times", "sstep_gram_mode", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
     "sstep_status_string", "sstep_destroy",
 )
 
@@ -41,7 +41,7 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
                 ("res0", C.c_double), ("hist_relres", C.c_void_p), ("hist_delta", C.c_void_p),
-                ("hist_cap", C.c_int32)]
+                ("hist_cap", C.c_int32), ("hist_lnorm", C.c_void_p)]
 
 
 class SStepError(RuntimeError):
@@ -89,6 +89,8 @@ def load():
     lib.sstep_n.restype = C.c_int64
     lib.sstep_step.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.sstep_step.restype = st
+    lib.sstep_last_iteration.argtypes = [P, P, P, P]
+    lib.sstep_last_iteration.restype = st
     lib.sstep_kernel_times.argtypes = [P, P, P, C.c_int32, P]
     lib.sstep_kernel_times.restype = st
     lib.sstep_gram_mode.argtypes = [P]

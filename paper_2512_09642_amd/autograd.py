@@ -14,34 +14,52 @@ import torch
 from .solver import Operator, Solver
 
 
+def _load(solver: Solver, coeffs: torch.Tensor) -> object:
+    """Loads ``coeffs`` into ``solver`` and returns the token that marks them
+    as the solver's current coefficients."""
+    op = solver.op
+    if op.kind == 0:
+        new = Operator.csr(op.row_ptr, op.col_idx, coeffs.detach())
+    else:
+        kx, ky, kz = op.split_faces(coeffs.detach())
+        new = Operator.stencil(*op.dims, kx, ky, kz)
+    solver.update_coefficients(new)
+    token = object()
+    solver.coeff_token = token
+    return token
+
+
 class SStepSolve(torch.autograd.Function):
     """``x = SStepSolve.apply(coeffs, b, solver, tol)``.
 
     ``coeffs`` holds the operator's coefficient values: the CSR ``val`` array
     or the concatenated face coefficients ``[kx | ky | kz]`` (device float64).
-    They are loaded into ``solver`` before the solve.  Returns x; gradients
+    They are loaded into ``solver`` before the solve, and again before the
+    adjoint solve if the shared solver has been given other coefficients in
+    between (several forwards before their backwards).  Returns x; gradients
     flow to ``coeffs`` and ``b``.
     """
 
     @staticmethod
     def forward(ctx, coeffs: torch.Tensor, b: torch.Tensor, solver: Solver, tol: float = 1e-8):
-        op = solver.op
-        if op.kind == 0:
-            new = Operator.csr(op.row_ptr, op.col_idx, coeffs.detach())
-        else:
-            kx, ky, kz = op.split_faces(coeffs.detach())
-            new = Operator.stencil(*op.dims, kx, ky, kz)
-        solver.update_coefficients(new)
+        token = _load(solver, coeffs)
         x, _ = solver.solve(b.detach().contiguous(), None, tol)
         ctx.solver = solver
         ctx.tol = tol
-        ctx.save_for_backward(x)
+        ctx.token = token
+        # coeffs is saved so that backward solves the adjoint with the operator
+        # of this forward (autograd raises if it is modified in place meanwhile)
+        ctx.save_for_backward(x, coeffs)
         return x
 
     @staticmethod
     def backward(ctx, gx: torch.Tensor):
-        (x,) = ctx.saved_tensors
+        x, coeffs = ctx.saved_tensors
         solver: Solver = ctx.solver
+        if solver.coeff_token is not ctx.token:
+            # another forward (or update_coefficients) has loaded other
+            # coefficients into the shared solver since: reload this one's
+            ctx.token = _load(solver, coeffs)
         lam, _ = solver.solve_adjoint(gx.detach().contiguous(), None, ctx.tol)
         dcoef = solver.grad_operator(lam, x) if ctx.needs_input_grad[0] else None
         db = lam if ctx.needs_input_grad[1] else None

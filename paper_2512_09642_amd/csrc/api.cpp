@@ -20,6 +20,7 @@
 
 #include "launch.h"
 #include "sstep.h"
+#include "tune_cache.h"
 
 using namespace sstep;
 
@@ -336,11 +337,9 @@ sstep_status start_state(sstep_ctx *ctx, const double *b, double *x, double tol,
 // ---------------------------------------------------------------------------
 // Gram schedule and its autotuner.
 // ---------------------------------------------------------------------------
-struct GramSchedule {
-    int nbg;       // stored-AP kernel: partial blocks; operator-applying kernel: block cap
-    int64_t slab;  // stored-AP kernel: 0 contiguous chunks, > 0 strided slabs of this many rows
-    double us;     // measured time per launch (0 = not measured)
-};
+// nbg: stored-AP kernel: partial blocks; operator-applying kernel: block cap.
+// slab: stored-AP kernel: 0 contiguous chunks, > 0 strided slabs of this many rows.
+using GramSchedule = TuneEntry;
 
 GramSchedule default_gram_schedule(const IterArgs &it)
 {
@@ -396,7 +395,7 @@ void set_gram_schedule(IterArgs &it, const GramSchedule &g)
         return;
     }
     const int64_t blocks_needed = (it.ld + kPad - 1) / kPad;
-    it.nbg = int(std::max<int64_t>(1, std::min<int64_t>(g.nbg, blocks_needed)));
+    it.nbg = int(std::max<int64_t>(1, std::min<int64_t>(std::min(g.nbg, kMaxGramBlocks), blocks_needed)));
     it.gslab = g.slab;
     it.gchunk = round_up((it.ld + it.nbg - 1) / it.nbg, kPad);
 }
@@ -418,52 +417,11 @@ std::string tune_cache_path()
 std::string tune_key(const IterArgs &it)
 {
     std::ostringstream k;
-    k << "gfx950 gram s=" << it.s << " prec=" << (it.fp32 ? "fp32" : "fp64") << " rows=" << it.ld
+    k << kTuneSchema << " gfx950 gram s=" << it.s << " prec=" << (it.fp32 ? "fp32" : "fp64") << " rows=" << it.ld
       << " wd=" << it.wdvec;
     if (it.gram_op)
         k << " op2=" << it.op.kind << " grid=" << it.op.g.nx << "x" << it.op.g.ny << "x" << it.op.g.nz;
     return k.str();
-}
-
-// The cache is a JSON object written one entry per line:
-//   "key": {"nbg": 256, "slab": 0, "us": 507.3},
-std::map<std::string, GramSchedule> read_tune_cache(const std::string &path)
-{
-    std::map<std::string, GramSchedule> m;
-    std::ifstream f(path);
-    std::string line;
-    while (std::getline(f, line)) {
-        const size_t a = line.find('"'), b = line.find("\": {");
-        if (a == std::string::npos || b == std::string::npos || b <= a)
-            continue;
-        GramSchedule g{0, 0, 0.0};
-        long long slab = 0;
-        if (std::sscanf(line.c_str() + b, "\": {\"nbg\": %d, \"slab\": %lld, \"us\": %lf", &g.nbg, &slab, &g.us) ==
-            3) {
-            g.slab = slab;
-            m[line.substr(a + 1, b - a - 1)] = g;
-        }
-    }
-    return m;
-}
-
-void write_tune_cache(const std::string &path, const std::map<std::string, GramSchedule> &m)
-{
-    const std::string tmp = path + ".tmp" + std::to_string(::getpid());
-    {
-        std::ofstream f(tmp);
-        if (!f)
-            return;
-        f << "{\n";
-        size_t q = 0;
-        for (const auto &kv : m) {
-            f << "  \"" << kv.first << "\": {\"nbg\": " << kv.second.nbg << ", \"slab\": " << kv.second.slab
-              << ", \"us\": " << kv.second.us << "}"
-              << (++q < m.size() ? "," : "") << "\n";
-        }
-        f << "}\n";
-    }
-    std::rename(tmp.c_str(), path.c_str());
 }
 
 // Times each candidate Gram schedule on the context's own buffers (the values
@@ -478,7 +436,7 @@ sstep_status tune_gram(sstep_ctx *ctx)
     if (!path.empty()) {
         cache = read_tune_cache(path);
         auto f = cache.find(key);
-        if (f != cache.end() && f->second.nbg > 0) {
+        if (f != cache.end() && gram_entry_ok(f->second, kMaxGramBlocks, kPad)) {
             set_gram_schedule(it, f->second);
             return SSTEP_OK;
         }
@@ -592,6 +550,9 @@ sstep_status run_solve(sstep_ctx *ctx, const double *b, double *x, double tol, s
                 HIPCHK(ctx, hipMemcpy(stats->hist_relres, ctx->it.hist, nr * sizeof(double), hipMemcpyDeviceToHost));
             if (stats->hist_delta && nd > 0)
                 HIPCHK(ctx, hipMemcpy(stats->hist_delta, ctx->it.hist + ctx->it.hist_cap, nd * sizeof(double),
+                                      hipMemcpyDeviceToHost));
+            if (stats->hist_lnorm && nd > 0)
+                HIPCHK(ctx, hipMemcpy(stats->hist_lnorm, ctx->it.hist + 2 * ctx->it.hist_cap, nd * sizeof(double),
                                       hipMemcpyDeviceToHost));
         }
     }
@@ -809,7 +770,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     OKCHK(dalloc(ctx, &it.st, 1));
     OKCHK(dalloc(ctx, &it.dbg, size_t(dbg_size(s))));
     it.hist_cap = o.record_history ? o.max_outer + 1 : 0;
-    OKCHK(dalloc(ctx, &it.hist, size_t(2 * std::max(it.hist_cap, 1))));
+    OKCHK(dalloc(ctx, &it.hist, size_t(3 * std::max(it.hist_cap, 1))));
     it.inv_sqrt_n = 1.0 / std::sqrt(double(n));
     HIPCHK(ctx, hipMemsetAsync(it.st, 0, sizeof(DevState), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -959,6 +920,24 @@ sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alph
     return SSTEP_OK;
 }
 
+sstep_status sstep_last_iteration(sstep_ctx *ctx, double *rnorm, double *delta, double *lnorm)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (ctx->batch)
+        return fail(ctx, SSTEP_E_ARG, "not available for a batched context");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    DevState h;
+    HIPCHK(ctx, hipMemcpy(&h, ctx->it.st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (rnorm)
+        *rnorm = h.rho;
+    if (delta)
+        *delta = h.delta;
+    if (lnorm)
+        *lnorm = h.lnorm;
+    return SSTEP_OK;
+}
+
 sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int32_t reps, double *ms_out)
 {
     if (!ctx)
@@ -1003,6 +982,8 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
 
 static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bool upload)
 {
+    if (gchunk < kMinBatchChunk || gchunk % kPad != 0 || factor < 1)
+        return fail(ctx, SSTEP_E_ARG, "batched tile schedule out of range");
     Batched &B = *ctx->batch;
     BatchArgs &a = B.ba;
     const int E = gram_entries(a.s);
@@ -1069,14 +1050,14 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     uint64_t h = 1469598103934665603ull;
     for (int64_t v : B.n)
         h = (h ^ uint64_t(v)) * 1099511628211ull;
-    key << "gfx950 batched s=" << a.s << " prec=" << (a.fp32 ? "fp32" : "fp64") << " nrhs=" << a.nrhs
+    key << kTuneSchema << " gfx950 batched s=" << a.s << " prec=" << (a.fp32 ? "fp32" : "fp64") << " nrhs=" << a.nrhs
         << " nsys=" << a.nsys << " faces=" << a.faces << " sizes=" << std::hex << h;
     const std::string path = tune_cache_path();
     std::map<std::string, GramSchedule> cache;
     if (!path.empty()) {
         cache = read_tune_cache(path);
         auto f = cache.find(key.str());
-        if (f != cache.end() && f->second.nbg > 0)
+        if (f != cache.end() && batched_entry_ok(f->second, kPad, kMinBatchChunk))
             return batched_tiles(ctx, f->second.slab, f->second.nbg, true);
     }
     int64_t best_chunk = B.gchunk;
@@ -1247,10 +1228,10 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         a.P = P;
         a.AP = AP;
     }
-    // tables and partials sized for the smallest tile (2048 rows)
+    // tables and partials sized for the smallest tile (kMinBatchChunk rows)
     int64_t max_nch = 0, max_pt = 0;
     for (const BSys &S : B.sys) {
-        max_nch += (S.ld + 2047) / 2048;
+        max_nch += (S.ld + kMinBatchChunk - 1) / kMinBatchChunk;
         max_pt += (S.n + kBlock - 1) / kBlock;
     }
     OKCHK(dalloc(ctx, &B.dsys, size_t(nsys)));

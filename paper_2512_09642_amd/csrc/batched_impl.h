@@ -91,12 +91,18 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs(BGlob *__restrict__ gl, c
         if (lane == 0)
             sg[t] = acc;
     }
+    __shared__ int stopped;
+    __syncthreads();
+    double *pdbg = dbg + static_cast<int64_t>(p) * dbg_size(S);
+    if (threadIdx.x == 0)
+        stopped = stop_test(ps, sg[E], pdbg + dbg_rho(S), nullptr, 0);
     __syncthreads();
     if (wave != 0)
         return;
-    const int stopped = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, dbg + static_cast<int64_t>(p) * dbg_size(S),
-                                    nullptr, 0);
-    if (stopped && lane == 0)
+    int now = stopped;
+    if (!now)
+        now = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, pdbg, nullptr, 0);
+    if (now && lane == 0)
         atomicAdd(&gl->ndone, 1);
 }
 
@@ -107,14 +113,5 @@ hipError_t bfgs_launch_s(const BatchArgs &a, hipStream_t st)
                        a.gpart, a.nu, a.cscale, a.fp32, a.dbg);
     return hipGetLastError();
 }
-
-hipError_t bgram_launch_1_8(const BatchArgs &a, hipStream_t st);
-hipError_t bgram_launch_9_16(const BatchArgs &a, hipStream_t st);
-hipError_t bgram_launch_17_24(const BatchArgs &a, hipStream_t st);
-hipError_t bgram_launch_25_32(const BatchArgs &a, hipStream_t st);
-hipError_t bfgs_launch_1_8(const BatchArgs &a, hipStream_t st);
-hipError_t bfgs_launch_9_16(const BatchArgs &a, hipStream_t st);
-hipError_t bfgs_launch_17_24(const BatchArgs &a, hipStream_t st);
-hipError_t bfgs_launch_25_32(const BatchArgs &a, hipStream_t st);
 
 }  // namespace sstep

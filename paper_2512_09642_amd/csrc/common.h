@@ -25,6 +25,7 @@ struct DevState {
     double relres;     // rho / rho0
     double p0scale;    // power-of-two factor applied to p_0 (FP32+IR); 1 in FP64
     double delta;      // ||ctil - G atil|| / ||ctil|| of the last Gram solve
+    double lnorm;      // ||L||_F, L the strictly lower part of the last scaled Gram matrix
     int32_t done;      // 1 once the solve has stopped
     int32_t status;    // sstep_status value
     int32_t iter;      // completed outer updates
@@ -32,7 +33,7 @@ struct DevState {
     int32_t first;     // 1 until rho0 has been recorded
     int32_t no_stop;   // 1 = never stop (single-step and timing entry points)
     int32_t hist_cap;  // capacity of the device history (0 = off)
-    int32_t pad;
+    uint32_t ticket;   // blocks of the running residual kernel that have stored their partial
     double alpha[kMaxS];  // coefficients of the unscaled basis, x += P alpha
 };
 

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "gram_impl.h"
+#include "stop.h"
 
 namespace sstep {
 
@@ -16,70 +17,32 @@ __device__ __forceinline__ double readlane(double v, int l)
 }
 
 // sg holds the reduced sums: Gram entries in canonical order (lower triangle
-// row by row, then the right-hand side) and ||r||^2 at index E.
-// 1. Stopping test on the true residual: stop when ||r_k|| < tol ||r_0||
-//    (strict; Sec. 8), at max_outer, or on a non-finite norm.
-// 2. Column scaling (Sec. 2): d_i = G_raw,ii^{-1/2}; G = S G_raw S with the
+// row by row, then the right-hand side).  The stopping test of iteration k
+// has already run (stop.h), and st->rho holds ||r_k||.
+// 1. Column scaling (Sec. 2): d_i = G_raw,ii^{-1/2}; G = S G_raw S with the
 //    diagonal set to one and each off-diagonal pair scaled once from the lower
 //    triangle, so G is exactly symmetric; ctil = S c.  A diagonal entry that is
 //    not positive and finite is a breakdown.
-// 3. nu forward Gauss-Seidel sweeps from atil = 0 (Sec. 2, FGS iteration;
+// 2. nu forward Gauss-Seidel sweeps from atil = 0 (Sec. 2, FGS iteration;
 //    Sec. 3), j = 0..s-1 in order, in residual form: lane i keeps row i of G
 //    and rho_i = ctil_i - (G atil)_i; visiting j adds rho_j to atil_j and
 //    subtracts G_ij rho_j from every rho_i -- the same update as
 //    atil_j <- ctil_j - sum_{i != j} G_ji atil_i since G_jj = 1.
-// 4. alpha = S atil for the update kernel; delta = ||ctil - G atil|| / ||ctil||
-//    (the Gram-solve accuracy of Sec. 7) and the history.
-// The basis width s is a template parameter so that the ν·s dependent steps of
-// the sweeps carry no bound checks.  Returns 1 when this call stopped the
-// solve (the caller may count it).
+// 3. alpha = S atil for the update kernel; delta = ||ctil - G atil|| / ||ctil||
+//    (the Gram-solve accuracy of Sec. 7), ||L||_F of the strictly lower part
+//    of G (Sec. 4) and their histories.
+// The basis width s is a template parameter so that the nu*s dependent steps of
+// the sweeps carry no bound checks.  Returns 1 on a breakdown (the solve is
+// stopped).
 template <int s>
 __device__ __forceinline__ int fgs_wave(DevState *__restrict__ st, const double *__restrict__ sg, int nu,
                                         double cscale, int fp32, double inv_sqrt_n, double *__restrict__ dbg,
                                         double *__restrict__ hist, int hist_cap)
 {
     const int lane = threadIdx.x % kWave;
-    constexpr int E = s * (s + 1) / 2 + s;
     constexpr int T0 = s * (s + 1) / 2;
-    // ---- stopping test ----------------------------------------------------
-    const double rho = sqrt(sg[E]);
-    const int first = st->first;
-    const double rho0 = first ? rho : st->rho0;
     const int k = st->iter;
-    int stop = 0, status = 0;
-    double relres = 0.0;
-    if (first && rho0 == 0.0) {
-        stop = 1;
-    } else if (!isfinite(rho)) {
-        stop = 1;
-        status = 6;  // SSTEP_E_NONFINITE
-        relres = rho;
-    } else {
-        relres = rho / rho0;
-        if (!st->no_stop) {
-            if (rho < st->tol * rho0)
-                stop = 1;
-            else if (k >= st->max_outer) {
-                stop = 1;
-                status = 5;  // SSTEP_E_NOCONV
-            }
-        }
-    }
-    if (lane == 0) {
-        st->first = 0;
-        st->rho0 = rho0;
-        st->rho = rho;
-        st->relres = relres;
-        if (k < hist_cap)
-            hist[k] = relres;
-        dbg[dbg_rho(s)] = rho;
-        if (stop) {
-            st->status = status;
-            st->done = 1;
-        }
-    }
-    if (stop)
-        return 1;
+    const double rho = st->rho;
 
     // ---- column scaling -----------------------------------------------------
     const int i = lane;
@@ -135,6 +98,12 @@ __device__ __forceinline__ int fgs_wave(DevState *__restrict__ st, const double 
     const double num = wave_sum(res * res);
     const double den = wave_sum(ct * ct);
     const double delta = den > 0.0 ? sqrt(num / den) : 0.0;
+    double lsq = 0.0;
+#pragma unroll
+    for (int j = 0; j < s; ++j)
+        if (j < i)
+            lsq += grow[j] * grow[j];
+    const double lnorm = sqrt(wave_sum(lsq));
     if (own) {
         st->alpha[i] = d * a;
         dbg[dbg_ctil(s) + i] = ct;
@@ -146,8 +115,11 @@ __device__ __forceinline__ int fgs_wave(DevState *__restrict__ st, const double 
     }
     if (lane == 0) {
         st->delta = delta;
-        if (k < hist_cap)
+        st->lnorm = lnorm;
+        if (k < hist_cap) {
             hist[hist_cap + k] = delta;
+            hist[2 * hist_cap + k] = lnorm;
+        }
         st->iter = k + 1;
         if (fp32) {
             const double rms = rho * inv_sqrt_n;
@@ -158,28 +130,23 @@ __device__ __forceinline__ int fgs_wave(DevState *__restrict__ st, const double 
 }
 
 constexpr int kFgsThreads = 256;
-constexpr int kSumThreads = 256;
 
-// Sum of the block partials of one Gram entry (blocks e < E) or of the
-// residual norm (block E), in a fixed order: thread t takes partials t,
-// t + 256, ..., the waves combine by butterfly and the four wave sums in order.
-// One block per entry keeps every partial load of the reduction in flight at
-// once across the chip.
+// Sum of the block partials of one Gram entry e (one block per entry), in a
+// fixed order: thread t takes partials t, t + 256, ..., the waves combine by
+// butterfly and the four wave sums in order.  One block per entry keeps every
+// partial load of the reduction in flight at once across the chip.
 template <int s>
 __global__ __launch_bounds__(kSumThreads) void k_partial_sums(const DevState *__restrict__ st,
                                                               const double *__restrict__ gpart, int nbg,
-                                                              const double *__restrict__ rpart, int nbr,
                                                               double *__restrict__ sums)
 {
-    constexpr int E = s * (s + 1) / 2 + s;
     __shared__ double part[kSumThreads / kWave];
     if (st->done)
         return;
     const int e = blockIdx.x;
-    const double *src = e < E ? gpart + static_cast<int64_t>(e) * nbg : rpart;
-    const int cnt = e < E ? nbg : nbr;
+    const double *src = gpart + static_cast<int64_t>(e) * nbg;
     double acc = 0.0;
-    for (int q = threadIdx.x; q < cnt; q += kSumThreads)
+    for (int q = threadIdx.x; q < nbg; q += kSumThreads)
         acc += src[q];
     acc = wave_sum(acc);
     if (threadIdx.x % kWave == 0)
@@ -204,10 +171,10 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
 {
     if (st->done)
         return;
-    __shared__ double sg[s * (s + 1) / 2 + s + 1];
+    __shared__ double sg[s * (s + 1) / 2 + s];
     constexpr int E = s * (s + 1) / 2 + s;
     const int wave = threadIdx.x / kWave;
-    for (int t = threadIdx.x; t <= E; t += kFgsThreads)
+    for (int t = threadIdx.x; t < E; t += kFgsThreads)
         sg[t] = sums[t];
     __syncthreads();
     if (wave != 0)
@@ -219,8 +186,7 @@ template <int s>
 hipError_t fgs_launch_s(const IterArgs &a, hipStream_t st)
 {
     constexpr int E = s * (s + 1) / 2 + s;
-    hipLaunchKernelGGL(k_partial_sums<s>, dim3(E + 1), dim3(kSumThreads), 0, st, a.st, a.gpart, a.nbg, a.rpart, a.nbr,
-                       a.gsum);
+    hipLaunchKernelGGL(k_partial_sums<s>, dim3(E), dim3(kSumThreads), 0, st, a.st, a.gpart, a.nbg, a.gsum);
     hipLaunchKernelGGL(k_fgs<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.gsum, a.nu, a.cscale, a.fp32,
                        a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap);
     return hipGetLastError();

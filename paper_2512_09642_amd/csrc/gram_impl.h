@@ -292,14 +292,4 @@ hipError_t gram_launch_s(const IterArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-// Launchers for a range of s, one translation unit per range (Gram and FGS).
-hipError_t gram_launch_1_8(const IterArgs &a, hipStream_t st);
-hipError_t gram_launch_9_16(const IterArgs &a, hipStream_t st);
-hipError_t gram_launch_17_24(const IterArgs &a, hipStream_t st);
-hipError_t gram_launch_25_32(const IterArgs &a, hipStream_t st);
-hipError_t fgs_launch_1_8(const IterArgs &a, hipStream_t st);
-hipError_t fgs_launch_9_16(const IterArgs &a, hipStream_t st);
-hipError_t fgs_launch_17_24(const IterArgs &a, hipStream_t st);
-hipError_t fgs_launch_25_32(const IterArgs &a, hipStream_t st);
-
 }  // namespace sstep

@@ -452,7 +452,4 @@ hipError_t gram_op_launch_s(const IterArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t gram_op_launch_1_8(const IterArgs &a, hipStream_t st);
-hipError_t gram_op_launch_9_16(const IterArgs &a, hipStream_t st);
-
 }  // namespace sstep

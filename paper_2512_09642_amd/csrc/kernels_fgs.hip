@@ -1,54 +1,55 @@
-// Dispatch of the Gram and FGS launches to the translation unit that holds
-// the instantiation for the basis width s.
-#include "batched_impl.h"
-#include "gram_op_impl.h"
+// Dispatch of the Gram, FGS and batched launches to the instantiation for the
+// basis width s (one object per width, see dispatch.h).
+#include "dispatch.h"
 
 namespace sstep {
 
+#define SSTEP_CASES_1_16(F) \
+    F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)
+#define SSTEP_CASES_17_32(F) \
+    F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)
+
 hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 {
-    if (a.gram_op)
-        return a.s <= 8 ? gram_op_launch_1_8(a, st) : gram_op_launch_9_16(a, st);
-    if (a.s <= 8)
-        return gram_launch_1_8(a, st);
-    if (a.s <= 16)
-        return gram_launch_9_16(a, st);
-    if (a.s <= 24)
-        return gram_launch_17_24(a, st);
-    return gram_launch_25_32(a, st);
+    if (a.gram_op) {
+#define SSTEP_GO(S)                                                                          \
+    case S:                                                                                  \
+        return a.fp32 ? gram_op_launch_s<float, S>(a, st) : gram_op_launch_s<double, S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_GO) default: return hipErrorInvalidValue; }
+#undef SSTEP_GO
+    }
+#define SSTEP_G(S)                                                                           \
+    case S:                                                                                  \
+        return a.fp32 ? gram_launch_s<float, S>(a, st) : gram_launch_s<double, S>(a, st);
+    switch (a.s) { SSTEP_CASES_1_16(SSTEP_G) SSTEP_CASES_17_32(SSTEP_G) default: return hipErrorInvalidValue; }
+#undef SSTEP_G
 }
 
 hipError_t launch_fgs(const IterArgs &a, hipStream_t st)
 {
-    if (a.s <= 8)
-        return fgs_launch_1_8(a, st);
-    if (a.s <= 16)
-        return fgs_launch_9_16(a, st);
-    if (a.s <= 24)
-        return fgs_launch_17_24(a, st);
-    return fgs_launch_25_32(a, st);
+#define SSTEP_F(S) \
+    case S:        \
+        return fgs_launch_s<S>(a, st);
+    switch (a.s) { SSTEP_CASES_1_16(SSTEP_F) SSTEP_CASES_17_32(SSTEP_F) default: return hipErrorInvalidValue; }
+#undef SSTEP_F
 }
 
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st)
 {
-    if (a.s <= 8)
-        return bgram_launch_1_8(a, st);
-    if (a.s <= 16)
-        return bgram_launch_9_16(a, st);
-    if (a.s <= 24)
-        return bgram_launch_17_24(a, st);
-    return bgram_launch_25_32(a, st);
+#define SSTEP_BG(S)                                                                          \
+    case S:                                                                                  \
+        return a.fp32 ? bgram_launch_s<float, S>(a, st) : bgram_launch_s<double, S>(a, st);
+    switch (a.s) { SSTEP_CASES_1_16(SSTEP_BG) SSTEP_CASES_17_32(SSTEP_BG) default: return hipErrorInvalidValue; }
+#undef SSTEP_BG
 }
 
 hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st)
 {
-    if (a.s <= 8)
-        return bfgs_launch_1_8(a, st);
-    if (a.s <= 16)
-        return bfgs_launch_9_16(a, st);
-    if (a.s <= 24)
-        return bfgs_launch_17_24(a, st);
-    return bfgs_launch_25_32(a, st);
+#define SSTEP_BF(S) \
+    case S:         \
+        return bfgs_launch_s<S>(a, st);
+    switch (a.s) { SSTEP_CASES_1_16(SSTEP_BF) SSTEP_CASES_17_32(SSTEP_BF) default: return hipErrorInvalidValue; }
+#undef SSTEP_BF
 }
 
 }  // namespace sstep

@@ -2,6 +2,7 @@
 // SpMV/Jacobi/Chebyshev basis step, the update x += P alpha, and helpers.
 // All of them are bound by HBM bandwidth (well under one flop per byte).
 #include "launch.h"
+#include "stop.h"
 
 namespace sstep {
 namespace {
@@ -41,12 +42,24 @@ __device__ __forceinline__ void block_sum_store(T v, T *out)
     }
 }
 
+// Where a residual kernel reports: with do_stop, the last block to finish sums
+// the partials of ||r||^2 and runs the stopping test, so that a converged
+// iteration launches no basis or Gram work; without it (the norm-only pass
+// of FP32+IR) only the partials are written.
+struct StopOut {
+    int do_stop;
+    double *dbg_rho;  // ||r|| for the single-step entry point
+    double *hist;     // relative-residual history [hist_cap]
+    int hist_cap;
+};
+
 // r = b - A x in FP64, partial sums of r^2 per logical block, and the basis
 // start p_0 = p0scale * (M^{-1} r or r) written as column 0 of P.
 template <class Op, typename TP>
-__global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict__ st, Op op, TP *__restrict__ p0,
+__global__ __launch_bounds__(kBlock) void k_residual(DevState *__restrict__ st, Op op, TP *__restrict__ p0,
                                                      double *__restrict__ rpart, int64_t n, int64_t chunk,
-                                                     uint32_t per, uint32_t nbl, int p0_mode, int write_p0)
+                                                     uint32_t per, uint32_t nbl, int p0_mode, int write_p0,
+                                                     StopOut so)
 {
     if (st->done)
         return;
@@ -68,6 +81,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict_
             p0[c] = static_cast<TP>(scale * (p0_mode ? r : dinv * r));
     }
     block_sum_store(acc, rpart + lb);
+    if (so.do_stop)
+        residual_stop_tail(st, rpart, static_cast<int>(nbl), so.dbg_rho, so.hist, so.hist_cap);
 }
 
 // The residual for the constant Poisson operator in FP64 (nx even) in the
@@ -76,9 +91,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict_
 // One partial sum of r^2 per block, blocks numbered blockIdx.x + gridDim.x *
 // blockIdx.y (the launch keeps their number within the partial buffer).
 template <typename TP>
-__global__ __launch_bounds__(1024) void k_residual_p2(const DevState *__restrict__ st, Grid3 g, double minv,
+__global__ __launch_bounds__(1024) void k_residual_p2(DevState *__restrict__ st, Grid3 g, double minv,
                                                       TP *__restrict__ p0, double *__restrict__ rpart, int p0_mode,
-                                                      int write_p0)
+                                                      int write_p0, StopOut so)
 {
     constexpr int KZ = 8;
     __shared__ double part[1024 / kWave];
@@ -132,6 +147,8 @@ __global__ __launch_bounds__(1024) void k_residual_p2(const DevState *__restrict
             sum += part[w];
         rpart[blockIdx.x + gridDim.x * blockIdx.y] = sum;
     }
+    if (so.do_stop)
+        residual_stop_tail(st, rpart, static_cast<int>(gridDim.x * gridDim.y), so.dbg_rho, so.hist, so.hist_cap);
 }
 
 // One step of the Chebyshev recurrence fused with the operator apply
@@ -506,13 +523,19 @@ struct Ops<float> {
     static OpCsr<float> csr(const OpDev &op) { return {op.rp, op.ci, op.val32, op.invd32}; }
 };
 
+StopOut stop_out(const IterArgs &a, bool write_p0)
+{
+    // the norm-only pass (no p_0) of FP32+IR runs no stopping test
+    return StopOut{write_p0 ? 1 : 0, a.dbg + dbg_rho(a.s), a.hist, a.hist_cap};
+}
+
 template <class Op, typename TP>
 hipError_t residual_for(const IterArgs &a, const Op &op, hipStream_t st, bool write_p0)
 {
     const uint32_t per = (static_cast<uint32_t>(a.nbr) + kNumXcd - 1) / kNumXcd;
     hipLaunchKernelGGL((k_residual<Op, TP>), dim3(per * kNumXcd), dim3(kBlock), 0, st, a.st, op,
                        static_cast<TP *>(a.P), a.rpart, a.op.n, a.rchunk, per, static_cast<uint32_t>(a.nbr),
-                       a.p0_mode, write_p0 ? 1 : 0);
+                       a.p0_mode, write_p0 ? 1 : 0, stop_out(a, write_p0));
     return hipGetLastError();
 }
 
@@ -526,7 +549,7 @@ hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
                             static_cast<uint32_t>((a.op.g.nz + 7) / 8));
             hipLaunchKernelGGL(k_residual_p2<TP>, grid, dim3(1024), 0, st, a.st, a.op.g,
                                a.op.precond ? 1.0 / 6.0 : 1.0, static_cast<TP *>(a.P), a.rpart, a.p0_mode,
-                               write_p0 ? 1 : 0);
+                               write_p0 ? 1 : 0, stop_out(a, write_p0));
             return hipGetLastError();
         }
         return residual_for<OpPoisson7<double>, TP>(a, make_poisson<double>(a.op), st, write_p0);

@@ -17,6 +17,9 @@ constexpr int64_t kPad = 256;
 constexpr int kMaxGramBlocks = 2048;
 // Widest basis served by the Gram kernel that applies a stencil operator itself.
 constexpr int kGoMaxS = 16;
+// Smallest row chunk of a batched tile; the tile tables and partial buffers
+// are sized for it.
+constexpr int64_t kMinBatchChunk = 2048;
 
 // Device copy of the operator in both precisions (the FP32 arrays exist only
 // in FP32+IR mode).
@@ -61,7 +64,7 @@ struct IterArgs {
     int wdvec = 0;        // Gram right-hand side uses M-diagonal * p_0 (else p_0)
     double cscale = 1.0;  // constant factor applied to c = P^T (W) in the FGS kernel
     double *dbg = nullptr;   // G (s*s), ctil (s), atil (s), d (s), rho: written by the FGS kernel
-    double *hist = nullptr;  // [2 * hist_cap]: relres then delta
+    double *hist = nullptr;  // [3 * hist_cap]: relres, delta, ||L||_F
     int hist_cap = 0;
     double inv_sqrt_n = 1.0;
     // Gram kernel that applies the stencil operator itself (AP not stored;

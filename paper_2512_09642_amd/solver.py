@@ -117,6 +117,7 @@ class SolveStats:
     res0: float
     hist_relres: np.ndarray | None = None
     hist_delta: np.ndarray | None = None
+    hist_lnorm: np.ndarray | None = None
 
 
 class Solver:
@@ -143,6 +144,7 @@ class Solver:
         opt.stream = self._stream_ptr()
         self.max_outer = max_outer
         self.record_history = record_history
+        self.coeff_token = None
         cop = op.to_c()
         ctx = C.c_void_p()
         st = self._lib.sstep_setup(C.byref(ctx), C.byref(cop), s, nu, lmin, lmax, C.byref(opt))
@@ -183,6 +185,7 @@ class Solver:
         cop = op.to_c()
         st = self._lib.sstep_update_coefficients(self._ctx, C.byref(cop))
         op._keep = []
+        self.coeff_token = None  # the differentiable solve's marker of which coefficients are loaded
         _check(st, self._ctx)
 
     def apply(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
@@ -197,15 +200,18 @@ class Solver:
         cap = (self.max_outer + 1) if (hist and self.record_history) else 0
         hr = np.zeros(max(cap, 1))
         hd = np.zeros(max(cap, 1))
+        hl = np.zeros(max(cap, 1))
         if cap:
             stats.hist_relres = hr.ctypes.data
             stats.hist_delta = hd.ctypes.data
+            stats.hist_lnorm = hl.ctypes.data
             stats.hist_cap = cap
         st = fn(self._ctx, _dev_ptr(b, self.n, "b"), _dev_ptr(x, self.n, "x"), tol, C.byref(stats))
         out = SolveStats(stats.outer_iters, stats.status, stats.rel_res, stats.res0)
         if cap:
             out.hist_relres = hr[:stats.outer_iters + 1].copy()
             out.hist_delta = hd[:stats.outer_iters].copy()
+            out.hist_lnorm = hl[:stats.outer_iters].copy()
         if raise_on_error:
             _check(st, self._ctx, out)
         return x, out
@@ -248,6 +254,14 @@ class Solver:
         if want_basis:
             out.update(P=P, AP=AP)
         return out
+
+    def last_iteration(self) -> dict:
+        """``rnorm``, ``delta`` (Gram-solve residual) and ``lnorm`` (||L||_F)
+        of the last outer iteration (after ``step`` or a solve)."""
+        v = np.zeros(3)
+        _check(self._lib.sstep_last_iteration(self._ctx, v[0:].ctypes.data, v[1:].ctypes.data, v[2:].ctypes.data),
+               self._ctx)
+        return dict(rnorm=float(v[0]), delta=float(v[1]), lnorm=float(v[2]))
 
     def kernel_times(self, b: torch.Tensor, x_scratch: torch.Tensor, reps: int = 5) -> dict:
         """Average ms per launch of each kernel class (HIP events)."""

@@ -9,9 +9,15 @@ import oracle
 
 
 def rel(a, b) -> float:
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    """The larger of the norm-wise relative difference ||a - b|| / ||b|| and the
+    entry-wise one max_i |a_i - b_i| / max_i |b_i|, so that a bound on it holds
+    for the vector as a whole and for every entry on the vector's scale."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    d = np.abs(a - b)
+    norm = float(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300))
+    ent = float(d.max() / max(np.abs(b).max(), 1e-300)) if b.size else 0.0
+    return max(norm, ent)
 
 
 def oracle_rhs(pr):

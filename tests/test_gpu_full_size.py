@@ -4,9 +4,11 @@ the benchmark builds it (default options, so the Gram kernel that applies the
 operator itself, the autotuned schedule and the graph-chunked solve).
 
 Two checks against the oracle:
-- lockstep: two outer iterations from the same x_k, each compared entry by
-  entry with the oracle's outer iteration (a few seconds each on the host),
-  G, ctil, atil and x_{k+1} within 1e-10 relative, ||r_k|| within 1e-12;
+- lockstep: two outer iterations from the same x_k, each compared with the
+  oracle's outer iteration (a few seconds each on the host): G, ctil, atil and
+  x_{k+1} within 1e-10 relative both norm-wise and entry by entry (every
+  |difference| within 1e-10 of the vector's largest entry), ||r_k|| within
+  1e-12, and the Gram diagnostics delta_k and ||L||_F;
 - free-running: the solve stops within 5% (at least one) of the oracle's
   outer-iteration count for the same problem (tests/golden/c2_oracle.json,
   written by tests/golden/make_golden.py --c2 from the oracle alone), its
@@ -65,6 +67,9 @@ def test_full_size_lockstep_matches_oracle(hip, c2):
             assert abs(g["rnorm"] - o["rnorm"]) <= 1e-12 * o["rnorm"], k
             for key in ("G", "ctil", "atil"):
                 assert rel(g[key], o[key]) <= 1e-10, (k, key, rel(g[key], o[key]))
+            d = sv.last_iteration()
+            assert abs(d["lnorm"] - o["lnorm"]) <= 1e-10 * o["lnorm"], (k, d["lnorm"], o["lnorm"])
+            assert abs(d["delta"] - o["delta"]) <= 1e-8 * o["delta"], (k, d["delta"], o["delta"])
             x = host(g["x"])
             assert rel(x, o["x"]) <= 1e-10, k
 
@@ -178,3 +183,67 @@ def test_full_size_csr_matches_oracle(hip, c2):
         x, st = sv.solve(bt, None, 1e-8)
     assert st.status == 0
     assert np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b) <= 1e-8
+
+
+@pytest.mark.parametrize("s,nu", gen.config3_sweep())
+@pytest.mark.parametrize("precision", ["fp64", "fp32ir"])
+def test_full_size_c3_sweep_pair(hip, c2, s, nu, precision):
+    """The mixed-precision sweep at the 224^3 problem's full size, every
+    (s, nu) pair in both precisions, with the solver built as the benchmark
+    builds it (default Gram kind and autotuned schedule for the pair): the
+    true relative residual, recomputed by the oracle in FP64, reaches 1e-8.
+    For FP32+IR the FP32 inner error of the first outer iteration is measured
+    against the oracle's FP64 step from the same x_0 = 0 (lockstep):
+    ||dx32 - dx64|| / ||dx64|| and ||G32 - G64|| / ||G64|| (reported, and
+    bounded by 1e-4 as a sanity gate)."""
+    pr, A, b = c2
+    bt = t64(b)
+    with hip.Solver(hip.Operator.stencil(N, N, N), s, nu, pr.lmin, pr.lmax, precision=precision) as sv:
+        x, st = sv.solve(bt, None, 1e-8)
+        assert st.status == 0
+        true_rel = np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b)
+        assert true_rel <= 1e-8, (s, nu, precision, true_rel)
+        if precision == "fp32ir":
+            g = sv.step(bt, t64(np.zeros(pr.n)))
+            o = oracle.step(A, b, np.zeros(pr.n), s, nu, pr.lmin, pr.lmax)
+            dx = np.linalg.norm(host(g["x"]) - o["x"]) / np.linalg.norm(o["x"])
+            dG = np.linalg.norm(g["G"] - o["G"]) / np.linalg.norm(o["G"])
+            print(f"s={s} nu={nu}: {st.outer_iters} outer, FP32 inner error dx {dx:.2e}, G {dG:.2e}")
+            assert dx <= 1e-4 and dG <= 1e-4, (dx, dG)
+        else:
+            print(f"s={s} nu={nu}: {st.outer_iters} outer (FP64)")
+
+
+C5_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle_grad.json")
+
+
+def test_full_size_c5_gradient_matches_oracle(hip):
+    """The differentiable solve at its full size (128^3 faces, sigma 0.5):
+    the autograd gradient (forward and adjoint at tol 1e-12) against the
+    oracle's reference gradient (tests/golden/c5_oracle_grad.json, written by
+    tests/golden/make_golden.py --c5 from the oracle alone), entry by entry at
+    the fixture's sampled positions and through the full vectors' norms; the
+    error at the benchmark tolerance 1e-8 is reported."""
+    with open(C5_GOLDEN) as f:
+        ref = json.load(f)
+    assert ref["status"] == [0, 0]
+    pr = gen.config5(0)
+    nx, ny, nz = pr.dims
+    ik, iv = np.asarray(ref["idx_k"]), np.asarray(ref["idx_v"])
+    op = hip.Operator.stencil(nx, ny, nz, pr.kx, pr.ky, pr.kz)
+    errs = {}
+    with hip.Solver(op, pr.s, pr.nu, pr.lmin, pr.lmax) as sv:
+        for tol in (1e-12, 1e-8):
+            coeffs = t64(np.concatenate([pr.kx, pr.ky, pr.kz])).requires_grad_(True)
+            bt = t64(pr.rhs[0]).requires_grad_(True)
+            x = hip.sstep_solve(coeffs, bt, sv, tol)
+            (0.5 * torch.sum((x - t64(pr.xtarget)) ** 2)).backward()
+            gk, gb, xh = host(coeffs.grad), host(bt.grad), host(x)
+            errs[tol] = dict(x=rel(xh[iv], ref["x"]), lam=rel(gb[iv], ref["lam"]), dk=rel(gk[ik], ref["dk"]),
+                             norm_dk=abs(np.linalg.norm(gk) - ref["norm_dk"]) / ref["norm_dk"],
+                             norm_lam=abs(np.linalg.norm(gb) - ref["norm_lam"]) / ref["norm_lam"])
+    print(f"128^3 gradient vs oracle: tol 1e-12 {errs[1e-12]}; tol 1e-8 {errs[1e-8]}")
+    e = errs[1e-12]
+    assert e["x"] <= 1e-8 and e["lam"] <= 1e-7 and e["dk"] <= 1e-7, e
+    assert e["norm_dk"] <= 1e-8 and e["norm_lam"] <= 1e-8, e
+    assert errs[1e-8]["dk"] <= 1e-3, errs[1e-8]

@@ -195,3 +195,30 @@ def test_adjoint_equals_forward_on_same_rhs(hip):
         x1, s1 = sv.solve(t64(b))
         x2, s2 = sv.solve_adjoint(t64(b))
     assert torch.equal(x1, x2) and s1.outer_iters == s2.outer_iters
+
+
+def test_autograd_two_forwards_then_two_backwards(hip):
+    """One solver shared by two differentiable solves with different
+    coefficients: both forwards run before either backward, so the second
+    forward has loaded its coefficients into the solver; each backward must
+    still solve the adjoint with its own forward's operator.  Each gradient is
+    checked against the oracle's (forward and adjoint at tol 1e-12)."""
+    N = 16
+    pa = gen.config5(0, N=N)
+    pb = gen.config5(1, N=N)
+    op = hip.Operator.stencil(N, N, N, pa.kx, pa.ky, pa.kz)
+    refs = [_loss_grads_oracle(p, p.rhs[0], p.xtarget, 1e-12) for p in (pa, pb)]
+    with hip.Solver(op, pa.s, pa.nu, pa.lmin, pa.lmax) as sv:
+        cs, bs, losses = [], [], []
+        for p in (pa, pb):
+            c = t64(np.concatenate([p.kx, p.ky, p.kz])).requires_grad_(True)
+            bt = t64(p.rhs[0]).requires_grad_(True)
+            x = hip.sstep_solve(c, bt, sv, 1e-12)
+            losses.append(0.5 * torch.sum((x - t64(p.xtarget)) ** 2))
+            cs.append(c)
+            bs.append(bt)
+        losses[0].backward()
+        losses[1].backward()
+    for c, bt, (x_o, lam_o, g_o) in zip(cs, bs, refs):
+        assert rel(host(bt.grad), lam_o) <= 1e-7
+        assert rel(host(c.grad), g_o) <= 1e-7

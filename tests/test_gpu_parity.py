@@ -73,6 +73,11 @@ def test_lockstep_outer_iterations_fp64(hip, name):
             assert rel(g["atil"], o["atil"]) <= 1e-10, (k, rel(g["atil"], o["atil"]))
             xn = host(g["x"])
             assert rel(xn, o["x"]) <= 1e-10, k
+            # Gram diagnostics of the same iteration (Sec. 7 delta, Sec. 4 ||L||_F)
+            d = sv.last_iteration()
+            assert abs(d["rnorm"] - o["rnorm"]) <= 1e-12 * o["rnorm"], k
+            assert abs(d["lnorm"] - o["lnorm"]) <= 1e-10 * o["lnorm"], (k, d["lnorm"], o["lnorm"])
+            assert abs(d["delta"] - o["delta"]) <= 1e-8 * o["delta"] + 1e-14, (k, d["delta"], o["delta"])
             if k == 0:
                 P, AP = host(g["P"]), host(g["AP"])
                 for j in range(s):
@@ -87,11 +92,18 @@ def test_free_running_solve_fp64(hip, name, chunk):
     make, form, s, nu = CASES[name]
     pr = make()
     A, b = oracle_rhs(pr)
-    ref = oracle.solve(A, b, None, s, nu, pr.lmin, pr.lmax, 1e-8)
+    ref = oracle.solve(A, b, None, s, nu, pr.lmin, pr.lmax, 1e-8, hist_cap=2000)
     assert ref["status"] == 0
     with hip.Solver(make_operator(hip, pr, form), s, nu, pr.lmin, pr.lmax, graph_chunk=chunk,
                     record_history=True) as sv:
         x, st = sv.solve(t64(b), None, 1e-8, history=True)
+    # per-update Gram diagnostics follow the oracle's while the trajectories
+    # agree (the first three updates)
+    assert st.hist_delta.shape == st.hist_lnorm.shape == (st.outer_iters,)
+    for k in range(3):
+        assert abs(st.hist_lnorm[k] - ref["hist_lnorm"][k]) <= 1e-9 * ref["hist_lnorm"][k], k
+        assert abs(st.hist_delta[k] - ref["hist_delta"][k]) <= 1e-7 * ref["hist_delta"][k] + 1e-14, k
+    assert np.all(st.hist_delta > 0) and np.all(st.hist_lnorm > 0)
     xh = host(x)
     true_rel = np.linalg.norm(b - oracle.spmv(A, xh)) / np.linalg.norm(b)
     assert true_rel <= 1e-8

@@ -555,3 +555,75 @@ def test_golden_c1_trajectory_unchanged():
     first = oracle.step(A, b, np.zeros(pr.n), pr.s, pr.nu, pr.lmin, pr.lmax)
     assert np.allclose(first["atil"], g["atil_first"], rtol=1e-13, atol=0)
     assert (g["lmin"], g["lmax"]) == (pr.lmin, pr.lmax)
+
+
+# ---------------------------------------------------------------------------
+# Gram diagnostics: delta_k (Sec. 7), ||L||_F (Sec. 4), kappa(G) (Sec. 4, 8)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["poisson3d", "faces3d", "poisson2d"])
+@pytest.mark.parametrize("nu", [1, 2, 7])
+def test_delta_is_residual_structure_of_last_sweep(kind, nu):
+    """delta_k = ||ctil - G atil|| / ||ctil|| must equal, by the FGS residual
+    structure (Sec. 3, Proposition), ||L^T (atil^(nu-1) - atil^(nu))|| / ||ctil||
+    with atil^(0) = 0: at nu = 1 that is ||L^T atil^(1)|| / ||ctil||.  The two
+    sweep counts come from the oracle's FGS; the step's own delta is computed
+    as a residual, so a dropped term, G_raw in place of G or the wrong
+    denominator in either breaks the equality."""
+    pr, A, b = small_problem(kind, seed=5)
+    out = oracle.step(A, b, np.zeros(pr.n), 6, nu, pr.lmin, pr.lmax)
+    assert out["status"] == 0
+    G, ct = out["G"], out["ctil"]
+    L = np.tril(G, -1)
+    prev = oracle.fgs(G, ct, nu - 1) if nu > 1 else np.zeros(6)
+    last = oracle.fgs(G, ct, nu)
+    assert np.array_equal(last, out["atil"])
+    want = np.linalg.norm(L.T @ (prev - last)) / np.linalg.norm(ct)
+    assert abs(out["delta"] - want) <= 1e-13 * max(want, 1e-3), (out["delta"], want)
+    assert out["delta"] > 0
+
+
+@pytest.mark.parametrize("kind", ["poisson3d", "faces3d", "poisson2d"])
+def test_lnorm_from_frobenius_identity(kind):
+    """||L||_F with G = I + L + L^T (Sec. 4): ||G||_F^2 = s + 2 ||L||_F^2, an
+    identity independent of how L is read off G; the solve's per-update history
+    equals the step's value at the same iterate."""
+    pr, A, b = small_problem(kind, seed=6)
+    s = 6
+    out = oracle.step(A, b, np.zeros(pr.n), s, 10, pr.lmin, pr.lmax)
+    G = out["G"]
+    want = math.sqrt((np.sum(G * G) - s) / 2)
+    assert abs(out["lnorm"] - want) <= 1e-13 * want
+    sol = oracle.solve(A, b, None, s, 10, pr.lmin, pr.lmax, 1e-10, hist_cap=200)
+    assert sol["hist_lnorm"][0] == out["lnorm"]
+    assert sol["hist_delta"][0] == out["delta"]
+
+
+def test_lnorm_grows_like_sqrt_s():
+    """Sec. 4, Theorem "Polynomial Growth": with column scaling the Chebyshev
+    Gram matrix has ||L||_F = O(sqrt(s)).  On an operator whose spectrum fills
+    the Chebyshev interval [0, 2] (a diagonal matrix, no preconditioner, so the
+    bounds are exact) ||L||_F^2 / s must stay bounded and flat as s grows from
+    4 to 32 (the monomial basis would grow exponentially)."""
+    n = 4000
+    lam = np.linspace(0.0, 2.0, n + 2)[1:-1]
+    A = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), lam.copy())
+    ratios = []
+    for s in (4, 8, 16, 32):
+        out = oracle.step(A, np.ones(n), np.zeros(n), s, 5, 0.0, 2.0, precond=0)
+        assert out["status"] == 0
+        ratios.append(out["lnorm"] ** 2 / s)
+    assert max(ratios) <= 0.5, ratios
+    assert max(ratios) / min(ratios) <= 1.2, ratios
+
+
+def test_gram_condition_closed_form():
+    """kappa of the tridiagonal Toeplitz matrix I + a (E + E^T), whose
+    eigenvalues are 1 + 2a cos(k pi / (s + 1)), k = 1..s (textbook)."""
+    for s, a in [(5, 0.3), (16, 0.45), (32, -0.2)]:
+        G = np.eye(s) + a * (np.eye(s, k=1) + np.eye(s, k=-1))
+        ev = 1 + 2 * a * np.cos(np.arange(1, s + 1) * math.pi / (s + 1))
+        want = ev.max() / ev.min()
+        assert abs(oracle.gram_condition(G) - want) <= 1e-12 * want
+    assert oracle.gram_condition(np.array([[1.0, 1.0], [1.0, 1.0]])) == float("inf") or \
+        oracle.gram_condition(np.array([[1.0, 1.0], [1.0, 1.0]])) > 1e15
