@@ -30,8 +30,9 @@ import numpy as np
 __all__ = [
     "rng", "uniform", "poisson2d_csr", "poisson3d_csr", "faces3d_csr",
     "face_coefficients", "jacobi_poisson_bounds", "gershgorin_jacobi_bounds",
-    "Problem", "config1", "config2", "config3_sweep", "config4", "config5",
-    "small_poisson3d", "small_faces3d", "CONFIGS",
+    "poisson27_csr", "jacobi_poisson27_bounds",
+    "Problem", "config1", "config2", "config3_sweep", "config4", "config5", "paper27",
+    "small_poisson3d", "small_faces3d", "small_poisson27", "CONFIGS",
 ]
 
 
@@ -112,6 +113,25 @@ def faces3d_csr(nx: int, ny: int, nz: int, kx, ky, kz):
     return _csr_from_bands(n, cols, vals, mask)
 
 
+def poisson27_csr(nx: int, ny: int, nz: int):
+    """27-point Dirichlet operator: diagonal 26 and -1 for each of the 26
+    neighbours of the 3 x 3 x 3 box inside the grid (columns ascending)."""
+    n = nx * ny * nz
+    p = np.arange(n, dtype=np.int64)
+    i = p % nx
+    j = (p // nx) % ny
+    k = p // (nx * ny)
+    cols, vals, masks = [], [], []
+    for dk in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                cols.append(p + di + nx * (dj + ny * dk))
+                vals.append(np.full(n, 26.0 if (di, dj, dk) == (0, 0, 0) else -1.0))
+                masks.append((i + di >= 0) & (i + di < nx) & (j + dj >= 0) & (j + dj < ny)
+                             & (k + dk >= 0) & (k + dk < nz))
+    return _csr_from_bands(n, np.stack(cols, axis=1), np.stack(vals, axis=1), np.stack(masks, axis=1))
+
+
 def face_coefficients(r: np.random.Generator, nx: int, ny: int, nz: int, sigma: float):
     """Log-normal face coefficients ``k_f = exp(sigma * Z)``, ``Z ~ N(0, 1)``,
     boundary faces included; drawn in the order kx, ky, kz (C order)."""
@@ -134,6 +154,19 @@ def jacobi_poisson_bounds(*dims: int):
     d = len(dims)
     c = sum(math.cos(math.pi / (na + 1)) for na in dims) / d
     return 1.0 - c, 1.0 + c
+
+
+def jacobi_poisson27_bounds(nx: int, ny: int, nz: int):
+    """Exact extreme eigenvalues of ``D^{-1} A`` for the 27-point operator
+    ``A = 27 I - T_x (x) T_y (x) T_z`` (``T`` = tridiag(1, 1, 1), eigenvalues
+    ``1 + 2 cos(m pi/(N+1))``), diagonal 26: ``(27 - prod_a f_a) / 26``.  The
+    product is multilinear in the three factors, so its extremes over the
+    factor ranges ``[1 - 2c_a, 1 + 2c_a]``, ``c_a = cos(pi/(N_a+1))``, sit at
+    the 8 corners."""
+    c = [math.cos(math.pi / (na + 1)) for na in (nx, ny, nz)]
+    prods = [a * b * d for a in (1 - 2 * c[0], 1 + 2 * c[0]) for b in (1 - 2 * c[1], 1 + 2 * c[1])
+             for d in (1 - 2 * c[2], 1 + 2 * c[2])]
+    return (27.0 - max(prods)) / 26.0, (27.0 - min(prods)) / 26.0
 
 
 def gershgorin_jacobi_bounds():
@@ -170,6 +203,7 @@ class Problem:
     xstar: np.ndarray | None = None
     rhs: list = field(default_factory=list)
     xtarget: np.ndarray | None = None
+    stencil: int = 7
     _csr: tuple | None = None
 
     @property
@@ -180,6 +214,8 @@ class Problem:
         if self._csr is None:
             if len(self.dims) == 2:
                 self._csr = poisson2d_csr(*self.dims)
+            elif self.stencil == 27:
+                self._csr = poisson27_csr(*self.dims)
             else:
                 self._csr = faces3d_csr(*self.dims, self.kx, self.ky, self.kz)
         return self._csr
@@ -236,6 +272,26 @@ def config5(seed: int = 0, N: int = 128, sigma: float = 0.5, s: int = 16, nu: in
     pr.rhs = [uniform(r, pr.n)]
     pr.xtarget = uniform(r, pr.n)
     return pr
+
+
+def paper27(seed: int = 0, N: int = 230, s: int = 20, nu: int = 30) -> Problem:
+    """The paper's own workload (Sec. 8): 3D Poisson on the unit cube with a
+    27-point stencil, Dirichlet boundary, 230^3 = 12,167,000 unknowns (about
+    12.2M per GPU), s in {10, 20}, nu in {6, 15, 30}; x* ~ U[-1, 1], b = A x*.
+    The bounds given here are the exact Jacobi bounds; the paper's runs take
+    them from 10 Lanczos steps with a 10% margin."""
+    r = rng(seed)
+    lmin, lmax = jacobi_poisson27_bounds(N, N, N)
+    return Problem(f"paper27_poisson3d_{N}", "stencil", (N, N, N), s, nu, lmin, lmax, xstar=uniform(r, N ** 3),
+                   stencil=27)
+
+
+def small_poisson27(nx: int, ny: int, nz: int, seed: int = 0, s: int = 8, nu: int = 25) -> Problem:
+    """Small 27-point Poisson problem (exact Jacobi bounds), x* ~ U[-1, 1]."""
+    r = rng(seed)
+    lmin, lmax = jacobi_poisson27_bounds(nx, ny, nz)
+    return Problem(f"poisson27_{nx}x{ny}x{nz}", "stencil", (nx, ny, nz), s, nu, lmin, lmax,
+                   xstar=uniform(r, nx * ny * nz), stencil=27)
 
 
 def small_poisson3d(nx: int, ny: int, nz: int, seed: int = 0, s: int = 8, nu: int = 25) -> Problem:

@@ -55,8 +55,9 @@ typedef enum {
 } sstep_status;
 
 typedef enum {
-    SSTEP_OP_CSR = 0,      /* general sparse SPD matrix, CSR */
-    SSTEP_OP_STENCIL7 = 1  /* matrix-free 7-point operator on a 3D grid */
+    SSTEP_OP_CSR = 0,       /* general sparse SPD matrix, CSR */
+    SSTEP_OP_STENCIL7 = 1,  /* matrix-free 7-point operator on a 3D grid */
+    SSTEP_OP_STENCIL27 = 2  /* matrix-free 27-point operator on a 3D grid (Sec. 8) */
 } sstep_op_kind;
 
 typedef enum {
@@ -76,6 +77,12 @@ typedef enum {
  *        ky[(k*(ny+1) + j)*nx + i],  kz[(k*ny + j)*nx + i].
  *     kx = ky = kz = NULL selects the constant Poisson operator (every k_f = 1:
  *     diagonal 6, off-diagonal -1).  n and nnz are ignored.
+ *  27-point stencil (kind = SSTEP_OP_STENCIL27): the Poisson operator of the
+ *     paper's experiments (Sec. 8), interior grid nx x ny x nz numbered as
+ *     above, homogeneous Dirichlet boundary: (A u)_p = 26 u_p - sum of u over
+ *     the 26 other points of the 3 x 3 x 3 box around p (u = 0 outside), i.e.
+ *     A = 27 I - T_x (x) T_y (x) T_z with T = tridiag(1, 1, 1).  Constant
+ *     coefficients: kx, ky, kz must be NULL; n and nnz are ignored.
  *  ptr_space: 0 = the arrays are host memory, 1 = device memory.  They are
  *  copied into library memory; the caller may free them on return. */
 typedef struct {
@@ -167,7 +174,8 @@ sstep_status sstep_solve_adjoint(sstep_ctx *ctx, const double *g, double *lam, d
  * accumulate = 1 adds to dA instead of overwriting it. */
 sstep_status sstep_grad_operator(sstep_ctx *ctx, const double *lam, const double *x, double *dA, int32_t accumulate);
 
-/* Number of values sstep_grad_operator writes. */
+/* Number of values sstep_grad_operator writes (0 for the 27-point operator,
+ * which has no coefficients: sstep_grad_operator gives SSTEP_E_UNSUPPORTED). */
 int64_t sstep_grad_size(const sstep_ctx *ctx);
 
 /* Number of unknowns n. */
@@ -183,6 +191,38 @@ int64_t sstep_n(const sstep_ctx *ctx);
  * parity tests. */
 sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alpha_tilde, double *G, double *ctil,
                         double *rnorm, double *P_out, double *AP_out);
+
+/* Lanczos estimate of the spectrum of M^{-1}A, the interval the Chebyshev
+ * basis needs (Sec. 2, Definition: [lambda_min, lambda_max] must enclose it;
+ * Sec. 8, setup: a few Lanczos steps give the extreme eigenvalues).  M^{-1}A
+ * is self-adjoint in the M-inner product, so the recurrence runs on
+ * M-orthonormal vectors from the start vector u (device, n doubles, not
+ * modified):
+ *   z_0 = u / ||u||_M;  alpha_j = z_j^T A z_j;
+ *   w = M^{-1} A z_j - alpha_j z_j - beta_j z_{j-1};  beta_{j+1} = ||w||_M;
+ *   z_{j+1} = w / beta_{j+1}
+ * for up to steps in [1, 64] steps, no reorthogonalisation, stopping early
+ * when beta_{j+1} <= 1e-13 max |alpha_i| or is not finite (m steps done).
+ * The Ritz values are the eigenvalues of T_m = tridiag(beta; alpha; beta),
+ * computed on the device by bisection.  Host outputs (each may be NULL),
+ * steps entries each, zero beyond m: alpha, beta (beta[i] = beta_{i+1}, below
+ * row i of T_m), ritz (ascending); m_out = m.  Runs on the context's stream;
+ * the vectors use the basis storage P when it holds 3n doubles (P is scratch
+ * between solves), otherwise 3n doubles allocated on the first call and kept
+ * until sstep_destroy.  SSTEP_E_ARG for a zero start vector. */
+sstep_status sstep_lanczos(sstep_ctx *ctx, const double *u, int32_t steps, double *alpha, double *beta,
+                           double *ritz, int32_t *m_out);
+
+/* Replaces the Chebyshev bounds 0 <= lambda_min < lambda_max of the context
+ * (the outer-iteration graph is captured again). */
+sstep_status sstep_set_bounds(sstep_ctx *ctx, double lambda_min, double lambda_max);
+
+/* sstep_lanczos from u, then the bounds with a relative safety margin in
+ * [0, 1) (Sec. 8: 10%): lambda_min = max(0, (1 - margin) theta_min),
+ * lambda_max = (1 + margin) theta_max for the extreme Ritz values, set on the
+ * context as by sstep_set_bounds and returned (host, may be NULL). */
+sstep_status sstep_lanczos_bounds(sstep_ctx *ctx, const double *u, int32_t steps, double margin,
+                                  double *lambda_min, double *lambda_max);
 
 /* Diagnostics of the last outer iteration of the last sstep_step or solve on
  * ctx (host outputs, each may be NULL): rnorm = ||b - A x_k|| of its residual,

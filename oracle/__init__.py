@@ -40,6 +40,10 @@ def _load():
         _lib.oracle_stencil7_nnz.argtypes = [i32, i32, i32]
         _lib.oracle_assemble_stencil7.restype = i64
         _lib.oracle_assemble_stencil7.argtypes = [i32, i32, i32, pd, pd, pd, pi, pi, pd]
+        _lib.oracle_stencil27_nnz.restype = i64
+        _lib.oracle_stencil27_nnz.argtypes = [i32, i32, i32]
+        _lib.oracle_assemble_stencil27.restype = i64
+        _lib.oracle_assemble_stencil27.argtypes = [i32, i32, i32, pi, pi, pd]
         _lib.oracle_jacobi.restype = C.c_int
         _lib.oracle_jacobi.argtypes = [i64, pi, pi, pd, C.c_int, pd, pd]
         _lib.oracle_chebyshev_basis.restype = None
@@ -56,6 +60,8 @@ def _load():
         _lib.oracle_sstep_solve.restype = C.c_int
         _lib.oracle_sstep_solve.argtypes = [i64, pi, pi, pd, pd, pd, C.c_int, C.c_int, d, d, d, C.c_int, C.c_int,
                                             C.c_int, C.POINTER(C.c_int), pd, pd, pd, pd, pd, C.c_int]
+        _lib.oracle_lanczos.restype = C.c_int
+        _lib.oracle_lanczos.argtypes = [i64, pi, pi, pd, C.c_int, pd, C.c_int, pd, pd]
         _lib.oracle_grad_csr.restype = None
         _lib.oracle_grad_csr.argtypes = [i64, pi, pi, pd, pd, pd]
         _lib.oracle_grad_faces.restype = None
@@ -114,6 +120,20 @@ def assemble_stencil7(nx, ny, nz, kx=None, ky=None, kz=None):
     v = np.empty(nnz)
     kx, ky, kz = _f64(kx), _f64(ky), _f64(kz)
     got = lib.oracle_assemble_stencil7(nx, ny, nz, _pd(kx), _pd(ky), _pd(kz), _pi(rp), _pi(ci), _pd(v))
+    assert got == nnz
+    return rp, ci, v
+
+
+def assemble_stencil27(nx, ny, nz):
+    """CSR of the 27-point operator (diagonal 26, -1 on the 26 neighbours of
+    the 3 x 3 x 3 box inside the grid), assembled by the oracle."""
+    lib = _load()
+    n = nx * ny * nz
+    nnz = lib.oracle_stencil27_nnz(nx, ny, nz)
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    v = np.empty(nnz)
+    got = lib.oracle_assemble_stencil27(nx, ny, nz, _pi(rp), _pi(ci), _pd(v))
     assert got == nnz
     return rp, ci, v
 
@@ -214,6 +234,32 @@ def solve(A, b, x0, s, nu, lmin, lmax, tol, max_outer=10000, precond=1, p0_mode=
     return out
 
 
+def lanczos(A, u, steps, precond=1):
+    """Lanczos on M^{-1}A in the M-inner product (Sec. 8 setup) from start
+    vector ``u``: returns dict ``alpha``, ``beta`` (length m <= steps, beta[i]
+    below row i), the Ritz values ``ritz`` (eigenvalues of the m x m
+    tridiagonal T_m, ascending; LAPACK's symmetric tridiagonal solver as the
+    step) and ``m``."""
+    rp, ci, v = _csr(A)
+    n = rp.size - 1
+    al = np.zeros(steps)
+    be = np.zeros(steps)
+    m = _load().oracle_lanczos(n, _pi(rp), _pi(ci), _pd(v), precond, _pd(_f64(u)), steps, _pd(al), _pd(be))
+    al, be = al[:m], be[:m]
+    if m == 0:
+        ritz = np.zeros(0)
+    else:
+        import scipy.linalg
+        ritz = scipy.linalg.eigvalsh_tridiagonal(al, be[:m - 1]) if m > 1 else al.copy()
+    return dict(alpha=al, beta=be, ritz=np.sort(ritz), m=m)
+
+
+def lanczos_bounds(ritz, margin=0.1):
+    """Chebyshev bounds from the extreme Ritz values with a relative safety
+    margin (Sec. 8: 10%): [(1 - margin) theta_min, (1 + margin) theta_max]."""
+    return (1.0 - margin) * float(ritz[0]), (1.0 + margin) * float(ritz[-1])
+
+
 def gram_condition(G) -> float:
     """2-norm condition number of a symmetric positive definite Gram matrix
     (Sec. 4 and the measured values of Sec. 8), from its extreme eigenvalues
@@ -246,4 +292,6 @@ def problem_csr(pr):
     if len(pr.dims) == 2:
         return _csr(pr.csr())
     nx, ny, nz = pr.dims
+    if getattr(pr, "stencil", 7) == 27:
+        return assemble_stencil27(nx, ny, nz)
     return assemble_stencil7(nx, ny, nz, pr.kx, pr.ky, pr.kz)

@@ -157,6 +157,45 @@ int64_t oracle_assemble_stencil7(int32_t nx, int32_t ny, int32_t nz, const doubl
     return nnz;
 }
 
+/* Number of stored entries of the 27-point operator on an nx x ny x nz grid:
+ * every point couples to the in-grid points of its 3 x 3 x 3 box. */
+int64_t oracle_stencil27_nnz(int32_t nx, int32_t ny, int32_t nz)
+{
+    /* per axis, the number of (point, offset in {-1, 0, 1}) pairs in the grid */
+    const int64_t px = 3 * (int64_t)nx - 2, py = 3 * (int64_t)ny - 2, pz = 3 * (int64_t)nz - 2;
+    return px * py * pz;
+}
+
+/* Assemble the 27-point Dirichlet operator of an nx x ny x nz interior grid
+ * (x fastest) as CSR: A = 27 I - (T_x (x) T_y (x) T_z) with T = tridiag(1, 1, 1)
+ * on each axis, i.e. diagonal 26 and -1 for each of the 26 neighbours of the
+ * 3 x 3 x 3 box that lie in the grid (Sec. 8: a 27-point finite-difference
+ * Poisson operator on the unit cube; this is the stencil with those
+ * coefficients).  Columns ascending.  Returns nnz; size the arrays with
+ * oracle_stencil27_nnz. */
+int64_t oracle_assemble_stencil27(int32_t nx, int32_t ny, int32_t nz, int32_t *row_ptr, int32_t *col_idx,
+                                  double *val)
+{
+    int64_t nnz = 0;
+    row_ptr[0] = 0;
+    for (int32_t k = 0; k < nz; ++k)
+        for (int32_t j = 0; j < ny; ++j)
+            for (int32_t i = 0; i < nx; ++i) {
+                const int64_t p = i + nx * ((int64_t)j + (int64_t)ny * k);
+                for (int dk = -1; dk <= 1; ++dk)
+                    for (int dj = -1; dj <= 1; ++dj)
+                        for (int di = -1; di <= 1; ++di) {
+                            const int32_t a = i + di, b = j + dj, c = k + dk;
+                            if (a < 0 || a >= nx || b < 0 || b >= ny || c < 0 || c >= nz)
+                                continue;
+                            col_idx[nnz] = (int32_t)(a + nx * ((int64_t)b + (int64_t)ny * c));
+                            val[nnz++] = (di == 0 && dj == 0 && dk == 0) ? 26.0 : -1.0;
+                        }
+                row_ptr[p + 1] = (int32_t)nnz;
+            }
+    return nnz;
+}
+
 /* Preconditioner M (Sec. 2): Jacobi M = diag(A) when precond = 1, identity
  * when precond = 0.  Writes invd = M^{-1} diagonal and dvec = M diagonal.
  * Returns ORACLE_E_ARG if a diagonal entry is missing or not positive. */
@@ -567,4 +606,82 @@ void oracle_grad_faces(int32_t nx, int32_t ny, int32_t nz, const double *lam, co
                     g = -(lam[p - nxy] - lam[p]) * (x[p - nxy] - x[p]);
                 dkz[((int64_t)k * ny + j) * nx + i] = g;
             }
+}
+
+/* ---------------------------------------------------------------------------
+ * Spectrum bounds for the Chebyshev basis by Lanczos (Sec. 8, setup of the
+ * experiments: a few Lanczos steps give the extreme eigenvalues of M^{-1}A,
+ * widened by a safety margin).
+ *
+ * M^{-1}A is self-adjoint in the M-inner product <u, v>_M = u^T M v, so the
+ * Lanczos recurrence runs on M-orthonormal vectors z_j:
+ *     z_0     = u / ||u||_M,                    beta_0 = 0, z_{-1} = 0,
+ *     y       = A z_j,            alpha_j = z_j^T y  (= <z_j, M^{-1}A z_j>_M),
+ *     w       = M^{-1} y - alpha_j z_j - beta_j z_{j-1},
+ *     beta_{j+1} = ||w||_M,       z_{j+1} = w / beta_{j+1}.
+ * T_m = tridiag(beta_1..beta_{m-1}; alpha_0..alpha_{m-1}; beta_1..beta_{m-1})
+ * is the projection of M^{-1}A on the Krylov space; its eigenvalues (Ritz
+ * values) approximate the spectrum from inside.  No reorthogonalisation.
+ * The recurrence stops early (m = j + 1) when beta_{j+1} is not above
+ * 1e-13 max_{i <= j} |alpha_i| (an invariant subspace, to rounding) or not
+ * finite.  Writes alpha[0..m), beta[0..m) (beta[i] = beta_{i+1}, the
+ * off-diagonal below row i; beta[m-1] is the value that stopped it or the
+ * last one), returns m (0 for invalid arguments or a zero start vector).
+ * ------------------------------------------------------------------------- */
+int oracle_lanczos(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val, int precond,
+                   const double *u, int steps, double *alpha, double *beta)
+{
+    if (n < 1 || !u || steps < 1 || !alpha || !beta)
+        return 0;
+    double *invd = (double *)malloc(sizeof(double) * n);
+    double *dvec = (double *)malloc(sizeof(double) * n);
+    double *zprev = (double *)calloc((size_t)n, sizeof(double));
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *y = (double *)malloc(sizeof(double) * n);
+    int m = 0;
+    if (!invd || !dvec || !zprev || !z || !y)
+        goto out;
+    if (oracle_jacobi(n, row_ptr, col_idx, val, precond, invd, dvec) != ORACLE_OK)
+        goto out;
+    {
+        /* z_0 = u / ||u||_M */
+        nsum_t acc = {0.0, 0.0};
+        for (int64_t i = 0; i < n; ++i)
+            nsum_add(&acc, dvec[i] * u[i] * u[i]);
+        const double un = sqrt(nsum_value(&acc));
+        if (!(un > 0.0) || !isfinite(un))
+            goto out;
+        for (int64_t i = 0; i < n; ++i)
+            z[i] = u[i] / un;
+    }
+    double bj = 0.0, amax = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        oracle_spmv(n, row_ptr, col_idx, val, z, y); /* y = A z_j */
+        const double aj = oracle_dot(n, z, y);
+        alpha[j] = aj;
+        if (fabs(aj) > amax)
+            amax = fabs(aj);
+        nsum_t acc = {0.0, 0.0};
+        for (int64_t i = 0; i < n; ++i) {
+            y[i] = invd[i] * y[i] - aj * z[i] - bj * zprev[i]; /* w */
+            nsum_add(&acc, dvec[i] * y[i] * y[i]);
+        }
+        const double bn = sqrt(nsum_value(&acc));
+        beta[j] = bn;
+        m = j + 1;
+        if (!(bn > 1e-13 * amax) || !isfinite(bn))
+            break;
+        for (int64_t i = 0; i < n; ++i) {
+            zprev[i] = z[i];
+            z[i] = y[i] / bn;
+        }
+        bj = bn;
+    }
+out:
+    free(invd);
+    free(dvec);
+    free(zprev);
+    free(z);
+    free(y);
+    return m;
 }

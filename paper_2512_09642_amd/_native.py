@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsstep.so
 SSTEP_OK = 0
 STATUS_NAMES = {0: "SSTEP_OK", 1: "SSTEP_E_ARG", 2: "SSTEP_E_HIP", 3: "SSTEP_E_NOMEM", 4: "SSTEP_E_BREAKDOWN",
                 5: "SSTEP_E_NOCONV", 6: "SSTEP_E_NONFINITE", 7: "SSTEP_E_UNSUPPORTED"}
-OP_CSR, OP_STENCIL7 = 0, 1
+OP_CSR, OP_STENCIL7, OP_STENCIL27 = 0, 1, 2
 FP64, FP32_IR = 0, 1
 GRAM_KINDS = {"auto": 0, "stored": 1, "apply": 2}
 KT_NAMES = ("residual", "basis", "gram", "fgs", "update")
@@ -20,7 +20,7 @@ KT_NAMES = ("residual", "basis", "gram", "fgs", "update")
 EXPORTS = (
     "sstep_default_options", "sstep_setup", "sstep_update_coefficients", "sstep_apply", "sstep_solve",
     "sstep_solve_adjoint", "sstep_grad_operator", "sstep_grad_size", "sstep_n", "sstep_step",
-    "sstep_last_iteration", "sstep_kernel_times", "sstep_gram_mode", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
+    "sstep_lanczos", "sstep_set_bounds", "sstep_lanczos_bounds", "sstep_last_iteration", "sstep_kernel_times", "sstep_gram_mode", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
     "sstep_status_string", "sstep_destroy",
 )
 
@@ -89,6 +89,12 @@ def load():
     lib.sstep_n.restype = C.c_int64
     lib.sstep_step.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.sstep_step.restype = st
+    lib.sstep_lanczos.argtypes = [P, P, C.c_int32, P, P, P, P]
+    lib.sstep_lanczos.restype = st
+    lib.sstep_set_bounds.argtypes = [P, C.c_double, C.c_double]
+    lib.sstep_set_bounds.restype = st
+    lib.sstep_lanczos_bounds.argtypes = [P, P, C.c_int32, C.c_double, P, P]
+    lib.sstep_lanczos_bounds.restype = st
     lib.sstep_last_iteration.argtypes = [P, P, P, P]
     lib.sstep_last_iteration.restype = st
     lib.sstep_kernel_times.argtypes = [P, P, P, C.c_int32, P]

@@ -47,6 +47,8 @@ struct sstep_ctx {
     int64_t grad_size = 0;
     int *bad_flag = nullptr;       // device flag of the diagonal check
     char *ap_step = nullptr;       // A P of sstep_step when AP is not kept (allocated on first use)
+    LzArgs lz;                     // Lanczos workspace (vectors: P's storage, or allocated on first use)
+    double *lz_vecs = nullptr;
     struct Batched *batch = nullptr;  // set for contexts made by sstep_setup_batched
     std::string err;
 };
@@ -164,6 +166,15 @@ sstep_status check_operator(sstep_ctx *ctx, const sstep_operator *A)
         const int given = (A->kx != nullptr) + (A->ky != nullptr) + (A->kz != nullptr);
         if (given != 0 && given != 3)
             return fail(ctx, SSTEP_E_ARG, "give all three face arrays kx, ky, kz or none");
+        return SSTEP_OK;
+    }
+    if (A->kind == SSTEP_OP_STENCIL27) {
+        if (A->nx < 1 || A->ny < 1 || A->nz < 1)
+            return fail(ctx, SSTEP_E_ARG, "stencil grid sizes must be >= 1");
+        if (int64_t(A->nx) * A->ny * A->nz >= (int64_t(1) << 31))
+            return fail(ctx, SSTEP_E_ARG, "stencil grid too large (n must be < 2^31)");
+        if (A->kx || A->ky || A->kz)
+            return fail(ctx, SSTEP_E_ARG, "the 27-point operator takes no coefficient arrays");
         return SSTEP_OK;
     }
     if (A->kind == SSTEP_OP_CSR) {
@@ -671,14 +682,14 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     // the stored-AP kernel is as fast).
     bool gram_op = false;
     {
-        const int64_t n = A->kind == SSTEP_OP_STENCIL7 ? int64_t(A->nx) * A->ny * A->nz : A->n;
+        const int64_t n = A->kind == SSTEP_OP_CSR ? A->n : int64_t(A->nx) * A->ny * A->nz;
         const uint64_t wbytes = o.precision == SSTEP_FP32_IR ? sizeof(float) : sizeof(double);
         const bool op_ok = A->kind == SSTEP_OP_STENCIL7 && s <= kGoMaxS &&
                            uint64_t(round_up(n, kPad)) * wbytes < (uint64_t(1) << 32);
         if (o.gram == SSTEP_GRAM_APPLY_OP && !op_ok)
             return fail(ctx, SSTEP_E_UNSUPPORTED,
-                        "the operator-applying Gram kernel needs a stencil operator, s <= 16 and columns under "
-                        "4 GiB");
+                        "the operator-applying Gram kernel needs a 7-point stencil operator, s <= 16 and columns "
+                        "under 4 GiB");
         gram_op = o.gram == SSTEP_GRAM_APPLY_OP || (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
     }
 
@@ -707,8 +718,8 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     it.theta = 2.0 / (lmax - lmin);
     it.sigma = (lmax + lmin) / 2.0;
     op.precond = o.precond;
-    if (A->kind == SSTEP_OP_STENCIL7) {
-        op.kind = A->kx ? kOpFaces : kOpPoisson;
+    if (A->kind == SSTEP_OP_STENCIL7 || A->kind == SSTEP_OP_STENCIL27) {
+        op.kind = A->kind == SSTEP_OP_STENCIL27 ? kOpPoisson27 : (A->kx ? kOpFaces : kOpPoisson);
         op.n = int64_t(A->nx) * A->ny * A->nz;
         op.g.nx = A->nx;
         op.g.ny = A->ny;
@@ -716,7 +727,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         op.g.nxy = int64_t(A->nx) * A->ny;
         op.g.dx = make_fastdiv(uint32_t(A->nx));
         op.g.dy = make_fastdiv(uint32_t(A->ny));
-        ctx->grad_size = faces_x(A) + faces_y(A) + faces_z(A);
+        ctx->grad_size = op.kind == kOpPoisson27 ? 0 : faces_x(A) + faces_y(A) + faces_z(A);
     } else {
         op.kind = kOpCsr;
         op.n = A->n;
@@ -734,8 +745,9 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     // right-hand side of the Gram system: c = P^T r with r = M p_0 (p0_mode 0)
     // or r = p_0 (p0_mode 1 or no preconditioner)
     const bool jac_p0 = o.precond == 1 && o.p0_mode == 0;
-    it.wdvec = jac_p0 && op.kind != kOpPoisson;
-    it.cscale = (jac_p0 && op.kind == kOpPoisson) ? 6.0 : 1.0;
+    const bool const_diag = op.kind == kOpPoisson || op.kind == kOpPoisson27;
+    it.wdvec = jac_p0 && !const_diag;
+    it.cscale = (jac_p0 && const_diag) ? (op.kind == kOpPoisson27 ? 26.0 : 6.0) : 1.0;
 
     // workspace: P and AP zero-filled, so the padding rows n..ld-1 read as 0;
     // stencil operators with s <= 16 use the Gram kernel that applies the
@@ -772,6 +784,15 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     it.hist_cap = o.record_history ? o.max_outer + 1 : 0;
     OKCHK(dalloc(ctx, &it.hist, size_t(3 * std::max(it.hist_cap, 1))));
     it.inv_sqrt_n = 1.0 / std::sqrt(double(n));
+    {
+        LzArgs &l = ctx->lz;
+        l.n = n;
+        l.nb = int(std::min<int64_t>(1024, (n + kBlock - 1) / kBlock));
+        l.chunk = round_up((n + l.nb - 1) / l.nb, kBlock);
+        OKCHK(dalloc(ctx, &l.part, size_t(l.nb)));
+        OKCHK(dalloc(ctx, &l.ab, size_t(3 * kMaxLanczos)));
+        OKCHK(dalloc(ctx, &l.ls, 1));
+    }
     HIPCHK(ctx, hipMemsetAsync(it.st, 0, sizeof(DevState), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     set_gram_schedule(it, default_gram_schedule(it));
@@ -812,11 +833,12 @@ sstep_status sstep_update_coefficients(sstep_ctx *ctx, const sstep_operator *A)
         if (A->kind != SSTEP_OP_CSR || A->n != op.n || A->nnz != op.nnz)
             return fail(ctx, SSTEP_E_ARG, "operator kind or sizes differ from setup");
     } else {
-        if (A->kind != SSTEP_OP_STENCIL7 || A->nx != op.g.nx || A->ny != op.g.ny || A->nz != op.g.nz)
+        const int kind = op.kind == kOpPoisson27 ? SSTEP_OP_STENCIL27 : SSTEP_OP_STENCIL7;
+        if (A->kind != kind || A->nx != op.g.nx || A->ny != op.g.ny || A->nz != op.g.nz)
             return fail(ctx, SSTEP_E_ARG, "operator kind or grid differ from setup");
         if ((op.kind == kOpFaces) != (A->kx != nullptr))
             return fail(ctx, SSTEP_E_ARG, "constant and face-coefficient stencils cannot be swapped");
-        if (op.kind == kOpPoisson)
+        if (op.kind == kOpPoisson || op.kind == kOpPoisson27)
             return SSTEP_OK;  // no coefficients
     }
     return load_coefficients(ctx, A, false);
@@ -861,6 +883,8 @@ sstep_status sstep_grad_operator(sstep_ctx *ctx, const double *lam, const double
         return SSTEP_E_ARG;
     if (!lam || !x || !dA)
         return fail(ctx, SSTEP_E_ARG, "lam, x and dA must not be NULL");
+    if (ctx->it.op.kind == kOpPoisson27)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "the 27-point operator has no coefficients to differentiate");
     HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
     HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
     HIPCHK(ctx, launch_grad(ctx->it.op, lam, x, dA, accumulate ? 1 : 0, ctx->stream));
@@ -917,6 +941,99 @@ sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alph
         *rnorm = dbg[size_t(dbg_rho(s))];
     if (h.status != SSTEP_OK)
         return fail(ctx, static_cast<sstep_status>(h.status), "step stopped");
+    return SSTEP_OK;
+}
+
+sstep_status sstep_lanczos(sstep_ctx *ctx, const double *u, int32_t steps, double *alpha, double *beta,
+                           double *ritz, int32_t *m_out)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (ctx->batch)
+        return fail(ctx, SSTEP_E_ARG, "not available for a batched context");
+    if (!u)
+        return fail(ctx, SSTEP_E_ARG, "u must not be NULL");
+    if (steps < 1 || steps > kMaxLanczos)
+        return fail(ctx, SSTEP_E_ARG, "steps must be in [1, 64]");
+    LzArgs &l = ctx->lz;
+    const IterArgs &it = ctx->it;
+    const size_t need = size_t(3) * size_t(it.ld) * sizeof(double);
+    const size_t pbytes = size_t(it.ld) * it.s * (it.fp32 ? sizeof(float) : sizeof(double));
+    if (pbytes >= need) {
+        // the basis storage is scratch between solves
+        double *P = static_cast<double *>(it.P);
+        l.v[0] = P, l.v[1] = P + it.ld, l.v[2] = P + 2 * it.ld;
+    } else {
+        if (!ctx->lz_vecs)
+            OKCHK(dalloc(ctx, &ctx->lz_vecs, size_t(3) * size_t(it.ld)));
+        l.v[0] = ctx->lz_vecs, l.v[1] = ctx->lz_vecs + it.ld, l.v[2] = ctx->lz_vecs + 2 * it.ld;
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    HIPCHK(ctx, hipMemsetAsync(l.ls, 0, sizeof(LzState), ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(l.ab, 0, size_t(3 * kMaxLanczos) * sizeof(double), ctx->stream));
+    HIPCHK(ctx, launch_lanczos(l, it.op, u, steps, ctx->stream));
+    std::vector<double> ab(size_t(3) * steps);
+    LzState h;
+    HIPCHK(ctx, hipMemcpyAsync(ab.data(), l.ab, ab.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&h, l.ls, sizeof(LzState), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const int m = h.m;
+    if (m_out)
+        *m_out = m;
+    for (int i = 0; i < steps; ++i) {
+        if (alpha)
+            alpha[i] = i < m ? ab[size_t(i)] : 0.0;
+        if (beta)
+            beta[i] = i < m ? ab[size_t(steps + i)] : 0.0;
+        if (ritz)
+            ritz[i] = i < m ? ab[size_t(2 * steps + i)] : 0.0;
+    }
+    if (m < 1)
+        return fail(ctx, SSTEP_E_ARG, "the start vector has zero M-norm");
+    return SSTEP_OK;
+}
+
+sstep_status sstep_set_bounds(sstep_ctx *ctx, double lambda_min, double lambda_max)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (ctx->batch)
+        return fail(ctx, SSTEP_E_ARG, "a batched context takes its bounds at setup");
+    if (!std::isfinite(lambda_min) || !std::isfinite(lambda_max) || lambda_min < 0.0 || !(lambda_max > lambda_min))
+        return fail(ctx, SSTEP_E_ARG, "bounds must be finite with 0 <= lambda_min < lambda_max");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->it.theta = 2.0 / (lambda_max - lambda_min);
+    ctx->it.sigma = (lambda_max + lambda_min) / 2.0;
+    // the basis kernels take theta and sigma as arguments: capture the graph again
+    if (ctx->gexec)
+        HIPCHK(ctx, hipGraphExecDestroy(ctx->gexec));
+    ctx->gexec = nullptr;
+    if (ctx->graph)
+        HIPCHK(ctx, hipGraphDestroy(ctx->graph));
+    ctx->graph = nullptr;
+    return capture_graph(ctx);
+}
+
+sstep_status sstep_lanczos_bounds(sstep_ctx *ctx, const double *u, int32_t steps, double margin,
+                                  double *lambda_min, double *lambda_max)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!(margin >= 0.0) || !(margin < 1.0))
+        return fail(ctx, SSTEP_E_ARG, "margin must be in [0, 1)");
+    std::vector<double> ritz(size_t(std::max(steps, 1)));
+    int32_t m = 0;
+    OKCHK(sstep_lanczos(ctx, u, steps, nullptr, nullptr, ritz.data(), &m));
+    const double lo = std::max(0.0, (1.0 - margin) * ritz[0]);
+    const double hi = (1.0 + margin) * ritz[size_t(m - 1)];
+    if (!(hi > lo))
+        return fail(ctx, SSTEP_E_BREAKDOWN, "Lanczos gave a degenerate interval (one Ritz value and no margin)");
+    OKCHK(sstep_set_bounds(ctx, lo, hi));
+    if (lambda_min)
+        *lambda_min = lo;
+    if (lambda_max)
+        *lambda_max = hi;
     return SSTEP_OK;
 }
 

@@ -116,6 +116,49 @@ struct OpPoisson7 {
     }
 };
 
+// Constant-coefficient 27-point operator (Sec. 8): diagonal 26, -1 on the 26
+// other points of the 3 x 3 x 3 box, so (A p)_c = 27 p_c - (sum of p over the
+// box); neighbours outside the grid are 0.
+template <typename T>
+struct OpPoisson27 {
+    Grid3 g;
+    T minv;  // 1/26 with Jacobi, 1 without
+
+    __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
+    {
+        const uint32_t q = fdiv(static_cast<uint32_t>(c), g.dx);
+        const uint32_t i = static_cast<uint32_t>(c) - q * g.nx;
+        const uint32_t k = fdiv(q, g.dy);
+        const uint32_t j = q - k * g.ny;
+        const bool has_w = i > 0, has_e = i + 1 < static_cast<uint32_t>(g.nx);
+        const bool has_s = j > 0, has_n = j + 1 < static_cast<uint32_t>(g.ny);
+        const bool has_b = k > 0, has_t = k + 1 < static_cast<uint32_t>(g.nz);
+        pc = p[c];
+        T box = T(0);
+#pragma unroll
+        for (int dk = -1; dk <= 1; ++dk) {
+            if ((dk < 0 && !has_b) || (dk > 0 && !has_t))
+                continue;
+            T plane = T(0);
+#pragma unroll
+            for (int dj = -1; dj <= 1; ++dj) {
+                if ((dj < 0 && !has_s) || (dj > 0 && !has_n))
+                    continue;
+                const int64_t r = c + dj * static_cast<int64_t>(g.nx) + dk * g.nxy;
+                T row = p[r];
+                if (has_w)
+                    row += p[r - 1];
+                if (has_e)
+                    row += p[r + 1];
+                plane += row;
+            }
+            box += plane;
+        }
+        y = T(27) * pc - box;
+        dinv = minv;
+    }
+};
+
 // Variable-coefficient 7-point operator from face coefficients (boundary
 // faces included): (A p)_c = sum_f k_f (p_c - p_q), p_q = 0 outside.
 template <typename T>

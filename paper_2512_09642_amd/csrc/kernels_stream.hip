@@ -2,6 +2,7 @@
 // SpMV/Jacobi/Chebyshev basis step, the update x += P alpha, and helpers.
 // All of them are bound by HBM bandwidth (well under one flop per byte).
 #include "launch.h"
+#include "opsel.h"
 #include "stop.h"
 
 namespace sstep {
@@ -504,24 +505,6 @@ __global__ __launch_bounds__(kBlock) void k_invert(const double *__restrict__ sr
 }
 
 
-template <typename T>
-OpPoisson7<T> make_poisson(const OpDev &op)
-{
-    return OpPoisson7<T>{op.g, op.precond ? T(1) / T(6) : T(1)};
-}
-
-template <typename T>
-struct Ops;
-template <>
-struct Ops<double> {
-    static OpFaces7<double> faces(const OpDev &op) { return {op.g, op.kx, op.ky, op.kz, op.precond}; }
-    static OpCsr<double> csr(const OpDev &op) { return {op.rp, op.ci, op.val, op.invd}; }
-};
-template <>
-struct Ops<float> {
-    static OpFaces7<float> faces(const OpDev &op) { return {op.g, op.kx32, op.ky32, op.kz32, op.precond}; }
-    static OpCsr<float> csr(const OpDev &op) { return {op.rp, op.ci, op.val32, op.invd32}; }
-};
 
 StopOut stop_out(const IterArgs &a, bool write_p0)
 {
@@ -555,6 +538,8 @@ hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
         return residual_for<OpPoisson7<double>, TP>(a, make_poisson<double>(a.op), st, write_p0);
     case kOpFaces:
         return residual_for<OpFaces7<double>, TP>(a, Ops<double>::faces(a.op), st, write_p0);
+    case kOpPoisson27:
+        return residual_for<OpPoisson27<double>, TP>(a, make_poisson27<double>(a.op), st, write_p0);
     default:
         return residual_for<OpCsr<double>, TP>(a, Ops<double>::csr(a.op), st, write_p0);
     }
@@ -645,6 +630,8 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
         return basis_for<OpPoisson7<T>, T>(a, make_poisson<T>(a.op), j, step, st);
     case kOpFaces:
         return basis_for<OpFaces7<T>, T>(a, Ops<T>::faces(a.op), j, step, st);
+    case kOpPoisson27:
+        return basis_for<OpPoisson27<T>, T>(a, make_poisson27<T>(a.op), j, step, st);
     default:
         return basis_csr<T>(a, j, step, st);
     }
@@ -698,6 +685,10 @@ hipError_t launch_apply(const OpDev &op, const double *x, double *y, hipStream_t
         hipLaunchKernelGGL(k_apply<OpFaces7<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::faces(op), x,
                            y, op.n, l.per, l.nbl);
         break;
+    case kOpPoisson27:
+        hipLaunchKernelGGL(k_apply<OpPoisson27<double>>, dim3(l.grid), dim3(kBlock), 0, st,
+                           make_poisson27<double>(op), x, y, op.n, l.per, l.nbl);
+        break;
     default:
         hipLaunchKernelGGL(k_apply<OpCsr<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::csr(op), x, y,
                            op.n, l.per, l.nbl);
@@ -708,6 +699,8 @@ hipError_t launch_apply(const OpDev &op, const double *x, double *y, hipStream_t
 hipError_t launch_grad(const OpDev &op, const double *lam, const double *x, double *dA, int accumulate,
                        hipStream_t st)
 {
+    if (op.kind == kOpPoisson27)
+        return hipErrorInvalidValue;  // no coefficients to differentiate
     if (op.kind == kOpCsr) {
         hipLaunchKernelGGL(k_grad_csr, dim3(blocks_for(op.n)), dim3(kBlock), 0, st, op.rp, op.ci, lam, x, dA, op.n,
                            accumulate);

@@ -9,7 +9,7 @@
 
 namespace sstep {
 
-enum OpKind { kOpCsr = 0, kOpPoisson = 1, kOpFaces = 2 };
+enum OpKind { kOpCsr = 0, kOpPoisson = 1, kOpFaces = 2, kOpPoisson27 = 3 };
 
 // Column padding of the basis buffers and of the M-diagonal arrays (rows).
 constexpr int64_t kPad = 256;
@@ -143,6 +143,26 @@ hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st);
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bupdate(const BatchArgs &a, hipStream_t st);
+
+// Lanczos spectrum estimate (kernels_lanczos.hip).
+constexpr int kMaxLanczos = 64;  // largest number of Lanczos steps
+struct LzState {
+    double scale;  // ||u||_M, then the last beta_{j+1}
+    double amax;   // max |alpha_i| so far
+    int32_t m;     // completed steps
+    int32_t stopped;
+};
+struct LzArgs {
+    LzState *ls = nullptr;
+    double *v[3] = {nullptr, nullptr, nullptr};  // z_{j-1}, z_j, y / w: n doubles each
+    double *part = nullptr;                      // block partials [nb]
+    double *ab = nullptr;                        // alpha [steps], beta [steps], Ritz values [steps]
+    int64_t n = 0, chunk = 0;
+    int nb = 0;
+};
+// Enqueues steps Lanczos steps from u (n doubles) and the Ritz values of T_m;
+// results in l.ab and l.ls once the stream reaches them.
+hipError_t launch_lanczos(const LzArgs &l, const OpDev &op, const double *u, int steps, hipStream_t st);
 
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);

@@ -60,10 +60,17 @@ class Operator:
     def stencil(nx: int, ny: int, nz: int, kx=None, ky=None, kz=None) -> "Operator":
         return Operator(N.OP_STENCIL7, nx * ny * nz, dims=(nx, ny, nz), kx=kx, ky=ky, kz=kz)
 
+    @staticmethod
+    def stencil27(nx: int, ny: int, nz: int) -> "Operator":
+        """The 27-point Poisson operator (diagonal 26, -1 on the box)."""
+        return Operator(N.OP_STENCIL27, nx * ny * nz, dims=(nx, ny, nz))
+
     @property
     def grad_size(self) -> int:
         if self.kind == N.OP_CSR:
             return self.nnz
+        if self.kind == N.OP_STENCIL27:
+            return 0
         nx, ny, nz = self.dims
         return (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
 
@@ -254,6 +261,29 @@ class Solver:
         if want_basis:
             out.update(P=P, AP=AP)
         return out
+
+    def lanczos(self, u: torch.Tensor, steps: int = 10) -> dict:
+        """Lanczos on M^{-1}A from ``u`` (device float64): ``alpha``, ``beta``,
+        ``ritz`` (ascending) of the ``m`` completed steps."""
+        al, be, rz = np.zeros(steps), np.zeros(steps), np.zeros(steps)
+        m = C.c_int32(0)
+        _check(self._lib.sstep_lanczos(self._ctx, _dev_ptr(u, self.n, "u"), steps, al.ctypes.data, be.ctypes.data,
+                                       rz.ctypes.data, C.byref(m)), self._ctx)
+        k = m.value
+        return dict(alpha=al[:k], beta=be[:k], ritz=rz[:k], m=k)
+
+    def set_bounds(self, lmin: float, lmax: float):
+        _check(self._lib.sstep_set_bounds(self._ctx, lmin, lmax), self._ctx)
+        self.lmin, self.lmax = lmin, lmax
+
+    def lanczos_bounds(self, u: torch.Tensor, steps: int = 10, margin: float = 0.1):
+        """Sets the Chebyshev bounds from ``steps`` Lanczos steps with a
+        relative ``margin`` (Sec. 8: 10 steps, 10%); returns (lmin, lmax)."""
+        lo, hi = C.c_double(0.0), C.c_double(0.0)
+        _check(self._lib.sstep_lanczos_bounds(self._ctx, _dev_ptr(u, self.n, "u"), steps, margin, C.byref(lo),
+                                              C.byref(hi)), self._ctx)
+        self.lmin, self.lmax = lo.value, hi.value
+        return lo.value, hi.value
 
     def last_iteration(self) -> dict:
         """``rnorm``, ``delta`` (Gram-solve residual) and ``lnorm`` (||L||_F)

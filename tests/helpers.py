@@ -30,6 +30,8 @@ def make_operator(lib, pr, form: str):
     """Library operator for a generated problem: ``stencil`` (matrix-free,
     3D only) or ``csr`` (the generator's CSR arrays)."""
     if form == "stencil":
+        if getattr(pr, "stencil", 7) == 27:
+            return lib.Operator.stencil27(*pr.dims)
         return lib.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz)
     rp, ci, v = pr.csr()
     return lib.Operator.csr(rp, ci, v)

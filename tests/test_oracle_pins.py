@@ -627,3 +627,144 @@ def test_gram_condition_closed_form():
         assert abs(oracle.gram_condition(G) - want) <= 1e-12 * want
     assert oracle.gram_condition(np.array([[1.0, 1.0], [1.0, 1.0]])) == float("inf") or \
         oracle.gram_condition(np.array([[1.0, 1.0], [1.0, 1.0]])) > 1e15
+
+
+# ---------------------------------------------------------------------------
+# Lanczos spectrum bounds (Sec. 8 setup)
+# ---------------------------------------------------------------------------
+
+def _krylov_ritz(Ad, d, u, m):
+    """Rayleigh-Ritz values of M^{-1}A on K_m(M^{-1}A, u), computed densely:
+    B = D^{-1/2} A D^{-1/2} on an orthonormal (QR) basis of D^{1/2} K_m."""
+    s = np.sqrt(d)
+    B = Ad / s[:, None] / s[None, :]
+    K = np.zeros((u.size, m))
+    v = s * u
+    for j in range(m):
+        K[:, j] = v / np.linalg.norm(v)
+        v = B @ K[:, j]
+    Q, _ = np.linalg.qr(K)
+    return np.linalg.eigvalsh(Q.T @ B @ Q)
+
+
+@pytest.mark.parametrize("kind", ["poisson3d", "faces3d", "poisson2d"])
+def test_lanczos_ritz_values_are_krylov_projection(kind):
+    """The Ritz values of a few Lanczos steps are the eigenvalues of M^{-1}A
+    projected on the Krylov space K_m(M^{-1}A, u) (textbook Rayleigh-Ritz),
+    formed here densely from a QR of the Krylov basis."""
+    pr, A, _ = small_problem(kind, seed=7)
+    Ad = dense(A)
+    d = np.diag(Ad).copy()
+    u = gen.uniform(gen.rng(3), pr.n)
+    for m in (2, 5, 8):
+        out = oracle.lanczos(A, u, m)
+        assert out["m"] == m
+        want = _krylov_ritz(Ad, d, u, m)
+        assert np.max(np.abs(out["ritz"] - want)) <= 1e-10 * np.abs(want).max(), (m, out["ritz"], want)
+
+
+@pytest.mark.parametrize("dims", [(3, 3, 2), (4, 3, 3)])
+def test_lanczos_full_run_finds_exact_extremes(dims):
+    """With as many steps as unknowns the extreme Ritz values reach the closed-
+    form extreme eigenvalues of the Jacobi-preconditioned Poisson operator."""
+    nx, ny, nz = dims
+    A = oracle.assemble_stencil7(nx, ny, nz)
+    n = nx * ny * nz
+    lo, hi = gen.jacobi_poisson_bounds(nx, ny, nz)
+    out = oracle.lanczos(A, gen.uniform(gen.rng(1), n), n)
+    assert abs(out["ritz"][0] - lo) <= 1e-10 and abs(out["ritz"][-1] - hi) <= 1e-10, (out["ritz"], lo, hi)
+
+
+def test_lanczos_ten_steps_inside_spectrum_and_margin():
+    """Ten steps on 20^3 Poisson: every Ritz value lies inside the exact
+    spectrum of M^{-1}A (Cauchy interlacing), the largest is already close to
+    lambda_max, and the 10% margin widens the extremes as stated."""
+    N = 20
+    A = oracle.assemble_stencil7(N, N, N)
+    lo, hi = gen.jacobi_poisson_bounds(N, N, N)
+    out = oracle.lanczos(A, gen.uniform(gen.rng(2), N ** 3), 10)
+    r = out["ritz"]
+    assert out["m"] == 10 and r.size == 10
+    assert r[0] >= lo - 1e-12 and r[-1] <= hi + 1e-12
+    assert hi - r[-1] <= 0.05 * hi
+    bl, bh = oracle.lanczos_bounds(r, 0.1)
+    assert bl == 0.9 * r[0] and bh == 1.1 * r[-1]
+    assert bh > hi
+
+
+def test_lanczos_faces_inside_gershgorin_and_dense_spectrum():
+    pr, A, _ = small_problem("faces3d", seed=8)
+    Ad = dense(A)
+    d = np.diag(Ad)
+    ev = np.linalg.eigvalsh(Ad / np.sqrt(d)[:, None] / np.sqrt(d)[None, :])
+    out = oracle.lanczos(A, gen.uniform(gen.rng(4), pr.n), 10)
+    assert out["ritz"][0] >= ev[0] - 1e-12 and out["ritz"][-1] <= ev[-1] + 1e-12
+    assert 0.0 <= out["ritz"][0] and out["ritz"][-1] <= 2.0
+
+
+def test_lanczos_stops_on_invariant_subspace_and_zero_start():
+    """An eigenvector start spans an invariant subspace: one step, Ritz value
+    = its eigenvalue; a zero start vector gives no steps."""
+    nx, ny, nz = 5, 4, 3
+    A = oracle.assemble_stencil7(nx, ny, nz)
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    v = (np.sin(math.pi * (i + 1) / (nx + 1)) * np.sin(2 * math.pi * (j + 1) / (ny + 1))
+         * np.sin(math.pi * (k + 1) / (nz + 1))).ravel()
+    lam = (6 - 2 * math.cos(math.pi / (nx + 1)) - 2 * math.cos(2 * math.pi / (ny + 1))
+           - 2 * math.cos(math.pi / (nz + 1))) / 6
+    out = oracle.lanczos(A, v, 10)
+    assert out["m"] == 1 and abs(out["ritz"][0] - lam) <= 1e-14
+    assert oracle.lanczos(A, np.zeros(nx * ny * nz), 10)["m"] == 0
+
+
+# ---------------------------------------------------------------------------
+# The 27-point operator of the paper's experiments (Sec. 8)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (9, 9, 9)])
+def test_poisson27_sine_eigenpairs(dims):
+    """A = 27 I - T_x (x) T_y (x) T_z: sine eigenvectors with eigenvalues
+    27 - prod_a (1 + 2 cos(m_a pi / (N_a + 1))); the generator's CSR and the
+    oracle's assembly are the same matrix."""
+    nx, ny, nz = dims
+    Ao = oracle.assemble_stencil27(nx, ny, nz)
+    Ag = gen.poisson27_csr(nx, ny, nz)
+    for a, b in zip(Ao, Ag):
+        assert np.array_equal(a, b)
+    rp, ci, v = Ao
+    assert rp[-1] == (3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2)
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    for a, b, c in [(1, 1, 1), (2, 3, 1), (nx, ny, nz), (nx, 1, 1), (1, ny, 2)]:
+        vec = (np.sin(a * math.pi * (i + 1) / (nx + 1)) * np.sin(b * math.pi * (j + 1) / (ny + 1))
+               * np.sin(c * math.pi * (k + 1) / (nz + 1))).ravel()
+        lam = 27 - ((1 + 2 * math.cos(a * math.pi / (nx + 1))) * (1 + 2 * math.cos(b * math.pi / (ny + 1)))
+                    * (1 + 2 * math.cos(c * math.pi / (nz + 1))))
+        assert np.linalg.norm(oracle.spmv(Ao, vec) - lam * vec) < 54 * 1e-14 * np.linalg.norm(vec)
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 3), (8, 8, 8), (11, 6, 9)])
+def test_poisson27_jacobi_bounds_closed_form(dims):
+    """The corner rule of the bounds equals the dense spectrum of D^{-1} A."""
+    nx, ny, nz = dims
+    Ad = dense(oracle.assemble_stencil27(nx, ny, nz))
+    ev = np.linalg.eigvalsh(Ad / 26.0)
+    lo, hi = gen.jacobi_poisson27_bounds(nx, ny, nz)
+    assert abs(ev[0] - lo) <= 1e-13 and abs(ev[-1] - hi) <= 1e-13, (ev[0], lo, ev[-1], hi)
+
+
+def test_poisson27_solve_converges_to_direct_solution():
+    """P9 on the 27-point operator: the s-step solve at tol 1e-12 reaches the
+    dense direct solution within kappa(A) tol."""
+    pr = gen.small_poisson27(7, 6, 5, seed=3, s=8, nu=30)
+    A = oracle.problem_csr(pr)
+    b = oracle.spmv(A, pr.xstar)
+    out = oracle.solve(A, b, None, pr.s, pr.nu, pr.lmin, pr.lmax, 1e-12)
+    assert out["status"] == 0
+    Ad = dense(A)
+    ev = np.linalg.eigvalsh(Ad)
+    xd = np.linalg.solve(Ad, b)
+    assert rel(out["x"], xd) <= (ev[-1] / ev[0]) * 1e-12
