@@ -13,8 +13,9 @@
  *      and nu forward Gauss-Seidel sweeps from alpha = 0      (Sec. 2, FGS iteration)
  *   5. x <- x + P alpha                                       (Sec. 2)
  * Every step runs in hand-written HIP kernels.  graph_chunk outer iterations
- * are captured in one HIP graph; the stopping test runs on the device inside
- * the residual kernel and, once it fires, every later kernel returns at once.
+ * are captured in one HIP graph; the stopping test runs on the device right
+ * after the residual kernel and, once it fires, every later kernel returns at
+ * once.
  * The host synchronises once per graph replay: it waits for the copy of the
  * device's stop flag that follows replay r (replay r + 1 already queued
  * behind it) before deciding whether to queue replay r + 2.

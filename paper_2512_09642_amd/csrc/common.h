@@ -33,7 +33,7 @@ struct DevState {
     int32_t first;     // 1 until rho0 has been recorded
     int32_t no_stop;   // 1 = never stop (single-step and timing entry points)
     int32_t hist_cap;  // capacity of the device history (0 = off)
-    uint32_t ticket;   // blocks of the running residual kernel that have stored their partial
+    int32_t pad;
     double alpha[kMaxS];  // coefficients of the unscaled basis, x += P alpha
 };
 

@@ -43,24 +43,26 @@ __device__ __forceinline__ void block_sum_store(T v, T *out)
     }
 }
 
-// Where a residual kernel reports: with do_stop, the last block to finish sums
-// the partials of ||r||^2 and runs the stopping test, so that a converged
-// iteration launches no basis or Gram work; without it (the norm-only pass
-// of FP32+IR) only the partials are written.
-struct StopOut {
-    int do_stop;
-    double *dbg_rho;  // ||r|| for the single-step entry point
-    double *hist;     // relative-residual history [hist_cap]
-    int hist_cap;
-};
+// The stopping test of iteration k, one block after the residual kernel: the
+// fixed-order sum of its partials of ||r||^2, then stop_test (stop.h), so
+// that every later kernel of a converged iteration returns at once.
+__global__ __launch_bounds__(kSumThreads) void k_stop(DevState *__restrict__ st, const double *__restrict__ rpart,
+                                                      int nbr, double *__restrict__ dbg_rho,
+                                                      double *__restrict__ hist, int hist_cap)
+{
+    if (st->done)
+        return;
+    const double rho2 = fixed_order_sum(rpart, nbr);
+    if (threadIdx.x == 0)
+        stop_test(st, rho2, dbg_rho, hist, hist_cap);
+}
 
 // r = b - A x in FP64, partial sums of r^2 per logical block, and the basis
 // start p_0 = p0scale * (M^{-1} r or r) written as column 0 of P.
 template <class Op, typename TP>
-__global__ __launch_bounds__(kBlock) void k_residual(DevState *__restrict__ st, Op op, TP *__restrict__ p0,
+__global__ __launch_bounds__(kBlock) void k_residual(const DevState *__restrict__ st, Op op, TP *__restrict__ p0,
                                                      double *__restrict__ rpart, int64_t n, int64_t chunk,
-                                                     uint32_t per, uint32_t nbl, int p0_mode, int write_p0,
-                                                     StopOut so)
+                                                     uint32_t per, uint32_t nbl, int p0_mode, int write_p0)
 {
     if (st->done)
         return;
@@ -82,8 +84,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(DevState *__restrict__ st, 
             p0[c] = static_cast<TP>(scale * (p0_mode ? r : dinv * r));
     }
     block_sum_store(acc, rpart + lb);
-    if (so.do_stop)
-        residual_stop_tail(st, rpart, static_cast<int>(nbl), so.dbg_rho, so.hist, so.hist_cap);
 }
 
 // The residual for the constant Poisson operator in FP64 (nx even) in the
@@ -92,9 +92,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(DevState *__restrict__ st, 
 // One partial sum of r^2 per block, blocks numbered blockIdx.x + gridDim.x *
 // blockIdx.y (the launch keeps their number within the partial buffer).
 template <typename TP>
-__global__ __launch_bounds__(1024) void k_residual_p2(DevState *__restrict__ st, Grid3 g, double minv,
+__global__ __launch_bounds__(1024) void k_residual_p2(const DevState *__restrict__ st, Grid3 g, double minv,
                                                       TP *__restrict__ p0, double *__restrict__ rpart, int p0_mode,
-                                                      int write_p0, StopOut so)
+                                                      int write_p0)
 {
     constexpr int KZ = 8;
     __shared__ double part[1024 / kWave];
@@ -148,8 +148,6 @@ __global__ __launch_bounds__(1024) void k_residual_p2(DevState *__restrict__ st,
             sum += part[w];
         rpart[blockIdx.x + gridDim.x * blockIdx.y] = sum;
     }
-    if (so.do_stop)
-        residual_stop_tail(st, rpart, static_cast<int>(gridDim.x * gridDim.y), so.dbg_rho, so.hist, so.hist_cap);
 }
 
 // One step of the Chebyshev recurrence fused with the operator apply
@@ -506,19 +504,13 @@ __global__ __launch_bounds__(kBlock) void k_invert(const double *__restrict__ sr
 
 
 
-StopOut stop_out(const IterArgs &a, bool write_p0)
-{
-    // the norm-only pass (no p_0) of FP32+IR runs no stopping test
-    return StopOut{write_p0 ? 1 : 0, a.dbg + dbg_rho(a.s), a.hist, a.hist_cap};
-}
-
 template <class Op, typename TP>
 hipError_t residual_for(const IterArgs &a, const Op &op, hipStream_t st, bool write_p0)
 {
     const uint32_t per = (static_cast<uint32_t>(a.nbr) + kNumXcd - 1) / kNumXcd;
     hipLaunchKernelGGL((k_residual<Op, TP>), dim3(per * kNumXcd), dim3(kBlock), 0, st, a.st, op,
                        static_cast<TP *>(a.P), a.rpart, a.op.n, a.rchunk, per, static_cast<uint32_t>(a.nbr),
-                       a.p0_mode, write_p0 ? 1 : 0, stop_out(a, write_p0));
+                       a.p0_mode, write_p0 ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -532,7 +524,7 @@ hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
                             static_cast<uint32_t>((a.op.g.nz + 7) / 8));
             hipLaunchKernelGGL(k_residual_p2<TP>, grid, dim3(1024), 0, st, a.st, a.op.g,
                                a.op.precond ? 1.0 / 6.0 : 1.0, static_cast<TP *>(a.P), a.rpart, a.p0_mode,
-                               write_p0 ? 1 : 0, stop_out(a, write_p0));
+                               write_p0 ? 1 : 0);
             return hipGetLastError();
         }
         return residual_for<OpPoisson7<double>, TP>(a, make_poisson<double>(a.op), st, write_p0);
@@ -641,7 +633,12 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
 
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0)
 {
-    return a.fp32 ? residual_t<float>(a, st, write_p0) : residual_t<double>(a, st, write_p0);
+    const hipError_t e = a.fp32 ? residual_t<float>(a, st, write_p0) : residual_t<double>(a, st, write_p0);
+    if (e != hipSuccess || !write_p0)
+        return e;  // the norm-only pass of FP32+IR runs no stopping test
+    hipLaunchKernelGGL(k_stop, dim3(1), dim3(kSumThreads), 0, st, a.st, a.rpart, a.nbr, a.dbg + dbg_rho(a.s), a.hist,
+                       a.hist_cap);
+    return hipGetLastError();
 }
 
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st)

@@ -1,7 +1,6 @@
 // Stopping test of the outer iteration (Sec. 8: stop at the first k with
-// ||r_k|| < tol ||r_0||, strict, on the true residual), and the "last block"
-// hand-off that lets the kernel forming the residual norm's partial sums run
-// the test itself, before any basis or Gram work of iteration k is started.
+// ||r_k|| < tol ||r_0||, strict, on the true residual), run right after the
+// residual kernel and before any basis or Gram work of iteration k.
 #pragma once
 
 #include "common.h"
@@ -60,9 +59,8 @@ __device__ inline int stop_test(DevState *__restrict__ st, double rho2, double *
 
 // Sum of part[0..cnt) in a fixed order by the first kSumThreads threads of a
 // block (thread t takes t, t + 256, ..., the waves combine by butterfly and
-// the four wave sums are added in order).  The caller has made the partials
-// of other blocks visible (last_block).  Returns the total in thread 0 (other
-// threads: unspecified).  Every thread of the block must call it.
+// the four wave sums are added in order).  Returns the total in thread 0
+// (other threads: unspecified).  Every thread of the block must call it.
 __device__ inline double fixed_order_sum(const double *part, int cnt)
 {
     __shared__ double wsum[kSumThreads / kWave];
@@ -81,42 +79,6 @@ __device__ inline double fixed_order_sum(const double *part, int cnt)
         for (int w = 0; w < kSumThreads / kWave; ++w)
             v += wsum[w];
     return v;
-}
-
-// Called by every thread of every block of a grid after thread 0 of the block
-// has stored the block's partial sum: true in exactly one block, the last to
-// arrive, once every partial is visible to it.  Thread 0 releases the
-// block's partial (device-scope fence: the XCD's L2 is written back) and
-// takes a ticket; the last block acquires (device-scope fence: its L2 lines
-// are invalidated, so the other XCDs' partials are read from memory) and
-// resets the ticket for the next launch.
-__device__ inline bool last_block(uint32_t *ticket, uint32_t nblocks)
-{
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        is_last = t + 1 == nblocks;
-    }
-    __syncthreads();
-    if (!is_last)
-        return false;
-    __threadfence();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-}
-
-// The tail of a residual kernel: hand the partial sums of ||r||^2 to the last
-// block, which sums them in the fixed order and runs the stopping test.
-__device__ inline void residual_stop_tail(DevState *__restrict__ st, const double *rpart, int nparts,
-                                          double *__restrict__ dbg_rho, double *__restrict__ hist, int hist_cap)
-{
-    if (!last_block(&st->ticket, static_cast<uint32_t>(nparts)))
-        return;
-    const double rho2 = fixed_order_sum(rpart, nparts);
-    if (threadIdx.x == 0)
-        stop_test(st, rho2, dbg_rho, hist, hist_cap);
 }
 
 }  // namespace sstep

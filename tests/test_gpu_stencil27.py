@@ -1,0 +1,137 @@
+"""The 27-point Poisson operator of the paper's experiments (Sec. 8) on the
+GPU, through the C ABI, against the oracle: operator apply, lockstep outer
+iterations (FP64 parity bar 1e-10, basis 1e-12), free-running solves, FP32+IR,
+Lanczos bounds, the CSR form of the same matrix, and the 230^3 workload
+(12,167,000 unknowns) at its full size."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from helpers import make_operator, oracle_rhs, rel
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def t64(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "ragged_s10": (lambda: gen.small_poisson27(23, 17, 13, seed=1, s=10, nu=15), "stencil"),
+    "ragged_s20": (lambda: gen.small_poisson27(19, 21, 9, seed=2, s=20, nu=30), "stencil"),
+    "csr_s10": (lambda: gen.small_poisson27(15, 12, 11, seed=3, s=10, nu=6), "csr"),
+    "tiny_s4": (lambda: gen.small_poisson27(3, 2, 5, seed=4, s=4, nu=10), "stencil"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply27_matches_oracle(hip, name):
+    make, form = CASES[name]
+    pr = make()
+    A = oracle.problem_csr(pr)
+    x = gen.uniform(gen.rng(98), pr.n)
+    with hip.Solver(make_operator(hip, pr, form), pr.s, pr.nu, pr.lmin, pr.lmax) as sv:
+        got = host(sv.apply(t64(x)))
+    rp, ci, v = A
+    scale = np.add.reduceat(np.abs(v) * np.abs(x[ci]), rp[:-1])
+    assert np.all(np.abs(got - oracle.spmv(A, x)) <= 1e-14 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lockstep27_fp64(hip, name):
+    make, form = CASES[name]
+    pr = make()
+    A, b = oracle_rhs(pr)
+    bt = t64(b)
+    x = np.zeros(pr.n)
+    with hip.Solver(make_operator(hip, pr, form), pr.s, pr.nu, pr.lmin, pr.lmax) as sv:
+        assert not sv.gram_applies_operator
+        for k in range(3):
+            g = sv.step(bt, t64(x), want_basis=(k == 0))
+            o = oracle.step(A, b, x, pr.s, pr.nu, pr.lmin, pr.lmax, want_basis=(k == 0))
+            assert o["status"] == 0
+            assert abs(g["rnorm"] - o["rnorm"]) <= 1e-12 * o["rnorm"]
+            for key in ("G", "ctil", "atil"):
+                assert rel(g[key], o[key]) <= 1e-10, (k, key, rel(g[key], o[key]))
+            if k == 0:
+                P, AP = host(g["P"]), host(g["AP"])
+                for j in range(pr.s):
+                    assert rel(P[j], o["P"][j]) <= 1e-12 and rel(AP[j], o["AP"][j]) <= 1e-12, j
+            x = host(g["x"])
+            assert rel(x, o["x"]) <= 1e-10, k
+
+
+@pytest.mark.parametrize("name", ["ragged_s10", "ragged_s20"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32ir"])
+def test_solve27_reaches_tolerance(hip, name, precision):
+    make, form = CASES[name]
+    pr = make()
+    A, b = oracle_rhs(pr)
+    ref = oracle.solve(A, b, None, pr.s, pr.nu, pr.lmin, pr.lmax, 1e-8)
+    with hip.Solver(make_operator(hip, pr, form), pr.s, pr.nu, pr.lmin, pr.lmax, precision=precision) as sv:
+        x, st = sv.solve(t64(b), None, 1e-8)
+    assert st.status == 0 and ref["status"] == 0
+    assert np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b) <= 1e-8
+    if precision == "fp64":
+        assert abs(st.outer_iters - ref["iters"]) <= max(1, int(0.05 * ref["iters"])), (st.outer_iters, ref["iters"])
+
+
+def test_lanczos27_matches_oracle(hip):
+    pr = gen.small_poisson27(23, 17, 13, seed=1)
+    A = oracle.problem_csr(pr)
+    u = gen.uniform(gen.rng(31), pr.n)
+    ref = oracle.lanczos(A, u, 10)
+    with hip.Solver(make_operator(hip, pr, "stencil"), 10, 15, pr.lmin, pr.lmax) as sv:
+        got = sv.lanczos(t64(u), 10)
+    assert got["m"] == ref["m"] == 10
+    for key in ("alpha", "beta", "ritz"):
+        assert rel(got[key], ref[key]) <= 1e-10, key
+    assert got["ritz"][0] >= pr.lmin - 1e-12 and got["ritz"][-1] <= pr.lmax + 1e-12
+
+
+def test_stencil27_argument_errors(hip):
+    pr = gen.small_poisson27(6, 5, 4)
+    with hip.Solver(hip.Operator.stencil27(6, 5, 4), 4, 5, pr.lmin, pr.lmax) as sv:
+        assert sv.grad_size == 0
+        x = torch.zeros(pr.n, dtype=torch.float64, device=DEV)
+        with pytest.raises(hip.SStepError) as e:
+            sv.grad_operator(x, x, out=torch.zeros(1, dtype=torch.float64, device=DEV))
+        assert e.value.name == "SSTEP_E_UNSUPPORTED"
+    with pytest.raises(hip.SStepError) as e:
+        hip.Solver(hip.Operator.stencil27(6, 5, 4), 4, 5, pr.lmin, pr.lmax, gram="apply")
+    assert e.value.name == "SSTEP_E_UNSUPPORTED"
+
+
+@pytest.fixture(scope="module")
+def p27():
+    pr = gen.paper27(0)
+    A = oracle.problem_csr(pr)
+    b = oracle.spmv(A, pr.xstar)
+    return pr, A, b
+
+
+def test_paper27_full_size_lockstep_and_solve(hip, p27):
+    """230^3 27-point Poisson, s = 20, nu = 30: one lockstep outer iteration
+    against the oracle (1e-10) and the solve with 10-step Lanczos bounds (10%
+    margin, Sec. 8) to a true relative residual <= 1e-8."""
+    pr, A, b = p27
+    bt = t64(b)
+    with hip.Solver(hip.Operator.stencil27(*pr.dims), pr.s, pr.nu, pr.lmin, pr.lmax) as sv:
+        g = sv.step(bt, t64(np.zeros(pr.n)))
+        o = oracle.step(A, b, np.zeros(pr.n), pr.s, pr.nu, pr.lmin, pr.lmax)
+        for key in ("G", "ctil", "atil"):
+            assert rel(g[key], o[key]) <= 1e-10, (key, rel(g[key], o[key]))
+        assert rel(host(g["x"]), o["x"]) <= 1e-10
+        lo, hi = sv.lanczos_bounds(t64(gen.uniform(gen.rng(41), pr.n)), 10, 0.1)
+        x, st = sv.solve(bt, None, 1e-8)
+    print(f"230^3 27-point s=20 nu=30: Lanczos bounds [{lo:.4e}, {hi:.4e}], {st.outer_iters} outer")
+    assert st.status == 0
+    assert np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b) <= 1e-8
