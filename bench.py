@@ -94,30 +94,76 @@ def measured_traffic(N: int, s: int, nu: int):
     return rec["basis_avg_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def _host_description() -> dict:
+    """CPU model and core counts of the host the oracle is timed on."""
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(N: int, s: int, nu: int, gpu_iters: int, sample_outer: int) -> dict:
-    """The FP64 oracle (single-threaded C) on the headline problem: a bounded
-    sample of outer iterations, extrapolated to the GPU's iteration count."""
+    """The FP64 oracle on the headline problem, timed on this host over a
+    bounded sample of outer iterations of its own solve loop (its stopping
+    test set out of reach, so exactly ``sample_outer`` updates run) and scaled
+    to the GPU's iteration count: once as the sequential reference build the
+    tests pin (one core) and once as the OpenMP build of the same loops on
+    every core the process may use (``value``)."""
     import gen
     import oracle
 
     pr = gen.config2(0, N=N, s=s, nu=nu)
     A = oracle.assemble_stencil7(N, N, N)
     b = oracle.spmv(A, pr.xstar)
-    x = np.zeros(pr.n)
-    t0 = time.perf_counter()
-    for _ in range(sample_outer):
-        x = oracle.step(A, b, x, s, nu, pr.lmin, pr.lmax)["x"]
-    dt = time.perf_counter() - t0
-    ms_per_outer = 1e3 * dt / sample_outer
+    runs = {}
+    for omp in (False, True):
+        threads = oracle.select_build(omp)
+        t0 = time.perf_counter()
+        out = oracle.solve(A, b, None, s, nu, pr.lmin, pr.lmax, 1e-300, max_outer=sample_outer)
+        dt = time.perf_counter() - t0
+        assert out["iters"] == sample_outer, out["iters"]
+        runs[omp] = (threads, dt, 1e3 * dt / sample_outer)
+    oracle.select_build(False)
+    threads, dt, ms = runs[True]
+    _, dt1, ms1 = runs[False]
     return {
-        "value": ms_per_outer * gpu_iters,
+        "value": ms * gpu_iters,
         "unit": "ms",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{sample_outer} outer iterations of the {N}^3 FP64 problem (s={s}, nu={nu}) in "
-                  f"{dt:.1f} s, {ms_per_outer:.0f} ms per outer iteration, scaled to the GPU's {gpu_iters} "
-                  "outer iterations to 1e-8",
+        "sample": f"{sample_outer} outer iterations of the oracle's solve of the {N}^3 FP64 problem (s={s}, "
+                  f"nu={nu}), OpenMP build on {threads} threads: {dt:.1f} s, {ms:.0f} ms per outer iteration, "
+                  f"scaled to the GPU's {gpu_iters} outer iterations to 1e-8",
+        "single_thread": {"value": ms1 * gpu_iters, "ms_per_outer": ms1, "seconds": dt1, "cores": 1},
+        "host": _host_description(),
     }
+
+
+def c5_gradient_error(grads) -> dict | None:
+    """Entry-wise error of the differentiable solve's gradient at tol 1e-8
+    against the oracle's reference gradient (forward and adjoint at 1e-12;
+    tests/golden/c5_oracle_grad.json, written from the oracle alone): the
+    largest |difference| over the fixture's sampled entries relative to the
+    largest |entry|."""
+    path = os.path.join(ROOT, "tests", "golden", "c5_oracle_grad.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f)
+    gk, gb, x = (t.detach().cpu().numpy() for t in grads)
+    out = {}
+    for name, got, idx, want in (("dL_dk", gk, ref["idx_k"], ref["dk"]), ("dL_db", gb, ref["idx_v"], ref["lam"]),
+                                 ("x", x, ref["idx_v"], ref["x"])):
+        want = np.asarray(want)
+        out[name] = float(np.abs(got[np.asarray(idx)] - want).max() / np.abs(want).max())
+    out["samples"] = len(ref["idx_k"])
+    return out
 
 
 class Leg:
@@ -224,7 +270,8 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
             t2 = time.perf_counter()
             leg.fwd.append(1e3 * (t1 - t0))
             leg.bwd.append(1e3 * (t2 - t1))
-            return None
+            leg.grads = (cf.grad, bb.grad, x.detach())
+            return leg.solver.last_forward_stats.outer_iters
 
         leg.run = run
         leg.bytes_per_outer = faces_bytes_per_outer(pr.n, pr.s, 8, fused=leg.solver.gram_applies_operator)
@@ -276,7 +323,7 @@ def main():
     ap.add_argument("--legs", default=",".join(ALL_LEGS), help="comma-separated subset of " + ",".join(ALL_LEGS))
     ap.add_argument("--c4-nsys", type=int, default=64)
     ap.add_argument("--kernel-reps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=2, help="oracle outer iterations for cpu_baseline")
+    ap.add_argument("--cpu-sample", type=int, default=10, help="oracle outer iterations for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of n doubles (calibrates traffic counters)")
@@ -342,7 +389,11 @@ def main():
                      max_rel_res=max(leg.pair_relres), gbps_effective=tot_bytes / (t * 1e-3) / 1e9)
         elif name == "c5_adjoint":
             f, bw = float(np.median(leg.fwd)), float(np.median(leg.bwd))
-            r.update(forward_ms=f, backward_ms=bw, backward_over_forward=bw / f, n=leg.n)
+            fi = leg.solver.last_forward_stats.outer_iters
+            ai = leg.solver.last_adjoint_stats.outer_iters
+            r.update(forward_ms=f, backward_ms=bw, backward_over_forward=bw / f, n=leg.n, forward_outer_iters=fi,
+                     adjoint_outer_iters=ai, forward_ms_per_outer=f / max(fi, 1), backward_ms_per_outer=bw / max(ai, 1),
+                     gradient_error_vs_oracle=c5_gradient_error(leg.grads))
         else:
             r.update(ms_per_outer=t / max(leg.iters, 1))
             if leg.bytes_per_outer:

@@ -119,6 +119,10 @@ typedef struct {
     int32_t gram;           /* sstep_gram_kind: how G = P^T A P (Sec. 2) is formed.  SSTEP_GRAM_AUTO
                                (default) = SSTEP_GRAM_APPLY_OP for FP64 stencil operators with
                                s <= 16 and n < 2^29, SSTEP_GRAM_STORED_AP otherwise */
+    int32_t basis;          /* 0 = Chebyshev basis (default, Sec. 2); 1 = monomial basis
+                               p_{j+1} = M^{-1} A p_j of the same Krylov space, the comparison of
+                               Sec. 4 (a diagnostic: its Gram matrix is badly conditioned; the
+                               bounds are then unused; not for batched contexts) */
     void *stream;           /* hipStream_t the caller's data is ordered on (NULL = default) */
 } sstep_options;
 

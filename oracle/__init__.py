@@ -15,57 +15,79 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB, LIB_OMP, build
 
 _lib = None
+_libs = {}
 
 STATUS = {0: "OK", 1: "E_ARG", 3: "E_NOMEM", 4: "E_BREAKDOWN", 5: "E_NOCONV", 6: "E_NONFINITE"}
 
 
-def _load():
+def select_build(openmp: bool) -> int:
+    """Route every function of this module to the sequential reference build
+    (default, the one the tests pin) or to the OpenMP timing build of the same
+    source (CPU baseline only).  Returns the OpenMP thread count in use (1 for
+    the reference build)."""
     global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        _lib = C.CDLL(LIB)
-        d, i32, i64 = C.c_double, C.c_int32, C.c_int64
-        pd, pi = C.POINTER(C.c_double), C.POINTER(C.c_int32)
-        _lib.oracle_dot.restype = d
-        _lib.oracle_dot.argtypes = [i64, pd, pd]
-        _lib.oracle_csr_validate.restype = C.c_int
-        _lib.oracle_csr_validate.argtypes = [i64, pi, pi]
-        _lib.oracle_spmv.restype = None
-        _lib.oracle_spmv.argtypes = [i64, pi, pi, pd, pd, pd]
-        _lib.oracle_stencil7_nnz.restype = i64
-        _lib.oracle_stencil7_nnz.argtypes = [i32, i32, i32]
-        _lib.oracle_assemble_stencil7.restype = i64
-        _lib.oracle_assemble_stencil7.argtypes = [i32, i32, i32, pd, pd, pd, pi, pi, pd]
-        _lib.oracle_stencil27_nnz.restype = i64
-        _lib.oracle_stencil27_nnz.argtypes = [i32, i32, i32]
-        _lib.oracle_assemble_stencil27.restype = i64
-        _lib.oracle_assemble_stencil27.argtypes = [i32, i32, i32, pi, pi, pd]
-        _lib.oracle_jacobi.restype = C.c_int
-        _lib.oracle_jacobi.argtypes = [i64, pi, pi, pd, C.c_int, pd, pd]
-        _lib.oracle_chebyshev_basis.restype = None
-        _lib.oracle_chebyshev_basis.argtypes = [i64, pi, pi, pd, pd, C.c_int, d, d, pd, pd]
-        _lib.oracle_gram.restype = None
-        _lib.oracle_gram.argtypes = [i64, C.c_int, pd, pd, pd, pd, pd]
-        _lib.oracle_column_scale.restype = C.c_int
-        _lib.oracle_column_scale.argtypes = [C.c_int, pd, pd, pd, pd, pd]
-        _lib.oracle_fgs.restype = None
-        _lib.oracle_fgs.argtypes = [C.c_int, pd, pd, C.c_int, pd]
-        _lib.oracle_sstep_step.restype = C.c_int
-        _lib.oracle_sstep_step.argtypes = [i64, pi, pi, pd, pd, pd, pd, C.c_int, C.c_int, d, d, C.c_int, C.c_int,
-                                           pd, pd, pd, pd, pd, pd, pd, pd, pd, pd]
-        _lib.oracle_sstep_solve.restype = C.c_int
-        _lib.oracle_sstep_solve.argtypes = [i64, pi, pi, pd, pd, pd, C.c_int, C.c_int, d, d, d, C.c_int, C.c_int,
-                                            C.c_int, C.POINTER(C.c_int), pd, pd, pd, pd, pd, C.c_int]
-        _lib.oracle_lanczos.restype = C.c_int
-        _lib.oracle_lanczos.argtypes = [i64, pi, pi, pd, C.c_int, pd, C.c_int, pd, pd]
-        _lib.oracle_grad_csr.restype = None
-        _lib.oracle_grad_csr.argtypes = [i64, pi, pi, pd, pd, pd]
-        _lib.oracle_grad_faces.restype = None
-        _lib.oracle_grad_faces.argtypes = [i32, i32, i32, pd, pd, pd, pd, pd]
+    _lib = None
+    lib = _load(LIB_OMP if openmp else LIB)
+    if not openmp:
+        return 1
+    f = lib.omp_get_max_threads
+    f.restype = C.c_int
+    return int(f())
+
+
+def _load(path=None):
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    path = path or LIB
+    if path in _libs:
+        _lib = _libs[path]
+        return _lib
+    if not os.path.exists(path):
+        build()
+    _lib = C.CDLL(path)
+    _libs[path] = _lib
+    d, i32, i64 = C.c_double, C.c_int32, C.c_int64
+    pd, pi = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    _lib.oracle_dot.restype = d
+    _lib.oracle_dot.argtypes = [i64, pd, pd]
+    _lib.oracle_csr_validate.restype = C.c_int
+    _lib.oracle_csr_validate.argtypes = [i64, pi, pi]
+    _lib.oracle_spmv.restype = None
+    _lib.oracle_spmv.argtypes = [i64, pi, pi, pd, pd, pd]
+    _lib.oracle_stencil7_nnz.restype = i64
+    _lib.oracle_stencil7_nnz.argtypes = [i32, i32, i32]
+    _lib.oracle_assemble_stencil7.restype = i64
+    _lib.oracle_assemble_stencil7.argtypes = [i32, i32, i32, pd, pd, pd, pi, pi, pd]
+    _lib.oracle_stencil27_nnz.restype = i64
+    _lib.oracle_stencil27_nnz.argtypes = [i32, i32, i32]
+    _lib.oracle_assemble_stencil27.restype = i64
+    _lib.oracle_assemble_stencil27.argtypes = [i32, i32, i32, pi, pi, pd]
+    _lib.oracle_jacobi.restype = C.c_int
+    _lib.oracle_jacobi.argtypes = [i64, pi, pi, pd, C.c_int, pd, pd]
+    _lib.oracle_chebyshev_basis.restype = None
+    _lib.oracle_chebyshev_basis.argtypes = [i64, pi, pi, pd, pd, C.c_int, d, d, pd, pd]
+    _lib.oracle_gram.restype = None
+    _lib.oracle_gram.argtypes = [i64, C.c_int, pd, pd, pd, pd, pd]
+    _lib.oracle_column_scale.restype = C.c_int
+    _lib.oracle_column_scale.argtypes = [C.c_int, pd, pd, pd, pd, pd]
+    _lib.oracle_fgs.restype = None
+    _lib.oracle_fgs.argtypes = [C.c_int, pd, pd, C.c_int, pd]
+    _lib.oracle_sstep_step.restype = C.c_int
+    _lib.oracle_sstep_step.argtypes = [i64, pi, pi, pd, pd, pd, pd, C.c_int, C.c_int, d, d, C.c_int, C.c_int,
+                                       C.c_int, pd, pd, pd, pd, pd, pd, pd, pd, pd, pd]
+    _lib.oracle_sstep_solve.restype = C.c_int
+    _lib.oracle_sstep_solve.argtypes = [i64, pi, pi, pd, pd, pd, C.c_int, C.c_int, d, d, d, C.c_int, C.c_int,
+                                        C.c_int, C.c_int, C.POINTER(C.c_int), pd, pd, pd, pd, pd, C.c_int]
+    _lib.oracle_lanczos.restype = C.c_int
+    _lib.oracle_lanczos.argtypes = [i64, pi, pi, pd, C.c_int, pd, C.c_int, pd, pd]
+    _lib.oracle_grad_csr.restype = None
+    _lib.oracle_grad_csr.argtypes = [i64, pi, pi, pd, pd, pd]
+    _lib.oracle_grad_faces.restype = None
+    _lib.oracle_grad_faces.argtypes = [i32, i32, i32, pd, pd, pd, pd, pd]
     return _lib
 
 
@@ -187,11 +209,16 @@ def fgs(G, ctil, nu):
     return a
 
 
-def step(A, b, xk, s, nu, lmin, lmax, precond=1, p0_mode=0, want_basis=False):
+BASIS = {"chebyshev": 0, "monomial": 1}
+
+
+def step(A, b, xk, s, nu, lmin, lmax, precond=1, p0_mode=0, want_basis=False, basis="chebyshev"):
     """One outer iteration from ``xk``.  Returns a dict with ``status``,
     ``x`` (x_{k+1}), ``atil``, ``G``, ``ctil``, ``Graw``, ``d``, ``rnorm``,
     ``delta`` (Gram-solve residual, Sec. 7), ``lnorm`` (||L||_F, Sec. 4) and,
-    with ``want_basis``, ``P`` / ``AP`` of shape (s, n)."""
+    with ``want_basis``, ``P`` / ``AP`` of shape (s, n).  ``basis`` is
+    ``"chebyshev"`` (Sec. 2) or ``"monomial"`` (p_{j+1} = M^{-1} A p_j, the
+    comparison of Sec. 4)."""
     rp, ci, v = _csr(A)
     n = rp.size - 1
     b, xk = _f64(b), _f64(xk)
@@ -201,7 +228,7 @@ def step(A, b, xk, s, nu, lmin, lmax, precond=1, p0_mode=0, want_basis=False):
     P = np.zeros((s, n)) if want_basis else None
     AP = np.zeros((s, n)) if want_basis else None
     st = _load().oracle_sstep_step(n, _pi(rp), _pi(ci), _pd(v), _pd(b), _pd(xk), _pd(xn), s, nu, lmin, lmax,
-                                   precond, p0_mode, _pd(out["atil"]), _pd(out["G"]), _pd(out["ctil"]),
+                                   precond, p0_mode, BASIS[basis], _pd(out["atil"]), _pd(out["G"]), _pd(out["ctil"]),
                                    _pd(out["Graw"]), _pd(out["d"]), _pd(out["rnorm"]), _pd(out["delta"]),
                                    _pd(out["lnorm"]), _pd(P), _pd(AP))
     out.update(status=st, x=xn, rnorm=float(out["rnorm"][0]), delta=float(out["delta"][0]),
@@ -211,7 +238,7 @@ def step(A, b, xk, s, nu, lmin, lmax, precond=1, p0_mode=0, want_basis=False):
     return out
 
 
-def solve(A, b, x0, s, nu, lmin, lmax, tol, max_outer=10000, precond=1, p0_mode=0, hist_cap=0):
+def solve(A, b, x0, s, nu, lmin, lmax, tol, max_outer=10000, precond=1, p0_mode=0, hist_cap=0, basis="chebyshev"):
     """Full solve; returns a dict with ``status``, ``x``, ``iters``,
     ``relres``, ``res0`` and the histories when ``hist_cap > 0``."""
     rp, ci, v = _csr(A)
@@ -225,7 +252,7 @@ def solve(A, b, x0, s, nu, lmin, lmax, tol, max_outer=10000, precond=1, p0_mode=
     hd = np.zeros(hist_cap) if hist_cap else None
     hl = np.zeros(hist_cap) if hist_cap else None
     st = _load().oracle_sstep_solve(n, _pi(rp), _pi(ci), _pd(v), _pd(b), _pd(x), s, nu, lmin, lmax, tol, max_outer,
-                                    precond, p0_mode, C.byref(it), _pd(rel), _pd(r0), _pd(hr), _pd(hd), _pd(hl),
+                                    precond, p0_mode, BASIS[basis], C.byref(it), _pd(rel), _pd(r0), _pd(hr), _pd(hd), _pd(hl),
                                     hist_cap)
     out = dict(status=st, x=x, iters=it.value, relres=float(rel[0]), res0=float(r0[0]))
     if hist_cap:

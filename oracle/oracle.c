@@ -36,6 +36,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum {
     ORACLE_OK = 0,
@@ -66,9 +69,37 @@ static void nsum_add(nsum_t *a, double v)
 
 static double nsum_value(const nsum_t *a) { return a->sum + a->comp; }
 
-/* Compensated dot product sum_m u[m] * v[m]. */
+/* Compensated dot product sum_m u[m] * v[m].  The timing build with OpenMP
+ * (oracle/build.py, CPU baseline only) sums contiguous per-thread ranges with
+ * the same compensated sum and combines the per-thread sums and corrections in
+ * thread order; the reference build used by the tests is sequential. */
 double oracle_dot(int64_t n, const double *u, const double *v)
 {
+#ifdef _OPENMP
+    if (n >= 65536 && omp_get_max_threads() > 1) {
+        double sums[512], comps[512];
+        int used = 1;
+        const int nt = omp_get_max_threads() < 512 ? omp_get_max_threads() : 512;
+#pragma omp parallel num_threads(nt)
+        {
+            const int t = omp_get_thread_num(), T = omp_get_num_threads();
+            const int64_t lo = n * t / T, hi = n * (t + 1) / T;
+            nsum_t a = {0.0, 0.0};
+            for (int64_t m = lo; m < hi; ++m)
+                nsum_add(&a, u[m] * v[m]);
+            sums[t] = a.sum;
+            comps[t] = a.comp;
+            if (t == 0)
+                used = T;
+        }
+        nsum_t acc = {0.0, 0.0};
+        for (int t = 0; t < used; ++t) {
+            nsum_add(&acc, sums[t]);
+            nsum_add(&acc, comps[t]);
+        }
+        return nsum_value(&acc);
+    }
+#endif
     nsum_t acc = {0.0, 0.0};
     for (int64_t m = 0; m < n; ++m)
         nsum_add(&acc, u[m] * v[m]);
@@ -102,6 +133,7 @@ int oracle_csr_validate(int64_t n, const int32_t *row_ptr, const int32_t *col_id
 void oracle_spmv(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                  const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
@@ -245,14 +277,35 @@ void oracle_chebyshev_basis(int64_t n, const int32_t *row_ptr, const int32_t *co
             break;
         double *pnext = P + (int64_t)(j + 1) * n;
         if (j == 0) {
+#pragma omp parallel for schedule(static)
             for (int64_t m = 0; m < n; ++m)
                 pnext[m] = theta * (invd[m] * y[m] - sigma * pj[m]);
         } else {
             const double *pprev = P + (int64_t)(j - 1) * n;
             const double two_theta = 2.0 * theta;
+#pragma omp parallel for schedule(static)
             for (int64_t m = 0; m < n; ++m)
                 pnext[m] = two_theta * (invd[m] * y[m] - sigma * pj[m]) - pprev[m];
         }
+    }
+}
+
+/* Monomial basis of the same Krylov space (the comparison of Sec. 4):
+ *   p_{j+1} = M^{-1} A p_j,
+ * with AP[:, j] = A p_j for j = 0..s-1 as above.  Column 0 of P must hold p_0. */
+void oracle_monomial_basis(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                           const double *invd, int s, double *P, double *AP)
+{
+    for (int j = 0; j < s; ++j) {
+        const double *pj = P + (int64_t)j * n;
+        double *y = AP + (int64_t)j * n;
+        oracle_spmv(n, row_ptr, col_idx, val, pj, y); /* y = A p_j */
+        if (j + 1 >= s)
+            break;
+        double *pnext = P + (int64_t)(j + 1) * n;
+#pragma omp parallel for schedule(static)
+        for (int64_t m = 0; m < n; ++m)
+            pnext[m] = invd[m] * y[m];
     }
 }
 
@@ -328,7 +381,7 @@ typedef struct {
     const int32_t *col_idx;
     const double *val;
     const double *invd;
-    int s, nu, p0_mode;
+    int s, nu, p0_mode, basis; /* basis: 0 Chebyshev, 1 monomial */
     double theta, sigma;
     double *P, *AP, *r; /* n*s, n*s, n */
 } oracle_ws;
@@ -337,6 +390,7 @@ typedef struct {
 static double residual(const oracle_ws *w, const double *b, const double *x, double *r)
 {
     oracle_spmv(w->n, w->row_ptr, w->col_idx, w->val, x, r);
+#pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < w->n; ++m)
         r[m] = b[m] - r[m];
     return sqrt(oracle_dot(w->n, r, r));
@@ -352,9 +406,13 @@ static int outer_update(const oracle_ws *w, double *x, double *atil_out, double 
     double Graw[64 * 64], G[64 * 64], c[64], ctil[64], d[64], atil[64], alpha[64];
 
     /* p_0 = M^{-1} r (p0_mode 0) or r (p0_mode 1) */
+#pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < n; ++m)
         w->P[m] = w->p0_mode ? w->r[m] : w->invd[m] * w->r[m];
-    oracle_chebyshev_basis(n, w->row_ptr, w->col_idx, w->val, w->invd, s, w->theta, w->sigma, w->P, w->AP);
+    if (w->basis == 1)
+        oracle_monomial_basis(n, w->row_ptr, w->col_idx, w->val, w->invd, s, w->P, w->AP);
+    else
+        oracle_chebyshev_basis(n, w->row_ptr, w->col_idx, w->val, w->invd, s, w->theta, w->sigma, w->P, w->AP);
     oracle_gram(n, s, w->P, w->AP, w->r, Graw, c);
     const int st = oracle_column_scale(s, Graw, c, G, ctil, d);
     if (Graw_out)
@@ -366,6 +424,7 @@ static int outer_update(const oracle_ws *w, double *x, double *atil_out, double 
     /* alpha = S atil (coefficients of the unscaled basis), x += P alpha */
     for (int i = 0; i < s; ++i)
         alpha[i] = d[i] * atil[i];
+#pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < n; ++m) {
         double acc = 0.0;
         for (int i = 0; i < s; ++i)
@@ -419,7 +478,7 @@ static int check_common(int64_t n, const int32_t *row_ptr, const int32_t *col_id
 }
 
 static int ws_init(oracle_ws *w, int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
-                   int s, int nu, double lmin, double lmax, int precond, int p0_mode, double **invd_store)
+                   int s, int nu, double lmin, double lmax, int precond, int p0_mode, int basis, double **invd_store)
 {
     memset(w, 0, sizeof(*w));
     w->n = n;
@@ -429,6 +488,7 @@ static int ws_init(oracle_ws *w, int64_t n, const int32_t *row_ptr, const int32_
     w->s = s;
     w->nu = nu;
     w->p0_mode = p0_mode;
+    w->basis = basis;
     w->theta = 2.0 / (lmax - lmin);
     w->sigma = (lmax + lmin) / 2.0;
     double *invd = (double *)malloc(sizeof(double) * n);
@@ -458,15 +518,16 @@ static void ws_free(oracle_ws *w, double *invd)
  * output pointer may be NULL. */
 int oracle_sstep_step(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                       const double *b, const double *xk, double *xnext, int s, int nu, double lmin, double lmax,
-                      int precond, int p0_mode, double *atil, double *G, double *ctil, double *Graw, double *d,
+                      int precond, int p0_mode, int basis, double *atil, double *G, double *ctil, double *Graw,
+                      double *d,
                       double *rnorm, double *delta, double *lnorm, double *P_out, double *AP_out)
 {
     int st = check_common(n, row_ptr, col_idx, val, s, nu, lmin, lmax);
-    if (st != ORACLE_OK || !b || !xk || !xnext)
+    if (st != ORACLE_OK || !b || !xk || !xnext || (basis != 0 && basis != 1))
         return st != ORACLE_OK ? st : ORACLE_E_ARG;
     oracle_ws w;
     double *invd = NULL;
-    st = ws_init(&w, n, row_ptr, col_idx, val, s, nu, lmin, lmax, precond, p0_mode, &invd);
+    st = ws_init(&w, n, row_ptr, col_idx, val, s, nu, lmin, lmax, precond, p0_mode, basis, &invd);
     if (st == ORACLE_OK) {
         const double rho = residual(&w, b, xk, w.r);
         if (rnorm)
@@ -492,17 +553,17 @@ int oracle_sstep_step(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
  * ||L||_F (Sec. 4).  On an error x holds the last completed iterate. */
 int oracle_sstep_solve(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                        const double *b, double *x, int s, int nu, double lmin, double lmax, double tol,
-                       int max_outer, int precond, int p0_mode, int *iters, double *relres, double *res0,
+                       int max_outer, int precond, int p0_mode, int basis, int *iters, double *relres, double *res0,
                        double *hist_relres, double *hist_delta, double *hist_lnorm, int hist_cap)
 {
     int st = check_common(n, row_ptr, col_idx, val, s, nu, lmin, lmax);
     if (st != ORACLE_OK)
         return st;
-    if (!b || !x || !(tol > 0.0) || !(tol < 1.0) || max_outer < 0)
+    if (!b || !x || !(tol > 0.0) || !(tol < 1.0) || max_outer < 0 || (basis != 0 && basis != 1))
         return ORACLE_E_ARG;
     oracle_ws w;
     double *invd = NULL;
-    st = ws_init(&w, n, row_ptr, col_idx, val, s, nu, lmin, lmax, precond, p0_mode, &invd);
+    st = ws_init(&w, n, row_ptr, col_idx, val, s, nu, lmin, lmax, precond, p0_mode, basis, &invd);
     double rho0 = 0.0;
     int k = 0;
     if (iters)

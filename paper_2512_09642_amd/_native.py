@@ -35,7 +35,7 @@ class Operator(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("p0_mode", C.c_int32),
                 ("max_outer", C.c_int32), ("graph_chunk", C.c_int32), ("record_history", C.c_int32),
-                ("autotune", C.c_int32), ("gram", C.c_int32), ("stream", C.c_void_p)]
+                ("autotune", C.c_int32), ("gram", C.c_int32), ("basis", C.c_int32), ("stream", C.c_void_p)]
 
 
 class Stats(C.Structure):

@@ -43,7 +43,8 @@ class SStepSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, coeffs: torch.Tensor, b: torch.Tensor, solver: Solver, tol: float = 1e-8):
         token = _load(solver, coeffs)
-        x, _ = solver.solve(b.detach().contiguous(), None, tol)
+        x, st = solver.solve(b.detach().contiguous(), None, tol)
+        solver.last_forward_stats = st
         ctx.solver = solver
         ctx.tol = tol
         ctx.token = token
@@ -60,7 +61,8 @@ class SStepSolve(torch.autograd.Function):
             # another forward (or update_coefficients) has loaded other
             # coefficients into the shared solver since: reload this one's
             ctx.token = _load(solver, coeffs)
-        lam, _ = solver.solve_adjoint(gx.detach().contiguous(), None, ctx.tol)
+        lam, sta = solver.solve_adjoint(gx.detach().contiguous(), None, ctx.tol)
+        solver.last_adjoint_stats = sta
         dcoef = solver.grad_operator(lam, x) if ctx.needs_input_grad[0] else None
         db = lam if ctx.needs_input_grad[1] else None
         return dcoef, db, None, None

@@ -300,6 +300,42 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
     return SSTEP_OK;
 }
 
+// The operator-applying Gram kernel: 7-point stencil operators, s <= 16,
+// columns under 4 GiB (32-bit byte offsets); by default for FP64 only (in
+// FP32+IR the stored-AP kernel is as fast).
+sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, const sstep_options &o, bool *gram_op)
+{
+    const int64_t n = A->kind == SSTEP_OP_CSR ? A->n : int64_t(A->nx) * A->ny * A->nz;
+    const uint64_t wbytes = o.precision == SSTEP_FP32_IR ? sizeof(float) : sizeof(double);
+    const bool op_ok = A->kind == SSTEP_OP_STENCIL7 && s <= kGoMaxS &&
+                       uint64_t(round_up(n, kPad)) * wbytes < (uint64_t(1) << 32);
+    if (o.gram == SSTEP_GRAM_APPLY_OP && !op_ok)
+        return fail(ctx, SSTEP_E_UNSUPPORTED,
+                    "the operator-applying Gram kernel needs a 7-point stencil operator, s <= 16 and columns "
+                    "under 4 GiB");
+    *gram_op = o.gram == SSTEP_GRAM_APPLY_OP || (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
+    return SSTEP_OK;
+}
+
+// Residual kernel schedule: at most 1024 row chunks (one partial each), or
+// for the constant Poisson operator with an even x-extent the 1024-thread
+// blocks of 2 x-points x 8 planes when they number at most 1024.
+void set_residual_schedule(IterArgs &it)
+{
+    const OpDev &op = it.op;
+    const int64_t n = op.n;
+    it.nbr = int(std::min<int64_t>(1024, (n + kBlock - 1) / kBlock));
+    it.rchunk = round_up((n + it.nbr - 1) / it.nbr, kBlock);
+    it.res_p2 = 0;
+    if (op.kind == kOpPoisson && op.g.nx % 2 == 0) {
+        const int64_t blocks = ((op.g.nxy / 2 + 1023) / 1024) * ((op.g.nz + 7) / 8);
+        if (blocks <= 1024) {
+            it.res_p2 = 1;
+            it.nbr = int(blocks);
+        }
+    }
+}
+
 // Basis launches per outer iteration: s, or s - 1 when the Gram kernel forms
 // the products itself (the last launch would only compute A p_{s-1}).
 int basis_launches(const IterArgs &a) { return a.gram_op ? a.s - 1 : a.s; }
@@ -589,6 +625,7 @@ void sstep_default_options(sstep_options *opt)
     opt->record_history = 0;
     opt->autotune = 1;
     opt->gram = SSTEP_GRAM_AUTO;
+    opt->basis = 0;
     opt->stream = nullptr;
 }
 
@@ -670,6 +707,8 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         return fail(ctx, SSTEP_E_ARG, "p0_mode must be 0 or 1");
     if (o.max_outer < 0)
         return fail(ctx, SSTEP_E_ARG, "max_outer must be >= 0");
+    if (o.basis != 0 && o.basis != 1)
+        return fail(ctx, SSTEP_E_ARG, "basis must be 0 (Chebyshev) or 1 (monomial)");
     if (o.graph_chunk <= 0)
         o.graph_chunk = 4;
     OKCHK(check_operator(ctx, A));
@@ -677,21 +716,8 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         OKCHK(check_csr_pattern(ctx, A));
     if (o.gram != SSTEP_GRAM_AUTO && o.gram != SSTEP_GRAM_STORED_AP && o.gram != SSTEP_GRAM_APPLY_OP)
         return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
-    // The operator-applying Gram kernel: stencil operators, s <= 16, columns
-    // under 4 GiB (32-bit byte offsets); by default for FP64 only (in FP32+IR
-    // the stored-AP kernel is as fast).
     bool gram_op = false;
-    {
-        const int64_t n = A->kind == SSTEP_OP_CSR ? A->n : int64_t(A->nx) * A->ny * A->nz;
-        const uint64_t wbytes = o.precision == SSTEP_FP32_IR ? sizeof(float) : sizeof(double);
-        const bool op_ok = A->kind == SSTEP_OP_STENCIL7 && s <= kGoMaxS &&
-                           uint64_t(round_up(n, kPad)) * wbytes < (uint64_t(1) << 32);
-        if (o.gram == SSTEP_GRAM_APPLY_OP && !op_ok)
-            return fail(ctx, SSTEP_E_UNSUPPORTED,
-                        "the operator-applying Gram kernel needs a 7-point stencil operator, s <= 16 and columns "
-                        "under 4 GiB");
-        gram_op = o.gram == SSTEP_GRAM_APPLY_OP || (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
-    }
+    OKCHK(choose_gram_kind(ctx, A, s, o, &gram_op));
 
     HIPCHK(ctx, hipGetDevice(&ctx->device));
     HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -713,6 +739,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     OpDev &op = it.op;
     it.fp32 = o.precision == SSTEP_FP32_IR;
     it.p0_mode = o.p0_mode;
+    it.monomial = o.basis;
     it.s = s;
     it.nu = nu;
     it.theta = 2.0 / (lmax - lmin);
@@ -766,16 +793,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         it.P = P;
         it.AP = AP;
     }
-    it.nbr = int(std::min<int64_t>(1024, (n + kBlock - 1) / kBlock));
-    it.rchunk = round_up((n + it.nbr - 1) / it.nbr, kBlock);
-    if (op.kind == kOpPoisson && op.g.nx % 2 == 0) {
-        // 1024-thread blocks of 2 x-points x 8 planes, one partial each
-        const int64_t blocks = ((op.g.nxy / 2 + 1023) / 1024) * ((op.g.nz + 7) / 8);
-        if (blocks <= 1024) {
-            it.res_p2 = 1;
-            it.nbr = int(blocks);
-        }
-    }
+    set_residual_schedule(it);
     OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
     OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * kMaxGramBlocks));
     OKCHK(dalloc(ctx, &it.gsum, size_t(gram_entries(s)) + 1));
@@ -1230,6 +1248,8 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         return fail(ctx, SSTEP_E_ARG, "unknown precision");
     if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0)
         return fail(ctx, SSTEP_E_ARG, "invalid options");
+    if (o.basis != 0)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves use the Chebyshev basis");
     if (o.graph_chunk <= 0)
         o.graph_chunk = 4;
     for (int q = 0; q < nsys; ++q) {

@@ -1,6 +1,8 @@
 // Streaming kernels of the outer iteration: residual + basis start, the fused
 // SpMV/Jacobi/Chebyshev basis step, the update x += P alpha, and helpers.
 // All of them are bound by HBM bandwidth (well under one flop per byte).
+#include <algorithm>
+
 #include "launch.h"
 #include "opsel.h"
 #include "stop.h"
@@ -649,6 +651,14 @@ hipError_t launch_p0scale(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st)
 {
+    if (a.monomial) {
+        // p_{j+1} = theta (M^{-1} A p_j - sigma p_j) with theta = 1, sigma = 0
+        IterArgs m = a;
+        m.theta = 1.0;
+        m.sigma = 0.0;
+        const int step = j + 1 >= a.s ? 2 : 0;
+        return a.fp32 ? basis_t<float>(m, j, step, st) : basis_t<double>(m, j, step, st);
+    }
     const int step = j + 1 >= a.s ? 2 : (j == 0 ? 0 : 1);
     return a.fp32 ? basis_t<float>(a, j, step, st) : basis_t<double>(a, j, step, st);
 }

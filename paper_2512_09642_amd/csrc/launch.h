@@ -47,6 +47,7 @@ struct IterArgs {
     OpDev op;
     int fp32 = 0;     // 1 = FP32 basis / SpMV / Gram
     int p0_mode = 0;  // 0: p_0 = M^{-1} r, 1: p_0 = r
+    int monomial = 0; // 1: monomial basis p_{j+1} = M^{-1} A p_j instead of Chebyshev
     int s = 0, nu = 0;
     double theta = 0, sigma = 0;
     void *P = nullptr;   // n x s, column-major, leading dimension ld

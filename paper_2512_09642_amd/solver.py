@@ -132,7 +132,8 @@ class Solver:
 
     def __init__(self, op: Operator, s: int, nu: int, lmin: float, lmax: float, *, precision: str = "fp64",
                  precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
-                 record_history: bool = False, autotune: bool = True, gram: str = "auto", stream=None):
+                 record_history: bool = False, autotune: bool = True, gram: str = "auto", basis: str = "chebyshev",
+                 stream=None):
         self._lib = N.load()
         self.op = op
         self.s, self.nu, self.lmin, self.lmax = s, nu, lmin, lmax
@@ -147,6 +148,7 @@ class Solver:
         opt.record_history = 1 if record_history else 0
         opt.autotune = 1 if autotune else 0
         opt.gram = N.GRAM_KINDS[gram]
+        opt.basis = {"chebyshev": 0, "monomial": 1}[basis]
         self._stream = stream
         opt.stream = self._stream_ptr()
         self.max_outer = max_outer

@@ -135,3 +135,48 @@ def test_paper27_full_size_lockstep_and_solve(hip, p27):
     print(f"230^3 27-point s=20 nu=30: Lanczos bounds [{lo:.4e}, {hi:.4e}], {st.outer_iters} outer")
     assert st.status == 0
     assert np.linalg.norm(b - oracle.spmv(A, host(x))) / np.linalg.norm(b) <= 1e-8
+
+
+@pytest.mark.parametrize("case", ["poisson7", "poisson27", "faces7"])
+def test_monomial_basis_lockstep(hip, case):
+    """The monomial basis of Sec. 4's comparison (p_{j+1} = M^{-1} A p_j) on
+    the GPU against the oracle's, one lockstep outer iteration (s = 6, where
+    its Gram matrix is still well inside FP64): G, ctil, atil, x_1 within
+    1e-10, and the condition numbers of both Gram matrices."""
+    if case == "poisson7":
+        pr = gen.small_poisson3d(17, 14, 12, seed=9)
+    elif case == "faces7":
+        pr = gen.small_faces3d(15, 13, 11, seed=10)
+    else:
+        pr = gen.small_poisson27(16, 13, 11, seed=11)
+    A, b = oracle_rhs(pr)
+    s = 6
+    with hip.Solver(make_operator(hip, pr, "stencil"), s, 20, pr.lmin, pr.lmax, basis="monomial") as sv:
+        g = sv.step(t64(b), t64(np.zeros(pr.n)))
+    o = oracle.step(A, b, np.zeros(pr.n), s, 20, pr.lmin, pr.lmax, basis="monomial")
+    for key in ("G", "ctil", "atil"):
+        assert rel(g[key], o[key]) <= 1e-10, (key, rel(g[key], o[key]))
+    assert rel(host(g["x"]), o["x"]) <= 1e-10
+    kg, ko = oracle.gram_condition(g["G"]), oracle.gram_condition(o["G"])
+    assert abs(kg - ko) <= 1e-6 * ko, (kg, ko)
+
+
+def test_gram_condition_chebyshev_vs_monomial_27(hip):
+    """kappa(G) of the first outer iteration for s = 10 and 20 on a 27-point
+    problem, Chebyshev basis with Lanczos bounds (10 steps, 10%): the GPU's G
+    gives the oracle's kappa; the monomial basis is orders of magnitude worse
+    (reported; the paper's 78 and 310 are for its AMG-preconditioned runs)."""
+    pr = gen.small_poisson27(40, 36, 32, seed=12)
+    A, b = oracle_rhs(pr)
+    u = gen.uniform(gen.rng(43), pr.n)
+    lo, hi = oracle.lanczos_bounds(oracle.lanczos(A, u, 10)["ritz"], 0.1)
+    for s in (10, 20):
+        with hip.Solver(make_operator(hip, pr, "stencil"), s, 30, lo, hi) as sv:
+            g = sv.step(t64(b), t64(np.zeros(pr.n)))
+        with hip.Solver(make_operator(hip, pr, "stencil"), s, 30, lo, hi, basis="monomial") as sv:
+            gm = sv.step(t64(b), t64(np.zeros(pr.n)))
+        o = oracle.step(A, b, np.zeros(pr.n), s, 30, lo, hi)
+        kg, ko, km = oracle.gram_condition(g["G"]), oracle.gram_condition(o["G"]), oracle.gram_condition(gm["G"])
+        print(f"27-point 40x36x32, s={s}: kappa(G) Chebyshev {kg:.3e} (oracle {ko:.3e}), monomial {km:.3e}")
+        assert abs(kg - ko) <= 1e-6 * ko
+        assert km > 100 * kg

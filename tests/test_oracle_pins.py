@@ -768,3 +768,47 @@ def test_poisson27_solve_converges_to_direct_solution():
     ev = np.linalg.eigvalsh(Ad)
     xd = np.linalg.solve(Ad, b)
     assert rel(out["x"], xd) <= (ev[-1] / ev[0]) * 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Monomial basis (the comparison of Sec. 4)
+# ---------------------------------------------------------------------------
+
+def test_monomial_basis_closed_form_on_eigenvector():
+    """p_j = (M^{-1}A)^j p_0: on an eigenvector v of M^{-1}A with eigenvalue
+    lambda the basis is lambda^j v and A p_j = 6 lambda^{j+1} v (Poisson)."""
+    nx, ny, nz = 6, 5, 4
+    A = oracle.assemble_stencil7(nx, ny, nz)
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    v = (np.sin(2 * math.pi * (i + 1) / (nx + 1)) * np.sin(math.pi * (j + 1) / (ny + 1))
+         * np.sin(3 * math.pi * (k + 1) / (nz + 1))).ravel()
+    lam = (6 - 2 * math.cos(2 * math.pi / (nx + 1)) - 2 * math.cos(math.pi / (ny + 1))
+           - 2 * math.cos(3 * math.pi / (nz + 1))) / 6
+    b = oracle.spmv(A, v)  # r_0 = b for x_0 = 0, p_0 = M^{-1} r_0 = lambda v
+    out = oracle.step(A, b, np.zeros(v.size), 5, 3, 0.1, 1.9, want_basis=True, basis="monomial")
+    for jj in range(5):
+        assert np.linalg.norm(out["P"][jj] - lam ** (jj + 1) * v) <= 1e-13 * np.linalg.norm(v)
+        assert np.linalg.norm(out["AP"][jj] - 6 * lam ** (jj + 2) * v) <= 1e-12 * np.linalg.norm(v)
+
+
+def test_monomial_gram_condition_grows_exponentially():
+    """Sec. 4, monomial comparison: the column-scaled monomial Gram matrix is
+    far worse conditioned than the Chebyshev one, and its condition grows
+    much faster with s."""
+    N = 16
+    A = oracle.assemble_stencil7(N, N, N)
+    lo, hi = gen.jacobi_poisson_bounds(N, N, N)
+    b = oracle.spmv(A, gen.uniform(gen.rng(8), N ** 3))
+    kc, km = {}, {}
+    for s in (4, 6, 8):
+        oc = oracle.step(A, b, np.zeros(N ** 3), s, 5, lo, hi)
+        om = oracle.step(A, b, np.zeros(N ** 3), s, 5, lo, hi, basis="monomial")
+        kc[s], km[s] = oracle.gram_condition(oc["G"]), oracle.gram_condition(om["G"])
+    assert km[8] > 1e4 * kc[8], (kc, km)
+    # per two more columns the monomial condition grows >= 100x and at least
+    # 10x faster than the Chebyshev one
+    for s0 in (4, 6):
+        gm, gc = km[s0 + 2] / km[s0], kc[s0 + 2] / kc[s0]
+        assert gm >= 100 and gm >= 10 * gc, (s0, gm, gc)
