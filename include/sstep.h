@@ -270,6 +270,28 @@ sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_oper
 sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double *const *x, double tol,
                                  sstep_stats *st);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc/hipFree): sstep_setup + sstep_solve +
+ * sstep_destroy in one call that allocates nothing.  The whole workspace
+ * (basis P, products AP when kept, partial sums, solve state, Jacobi
+ * diagonals) lives in one static device array of 64 MiB per GPU, held from
+ * the library's first use on that GPU until the process ends; a problem whose
+ * workspace does not fit (about 128-256 bytes per unknown at s = 16, so up to
+ * some 250k-500k unknowns) gets SSTEP_E_ARG with the sizes in the message.
+ * Same arguments and results as sstep_setup / sstep_solve, with these limits:
+ * FP64 only (SSTEP_E_UNSUPPORTED otherwise); operator arrays (CSR, face
+ * coefficients) must be device memory (ptr_space = 1) and are used in place,
+ * the CSR pattern is validated on the device; the Gram schedule is the
+ * default one (no autotuning); no history is recorded (st->hist_* ignored);
+ * the outer iterations are launched directly on opt->stream, graph_chunk at a
+ * time, with a wait for the stop flag after each group, so the call cannot be
+ * captured into a graph.  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other host threads, other streams) race and
+ * give wrong results.  Errors: sstep_last_error(NULL). */
+sstep_status sstep_solve_noalloc(const sstep_operator *A, int32_t s, int32_t nu, double lambda_min,
+                                 double lambda_max, const sstep_options *opt, const double *b, double *x, double tol,
+                                 sstep_stats *st);
+
 const char *sstep_last_error(const sstep_ctx *ctx);
 const char *sstep_status_string(sstep_status s);
 void sstep_destroy(sstep_ctx *ctx);

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -1514,3 +1515,233 @@ sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace lives in a static device array of
+// kNoallocBytes per GPU, located once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+constexpr int kNoallocMaxDevices = 64;
+
+__device__ __align__(256) char scratch[kNoallocBytes];
+
+std::mutex g_noalloc_mutex;
+void *g_noalloc_ptr[kNoallocMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up on the first call on
+// the device, with the device current).
+sstep_status noalloc_scratch(char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(nullptr, "hipGetDevice", e);
+    if (dev < 0 || dev >= kNoallocMaxDevices)
+        return fail(nullptr, SSTEP_E_UNSUPPORTED, "device index beyond the no-allocation table");
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return hip_fail(nullptr, "hipGetSymbolAddress(scratch)", e != hipSuccess ? e : hipErrorInvalidSymbol);
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = static_cast<char *>(g_noalloc_ptr[dev]);
+    return SSTEP_OK;
+}
+
+// Byte offsets of the workspace regions in the scratch array, 256-aligned.
+struct NoallocLayout {
+    size_t st, rpart, gpart, gsum, dbg, hist, bad, dvec, invd, P, AP, total;
+};
+
+NoallocLayout noalloc_layout(const IterArgs &it)
+{
+    NoallocLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t E = size_t(gram_entries(it.s));
+    const size_t ld = size_t(it.ld);
+    L.st = take(sizeof(DevState));
+    L.rpart = take(size_t(it.nbr) * sizeof(double));
+    L.gpart = take(E * size_t(it.nbg) * sizeof(double));
+    L.gsum = take((E + 1) * sizeof(double));
+    L.dbg = take(size_t(dbg_size(it.s)) * sizeof(double));
+    L.hist = take(3 * sizeof(double));
+    L.bad = take(sizeof(int));
+    const bool faces = it.op.kind == kOpFaces, csr = it.op.kind == kOpCsr;
+    L.dvec = take(faces || csr ? ld * sizeof(double) : 0);
+    L.invd = take(csr ? ld * sizeof(double) : 0);
+    L.P = take(ld * size_t(it.s) * sizeof(double));
+    L.AP = take(it.gram_op ? 0 : ld * size_t(it.s) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double lmin, double lmax,
+                          const sstep_options *opt, const double *b, double *x, double tol, sstep_stats *stats)
+{
+    sstep_options o;
+    if (opt)
+        o = *opt;
+    else
+        sstep_default_options(&o);
+    if (s < 1 || s > kMaxS)
+        return fail(nullptr, SSTEP_E_ARG, "s must be in [1, 32]");
+    if (nu < 1)
+        return fail(nullptr, SSTEP_E_ARG, "nu must be >= 1");
+    if (!std::isfinite(lmin) || !std::isfinite(lmax) || lmin < 0.0 || !(lmax > lmin))
+        return fail(nullptr, SSTEP_E_ARG, "bounds must be finite with 0 <= lambda_min < lambda_max");
+    if (o.precision != SSTEP_FP64)
+        return fail(nullptr, SSTEP_E_UNSUPPORTED, "the allocation-free solve runs in FP64 only");
+    if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0 ||
+        (o.basis != 0 && o.basis != 1))
+        return fail(nullptr, SSTEP_E_ARG, "invalid options");
+    if (o.gram != SSTEP_GRAM_AUTO && o.gram != SSTEP_GRAM_STORED_AP && o.gram != SSTEP_GRAM_APPLY_OP)
+        return fail(nullptr, SSTEP_E_ARG, "unknown gram kind");
+    if (!b || !x)
+        return fail(nullptr, SSTEP_E_ARG, "b and x must not be NULL");
+    if (!(tol > 0.0) || !(tol < 1.0))
+        return fail(nullptr, SSTEP_E_ARG, "tol must be in (0, 1)");
+    OKCHK(check_operator(nullptr, A));
+    const bool has_arrays = A->kind == SSTEP_OP_CSR || (A->kind == SSTEP_OP_STENCIL7 && A->kx);
+    if (has_arrays && A->ptr_space != 1)
+        return fail(nullptr, SSTEP_E_ARG, "the allocation-free solve takes operator arrays in device memory");
+    bool gram_op = false;
+    OKCHK(choose_gram_kind(nullptr, A, s, o, &gram_op));
+
+    IterArgs it;
+    OpDev &op = it.op;
+    op.precond = o.precond;
+    if (A->kind == SSTEP_OP_CSR) {
+        op.kind = kOpCsr;
+        op.n = A->n;
+        op.nnz = A->nnz;
+        op.rp = A->row_ptr;
+        op.ci = A->col_idx;
+        op.val = A->val;
+    } else {
+        op.kind = A->kind == SSTEP_OP_STENCIL27 ? kOpPoisson27 : (A->kx ? kOpFaces : kOpPoisson);
+        op.n = int64_t(A->nx) * A->ny * A->nz;
+        op.g.nx = A->nx;
+        op.g.ny = A->ny;
+        op.g.nz = A->nz;
+        op.g.nxy = int64_t(A->nx) * A->ny;
+        op.g.dx = make_fastdiv(uint32_t(A->nx));
+        op.g.dy = make_fastdiv(uint32_t(A->ny));
+        op.kx = A->kx;
+        op.ky = A->ky;
+        op.kz = A->kz;
+    }
+    it.fp32 = 0;
+    it.p0_mode = o.p0_mode;
+    it.monomial = o.basis;
+    it.s = s;
+    it.nu = nu;
+    it.theta = 2.0 / (lmax - lmin);
+    it.sigma = (lmax + lmin) / 2.0;
+    it.ld = round_up(op.n, kPad);
+    it.gram_op = gram_op;
+    const bool jac_p0 = o.precond == 1 && o.p0_mode == 0;
+    const bool const_diag = op.kind == kOpPoisson || op.kind == kOpPoisson27;
+    it.wdvec = jac_p0 && !const_diag;
+    it.cscale = (jac_p0 && const_diag) ? (op.kind == kOpPoisson27 ? 26.0 : 6.0) : 1.0;
+    it.inv_sqrt_n = 1.0 / std::sqrt(double(op.n));
+    it.hist_cap = 0;
+    set_residual_schedule(it);
+    set_gram_schedule(it, default_gram_schedule(it));  // the context path's schedule without autotuning
+    const NoallocLayout L = noalloc_layout(it);
+    if (L.total > kNoallocBytes)
+        return fail(nullptr, SSTEP_E_ARG,
+                    "problem too large for the allocation-free solve: needs " + std::to_string(L.total) +
+                        " bytes of workspace, the static scratch holds " + std::to_string(kNoallocBytes));
+
+    char *base = nullptr;
+    OKCHK(noalloc_scratch(&base));
+    it.st = reinterpret_cast<DevState *>(base + L.st);
+    it.rpart = reinterpret_cast<double *>(base + L.rpart);
+    it.gpart = reinterpret_cast<double *>(base + L.gpart);
+    it.gsum = reinterpret_cast<double *>(base + L.gsum);
+    it.dbg = reinterpret_cast<double *>(base + L.dbg);
+    it.hist = reinterpret_cast<double *>(base + L.hist);
+    int *bad = reinterpret_cast<int *>(base + L.bad);
+    it.P = base + L.P;
+    it.AP = it.gram_op ? nullptr : base + L.AP;
+
+    hipStream_t st = static_cast<hipStream_t>(o.stream);
+    // the array keeps the previous call's contents: clear everything that is
+    // read before it is written (padding rows of P, AP and the diagonal)
+    HIPCHK(nullptr, launch_fill_zero(base, L.total, st));
+    if (op.kind == kOpCsr) {
+        HIPCHK(nullptr, launch_check_csr_rows(op.rp, op.n, op.nnz, bad, st));
+        int hbad = 0;
+        HIPCHK(nullptr, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipStreamSynchronize(st));
+        if (!hbad) {
+            HIPCHK(nullptr, launch_check_csr_cols(op.rp, op.ci, op.n, bad, st));
+            HIPCHK(nullptr, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(nullptr, hipStreamSynchronize(st));
+        }
+        if (hbad)
+            return fail(nullptr, SSTEP_E_ARG, "malformed CSR pattern");
+        double *dvec = reinterpret_cast<double *>(base + L.dvec), *invd = reinterpret_cast<double *>(base + L.invd);
+        op.dvec = dvec;
+        op.invd = invd;
+        HIPCHK(nullptr, launch_diag_from_csr(op, dvec, bad, st));
+        HIPCHK(nullptr, launch_invert(dvec, invd, op.n, op.precond, st));
+    } else if (op.kind == kOpFaces) {
+        double *dvec = reinterpret_cast<double *>(base + L.dvec);
+        op.dvec = dvec;
+        HIPCHK(nullptr, launch_diag_from_faces(op, dvec, bad, st));
+    }
+    if (op.kind == kOpCsr || op.kind == kOpFaces) {
+        int hbad = 0;
+        HIPCHK(nullptr, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipStreamSynchronize(st));
+        if (hbad)
+            return fail(nullptr, SSTEP_E_ARG, "matrix has a missing, non-positive or non-finite diagonal entry");
+    }
+    HIPCHK(nullptr, launch_init_state(it.st, b, x, tol, o.max_outer, st));
+
+    // outer iterations in chunks of graph_chunk launches, then a look at the
+    // device's stop flag (every kernel returns at once after the stop)
+    const int chunk = o.graph_chunk > 0 ? o.graph_chunk : 4;
+    const int64_t max_chunks = (int64_t(o.max_outer) + 1 + chunk - 1) / chunk + 1;
+    int32_t done = 0;
+    for (int64_t c = 0; c < max_chunks && !done; ++c) {
+        for (int q = 0; q < chunk; ++q)
+            HIPCHK(nullptr, enqueue_iteration(it, st));
+        HIPCHK(nullptr, hipMemcpyAsync(&done, &it.st->done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(nullptr, hipStreamSynchronize(st));
+    }
+    DevState h;
+    HIPCHK(nullptr, hipMemcpyAsync(&h, it.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+    if (!h.done)
+        return fail(nullptr, SSTEP_E_HIP, "solve did not stop within the launch bound");
+    if (stats) {
+        stats->outer_iters = h.iter;
+        stats->status = h.status;
+        stats->rel_res = h.relres;
+        stats->res0 = h.rho0;
+    }
+    if (h.status != SSTEP_OK)
+        return fail(nullptr, static_cast<sstep_status>(h.status),
+                    std::string("solve stopped: ") + sstep_status_string(static_cast<sstep_status>(h.status)));
+    return SSTEP_OK;
+}
+
+}  // namespace
+
+extern "C" sstep_status sstep_solve_noalloc(const sstep_operator *A, int32_t s, int32_t nu, double lambda_min,
+                                            double lambda_max, const sstep_options *opt, const double *b, double *x,
+                                            double tol, sstep_stats *st)
+{
+    return noalloc_impl(A, s, nu, lambda_min, lambda_max, opt, b, x, tol, st);
+}

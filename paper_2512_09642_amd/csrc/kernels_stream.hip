@@ -631,7 +631,90 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_zero(uint64_t *__restrict__ p, int64_t words)
+{
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < words;
+         q += static_cast<int64_t>(gridDim.x) * kBlock)
+        p[q] = 0;
+}
+
+__global__ void k_init_state(DevState *__restrict__ s, const double *b, double *x, double tol, int max_outer)
+{
+    if (threadIdx.x != 0)
+        return;
+    DevState h{};
+    h.b = b;
+    h.x = x;
+    h.tol = tol;
+    h.p0scale = 1.0;
+    h.first = 1;
+    h.max_outer = max_outer;
+    *s = h;
+}
+
+// Row pointers of a CSR pattern: rp[0] = 0, rp[n] = nnz, non-decreasing.
+__global__ __launch_bounds__(kBlock) void k_check_csr_rows(const int32_t *__restrict__ rp, int64_t n, int64_t nnz,
+                                                           int *__restrict__ bad)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i > n)
+        return;
+    bool ok = true;
+    if (i == 0)
+        ok = rp[0] == 0;
+    else
+        ok = rp[i] >= rp[i - 1] && rp[i] <= nnz;
+    if (i == n)
+        ok = ok && rp[n] == nnz;
+    if (!ok)
+        atomicOr(bad, 1);
+}
+
+// Columns of a CSR pattern whose row pointers passed k_check_csr_rows: in
+// [0, n) and strictly ascending within each row.
+__global__ __launch_bounds__(kBlock) void k_check_csr_cols(const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci, int64_t n,
+                                                           int *__restrict__ bad)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] < 0 || ci[k] >= n || (k > rp[i] && ci[k] <= ci[k - 1])) {
+            atomicOr(bad, 1);
+            return;
+        }
+}
+
 }  // namespace
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st)
+{
+    const int64_t words = static_cast<int64_t>(bytes / 8);
+    if (words == 0)
+        return hipSuccess;
+    const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>((words + kBlock - 1) / kBlock, 4096));
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(kBlock), 0, st, static_cast<uint64_t *>(p), words);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(DevState *s, const double *b, double *x, double tol, int max_outer, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kWave), 0, st, s, b, x, tol, max_outer);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_csr_rows(const int32_t *rp, int64_t n, int64_t nnz, int *bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_csr_rows, dim3(blocks_for(n + 1)), dim3(kBlock), 0, st, rp, n, nnz, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_csr_cols(const int32_t *rp, const int32_t *ci, int64_t n, int *bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_csr_cols, dim3(blocks_for(n)), dim3(kBlock), 0, st, rp, ci, n, bad);
+    return hipGetLastError();
+}
 
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0)
 {

@@ -165,6 +165,14 @@ struct LzArgs {
 // results in l.ab and l.ls once the stream reaches them.
 hipError_t launch_lanczos(const LzArgs &l, const OpDev &op, const double *u, int steps, hipStream_t st);
 
+// Helpers of the allocation-free solve: zero bytes (a multiple of 8) at p;
+// the initial solve state; two-phase device checks of a CSR pattern (row
+// pointers first, then columns), setting *bad on a violation.
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_init_state(DevState *s, const double *b, double *x, double tol, int max_outer, hipStream_t st);
+hipError_t launch_check_csr_rows(const int32_t *rp, int64_t n, int64_t nnz, int *bad, hipStream_t st);
+hipError_t launch_check_csr_cols(const int32_t *rp, const int32_t *ci, int64_t n, int *bad, hipStream_t st);
+
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);
