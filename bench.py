@@ -325,6 +325,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=10, help="oracle outer iterations for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the one-time measurements after the timed steps (C3 sweep, Lanczos bounds, the "
+                         "27-point table, the coarse solve)")
+    ap.add_argument("--N27", type=int, default=230, help="grid edge of the paper's 27-point workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of n doubles (calibrates traffic counters)")
     ap.add_argument("--sweep", action="store_true",
@@ -450,6 +454,14 @@ def main():
         r = main_leg.b - main_leg.solver.apply(main_leg.x)
         results["c2_fp64"]["rel_res_true"] = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(main_leg.b))
         log(f"kernel times (ms): {kt}")
+        if not args.no_extras:
+            log("one-time measurements (not in the timed steps)")
+            out["extras"] = {
+                "c3_sweep": extra_c3(lib, torch, args.N),
+                "lanczos_bounds": extra_lanczos(lib, torch, args.c4_nsys),
+                "paper27_table": extra_paper27(lib, torch, args.N27),
+                "coarse_solve": extra_coarse(lib, torch),
+            }
         if not args.no_cpu_baseline:
             log("timing the oracle on the host (cpu_baseline)")
             out["cpu_baseline"] = cpu_baseline(args.N, args.s, args.nu, results["c2_fp64"]["outer_iters"],
@@ -457,6 +469,206 @@ def main():
     for leg in legs.values():
         leg.solver.close()
     print(json.dumps(out), flush=True)
+
+
+def _finite(v):
+    """A float for the JSON line, or None when it is not finite."""
+    v = float(v)
+    return v if np.isfinite(v) else None
+
+
+def _kappa(sv, b, x):
+    """2-norm condition number of the scaled Gram matrix of one outer
+    iteration from x = 0 (None on a breakdown or an infinite value)."""
+    x.zero_()
+    try:
+        return _finite(np.linalg.cond(sv.step(b, x)["G"]))
+    except Exception:  # a breakdown of the badly conditioned monomial basis
+        return None
+
+
+def _timed_solve(sv, b, x, tol, torch, reps=2, warm=True):
+    """Median wall time (ms) of ``reps`` solves after one warm-up, and stats."""
+    if warm:
+        x.zero_()
+        sv.solve(b, x, tol, raise_on_error=False)
+    ts, st = [], None
+    for _ in range(reps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = sv.solve(b, x, tol, raise_on_error=False)
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - t0))
+    return float(np.median(ts)), st
+
+
+def extra_c3(lib, torch, N):
+    """The mixed-precision sweep of the 224^3 problem: for every (s, nu), the
+    FP64 and FP32+IR times to 1e-8, their iteration counts, and the FP32 inner
+    error of the first outer iteration against the FP64 step from the same
+    x_0 = 0 (the FP64 step is the one the parity tests hold to the oracle)."""
+    import gen
+
+    dev = torch.device("cuda:0")
+    rows = []
+    b = None
+    for s, nu in gen.config3_sweep():
+        pr = gen.config2(0, N=N, s=s, nu=nu)
+        row = {"s": s, "nu": nu}
+        steps = {}
+        for prec in ("fp64", "fp32ir"):
+            with lib.Solver(lib.Operator.stencil(N, N, N), s, nu, pr.lmin, pr.lmax, precision=prec) as sv:
+                if b is None:
+                    b = sv.apply(torch.as_tensor(pr.xstar, device=dev))
+                x = torch.zeros_like(b)
+                t, st = _timed_solve(sv, b, x, 1e-8, torch)
+                bpo = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4, sv.gram_applies_operator)
+                row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "status": st.status,
+                             "gbps_effective": bpo * st.outer_iters / (t * 1e-3) / 1e9}
+                x.zero_()
+                steps[prec] = sv.step(b, x)
+                steps[prec]["x"] = x.clone()
+        d64 = steps["fp64"]["x"]
+        row["fp32_inner_error_dx"] = float(torch.linalg.vector_norm(steps["fp32ir"]["x"] - d64)
+                                           / torch.linalg.vector_norm(d64))
+        row["fp32_inner_error_G"] = float(np.linalg.norm(steps["fp32ir"]["G"] - steps["fp64"]["G"])
+                                          / np.linalg.norm(steps["fp64"]["G"]))
+        row["fp32ir_speedup"] = row["fp64"]["time_ms"] / row["fp32ir"]["time_ms"]
+        rows.append(row)
+        log(f"c3 s={s} nu={nu}: fp64 {row['fp64']['time_ms']:.1f} ms ({row['fp64']['outer_iters']}), fp32ir "
+            f"{row['fp32ir']['time_ms']:.1f} ms ({row['fp32ir']['outer_iters']}), inner error "
+            f"{row['fp32_inner_error_dx']:.1e}")
+    return rows
+
+
+def extra_lanczos(lib, torch, c4_nsys):
+    """Chebyshev bounds from 10 Lanczos steps with a 10% margin (Sec. 8 setup)
+    against the Gershgorin bounds [0, 2] on the face-coefficient workloads:
+    outer iterations and time to 1e-8 of the 128^3 differentiable-solve
+    problem and of the batched workload."""
+    import gen
+
+    dev = torch.device("cuda:0")
+    out = {}
+    pr = gen.config5(0)
+    b = torch.as_tensor(pr.rhs[0], device=dev)
+    u = torch.as_tensor(gen.uniform(gen.rng(101), pr.n), device=dev)
+    res = {}
+    for kind in ("gershgorin", "lanczos"):
+        with lib.Solver(lib.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz), pr.s, pr.nu, pr.lmin, pr.lmax) as sv:
+            bounds = (pr.lmin, pr.lmax)
+            if kind == "lanczos":
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                bounds = sv.lanczos_bounds(u, 10, 0.1)
+                res["lanczos_ms"] = 1e3 * (time.perf_counter() - t0)
+            x = torch.zeros_like(b)
+            t, st = _timed_solve(sv, b, x, 1e-8, torch)
+            res[kind] = {"bounds": list(bounds), "outer_iters": st.outer_iters, "time_ms": t, "status": st.status}
+    out["c5_128"] = res
+    probs = gen.config4(seed=0, nsys=c4_nsys)
+    lo, hi = [], []
+    for q, p in enumerate(probs):
+        with lib.Solver(lib.Operator.stencil(*p.dims, p.kx, p.ky, p.kz), 16, 25, p.lmin, p.lmax,
+                        autotune=False) as sv:
+            uq = torch.as_tensor(gen.uniform(gen.rng(200 + q), p.n), device=dev)
+            a, z = sv.lanczos_bounds(uq, 10, 0.1)
+            lo.append(a)
+            hi.append(z)
+    ops = [lib.Operator.stencil(*p.dims, p.kx, p.ky, p.kz) for p in probs]
+    bq = [torch.as_tensor(np.concatenate(p.rhs), device=dev) for p in probs]
+    res = {}
+    for kind, (l, h) in (("gershgorin", ([p.lmin for p in probs], [p.lmax for p in probs])), ("lanczos", (lo, hi))):
+        with lib.BatchedSolver(ops, 8, 16, 25, l, h) as bs:
+            x = [torch.zeros_like(v) for v in bq]
+            bs.solve(bq, x, 1e-8, raise_on_error=False)
+            for v in x:
+                v.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = bs.solve(bq, x, 1e-8, raise_on_error=False)
+            torch.cuda.synchronize()
+            its = [p.outer_iters for p in st]
+            res[kind] = {"time_ms": 1e3 * (time.perf_counter() - t0), "outer_iters_min": min(its),
+                         "outer_iters_max": max(its), "outer_iters_median": float(np.median(its)),
+                         "pairs_converged": sum(p.status == 0 for p in st)}
+    out["c4_batched"] = res
+    log(f"lanczos bounds: {out}")
+    return out
+
+
+def extra_paper27(lib, torch, N27):
+    """The paper's own workload (Sec. 8): 27-point Poisson on 230^3 (12.2M
+    unknowns), Chebyshev bounds from 10 Lanczos steps with a 10% margin, s in
+    {10, 20}, nu in {6, 15, 30}, Jacobi instead of the paper's AMG: outer
+    iterations to the paper's 1e-6 and to 1e-8, time, and the condition
+    number of the first scaled Gram matrix for the Chebyshev and the monomial
+    basis (Sec. 4)."""
+    import gen
+
+    dev = torch.device("cuda:0")
+    pr = gen.paper27(0, N=N27)
+    rows = []
+    b = None
+    u = torch.as_tensor(gen.uniform(gen.rng(41), pr.n), device=dev)
+    for s in (10, 20):
+        for nu in (6, 15, 30):
+            row = {"s": s, "nu": nu}
+            with lib.Solver(lib.Operator.stencil27(N27, N27, N27), s, nu, pr.lmin, pr.lmax, max_outer=1000) as sv:
+                if b is None:
+                    b = sv.apply(torch.as_tensor(pr.xstar, device=dev))
+                row["bounds"] = list(sv.lanczos_bounds(u, 10, 0.1))
+                x = torch.zeros_like(b)
+                for tol in (1e-6, 1e-8):
+                    t, st = _timed_solve(sv, b, x, tol, torch, reps=1, warm=(tol == 1e-6))
+                    row[f"tol{tol:.0e}"] = {"outer_iters": st.outer_iters, "time_ms": t, "status": st.status,
+                                            "rel_res": _finite(st.rel_res)}
+                if nu == 30:
+                    row["kappa_G_chebyshev"] = _kappa(sv, b, x)
+            if nu == 30:
+                with lib.Solver(lib.Operator.stencil27(N27, N27, N27), s, nu, *row["bounds"],
+                                basis="monomial") as sv:
+                    row["kappa_G_monomial"] = _kappa(sv, b, torch.zeros_like(b))
+            rows.append(row)
+            log(f"paper27 {row}")
+    return rows
+
+
+def extra_coarse(lib, torch):
+    """The streaming coarse solve (Sec. 8, AMG and performance): nu_coarse = 20
+    FGS sweeps on A_c = P^T A_f P of a two-level hierarchy with n_c = 17^3 =
+    4913, A_c never formed against A_c formed on the device: time per coarse
+    solve and the library workspace of each."""
+    import gen
+
+    dev = torch.device("cuda:0")
+    tl = gen.two_level(0)
+    f = torch.as_tensor(tl.f, device=dev)
+    out = {"n_coarse": tl.n_coarse, "n_fine": int(np.prod(tl.nf)), "nu": tl.nu,
+           "dense_A_c_bytes": 8 * tl.n_coarse ** 2}
+    us = {}
+    for formed in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cs = lib.CoarseSolver(lib.Operator.stencil(*tl.nf, tl.kx, tl.ky, tl.kz), formed=formed)
+        setup = 1e3 * (time.perf_counter() - t0)
+        u = cs.fgs(f, tl.nu)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cs.fgs(f, tl.nu, u)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        us[formed] = u.clone()
+        out["formed" if formed else "streamed"] = {"setup_ms": setup, "fgs_ms": float(np.median(ts)),
+                                                   "workspace_bytes": cs.workspace_bytes}
+        cs.close()
+    out["streamed_vs_formed_rel_diff"] = float(torch.linalg.vector_norm(us[False] - us[True])
+                                               / torch.linalg.vector_norm(us[True]))
+    log(f"coarse {out}")
+    return out
 
 
 def sweep(lib, torch, args):

@@ -31,7 +31,7 @@ __all__ = [
     "rng", "uniform", "poisson2d_csr", "poisson3d_csr", "faces3d_csr",
     "face_coefficients", "jacobi_poisson_bounds", "gershgorin_jacobi_bounds",
     "poisson27_csr", "jacobi_poisson27_bounds",
-    "Problem", "config1", "config2", "config3_sweep", "config4", "config5", "paper27",
+    "Problem", "config1", "config2", "config3_sweep", "config4", "config5", "paper27", "TwoLevel", "two_level",
     "small_poisson3d", "small_faces3d", "small_poisson27", "CONFIGS",
 ]
 
@@ -292,6 +292,37 @@ def small_poisson27(nx: int, ny: int, nz: int, seed: int = 0, s: int = 8, nu: in
     lmin, lmax = jacobi_poisson27_bounds(nx, ny, nz)
     return Problem(f"poisson27_{nx}x{ny}x{nz}", "stencil", (nx, ny, nz), s, nu, lmin, lmax,
                    xstar=uniform(r, nx * ny * nz), stencil=27)
+
+
+@dataclass
+class TwoLevel:
+    """A synthetic two-level hierarchy (Sec. 6; Sec. 8 streaming coarse solve):
+    coarse grid ``nc`` points per axis, fine grid ``2 nc + 1``, log-normal face
+    coefficients of the fine 7-point operator, a coarse right-hand side, nu
+    coarse FGS sweeps."""
+    nc: tuple
+    kx: np.ndarray
+    ky: np.ndarray
+    kz: np.ndarray
+    f: np.ndarray
+    nu: int = 20
+
+    @property
+    def nf(self) -> tuple:
+        return tuple(2 * c + 1 for c in self.nc)
+
+    @property
+    def n_coarse(self) -> int:
+        return int(np.prod(self.nc))
+
+
+def two_level(seed: int = 0, nc=(17, 17, 17), sigma: float = 1.0, nu: int = 20) -> TwoLevel:
+    """Coarse 17^3 = 4913 unknowns (about the paper's n_c = 5000), fine
+    35^3; faces k_f = exp(sigma Z) drawn kx, ky, kz; f ~ U[-1, 1]."""
+    r = rng(seed)
+    fx, fy, fz = (2 * c + 1 for c in nc)
+    kx, ky, kz = face_coefficients(r, fx, fy, fz, sigma)
+    return TwoLevel(tuple(nc), kx, ky, kz, uniform(r, int(np.prod(nc))), nu)
 
 
 def small_poisson3d(nx: int, ny: int, nz: int, seed: int = 0, s: int = 8, nu: int = 25) -> Problem:

@@ -270,6 +270,32 @@ sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_oper
 sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double *const *x, double tol,
                                  sstep_stats *st);
 
+/* Coarse-grid solve of a two-level hierarchy (Sec. 6, Proposition "AMG
+ * Convergence" and the streaming remark; Sec. 8, "AMG and performance"):
+ * Af is a 7-point stencil operator (constant or face coefficients) on a fine
+ * grid of (2 ncx + 1) x (2 ncy + 1) x (2 ncz + 1) points; P is the trilinear
+ * prolongation from the ncx x ncy x ncz coarse grid (coarse point (I, J, K) on
+ * fine point (2I+1, 2J+1, 2K+1), hat weights 1, 1/2 per axis); the coarse
+ * operator is A_c = P^T Af P.  formed = 0: A_c is never formed (streamed:
+ * each Gauss-Seidel update forms p_j^T Af (P u) on the fly from the fine
+ * coefficients; the library keeps a_jj, a wavefront table and the fine
+ * vector P u); formed = 1: the 27 entries of each row of A_c are formed on
+ * the device at setup.  SSTEP_E_ARG for even fine sides. */
+sstep_status sstep_coarse_setup(sstep_ctx **out, const sstep_operator *Af, int32_t formed, const sstep_options *opt);
+
+/* u = nu forward Gauss-Seidel sweeps on A_c u = f from u = 0, unknowns in
+ * natural order (x fastest), each update u_j = (f_j - sum_{i != j} a_ji u_i)
+ * / a_jj with the updated values of the lower-numbered unknowns (Sec. 6: nu =
+ * 10-30 sweeps; Sec. 8: nu_coarse = 20).  f, u: device, n_c doubles each.
+ * The sweep runs in wavefronts I + 2J + 4K, which gives exactly the
+ * sequential order's values. */
+sstep_status sstep_coarse_fgs(sstep_ctx *ctx, const double *f, double *u, int32_t nu);
+
+/* Number of coarse unknowns and the library's device workspace in bytes for
+ * the context's variant (streamed or formed; the fine coefficients
+ * excluded). */
+sstep_status sstep_coarse_info(const sstep_ctx *ctx, int64_t *n_coarse, int64_t *workspace_bytes);
+
 /* For callers that cannot allocate device memory (serving loops and
  * harnesses that forbid hipMalloc/hipFree): sstep_setup + sstep_solve +
  * sstep_destroy in one call that allocates nothing.  The whole workspace

@@ -84,6 +84,10 @@ def _load(path=None):
                                         C.c_int, C.c_int, C.POINTER(C.c_int), pd, pd, pd, pd, pd, C.c_int]
     _lib.oracle_lanczos.restype = C.c_int
     _lib.oracle_lanczos.argtypes = [i64, pi, pi, pd, C.c_int, pd, C.c_int, pd, pd]
+    _lib.oracle_prolongation_trilinear.restype = i64
+    _lib.oracle_prolongation_trilinear.argtypes = [i32, i32, i32, pi, pi, pd]
+    _lib.oracle_gs.restype = C.c_int
+    _lib.oracle_gs.argtypes = [i64, pi, pi, pd, pd, C.c_int, pd]
     _lib.oracle_grad_csr.restype = None
     _lib.oracle_grad_csr.argtypes = [i64, pi, pi, pd, pd, pd]
     _lib.oracle_grad_faces.restype = None
@@ -285,6 +289,53 @@ def lanczos_bounds(ritz, margin=0.1):
     """Chebyshev bounds from the extreme Ritz values with a relative safety
     margin (Sec. 8: 10%): [(1 - margin) theta_min, (1 + margin) theta_max]."""
     return (1.0 - margin) * float(ritz[0]), (1.0 + margin) * float(ritz[-1])
+
+
+def prolongation(ncx, ncy, ncz):
+    """CSR (n_f x n_c) of the trilinear prolongation from the coarse grid to
+    the (2 nc + 1)-point fine grid per axis (Sec. 6 two-level hierarchy)."""
+    nf = (2 * ncx + 1) * (2 * ncy + 1) * (2 * ncz + 1)
+    nc = ncx * ncy * ncz
+    rp = np.empty(nf + 1, np.int32)
+    ci = np.empty(27 * nc, np.int32)
+    v = np.empty(27 * nc)
+    nnz = _load().oracle_prolongation_trilinear(ncx, ncy, ncz, _pi(rp), _pi(ci), _pd(v))
+    return rp, ci[:nnz].copy(), v[:nnz].copy()
+
+
+def galerkin(Af, P, nc):
+    """A_c = P^T A_f P formed explicitly (SciPy's sparse products as the
+    step), returned as CSR with sorted columns."""
+    import scipy.sparse as sp
+    rp, ci, v = _csr(Af)
+    nf = rp.size - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(nf, nf))
+    Pm = sp.csr_matrix((P[2], P[1], P[0]), shape=(nf, nc))
+    Ac = (Pm.T @ (A @ Pm)).tocsr()
+    Ac.sort_indices()
+    return Ac.indptr.astype(np.int32), Ac.indices.astype(np.int32), Ac.data.astype(np.float64)
+
+
+def gs(A, f, nu):
+    """nu forward Gauss-Seidel sweeps on A u = f from u = 0 (natural order)."""
+    rp, ci, v = _csr(A)
+    n = rp.size - 1
+    u = np.empty(n)
+    st = _load().oracle_gs(n, _pi(rp), _pi(ci), _pd(v), _pd(_f64(f)), nu, _pd(u))
+    if st:
+        raise ValueError("non-positive or missing diagonal")
+    return u
+
+
+def coarse_fgs(nc_dims, kx, ky, kz, f, nu):
+    """The coarse-grid solve of the two-level hierarchy: A_f the 7-point
+    face-coefficient operator on the fine grid (2 nc + 1 per axis), A_c =
+    P^T A_f P formed, then nu FGS sweeps on A_c u = f from zero.  Returns
+    (u, A_c)."""
+    ncx, ncy, ncz = nc_dims
+    Af = assemble_stencil7(2 * ncx + 1, 2 * ncy + 1, 2 * ncz + 1, kx, ky, kz)
+    Ac = galerkin(Af, prolongation(ncx, ncy, ncz), ncx * ncy * ncz)
+    return gs(Ac, f, nu), Ac
 
 
 def gram_condition(G) -> float:

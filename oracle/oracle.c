@@ -746,3 +746,86 @@ out:
     free(y);
     return m;
 }
+
+/* ---------------------------------------------------------------------------
+ * Coarse-grid solve of a two-level hierarchy (Sec. 6; Sec. 8, "AMG and
+ * performance"): A_c = P^T A_f P with a geometric prolongation P, solved by
+ * nu forward Gauss-Seidel sweeps from zero.
+ * ------------------------------------------------------------------------- */
+
+/* Trilinear prolongation from an ncx x ncy x ncz coarse grid to the fine grid
+ * of (2 ncx + 1) x (2 ncy + 1) x (2 ncz + 1) points (both x fastest, zero
+ * Dirichlet boundary): coarse point (I, J, K) sits on fine point
+ * (2I+1, 2J+1, 2K+1), and its basis function is the product over the axes of
+ * the 1D hat 1, 1/2, 0 at fine distance 0, 1, >= 2.  Writes P as CSR
+ * (n_f rows, up to 8 entries per row, columns ascending); sizes: row_ptr
+ * n_f + 1, col_idx and val 27 n_c.  Returns nnz. */
+int64_t oracle_prolongation_trilinear(int32_t ncx, int32_t ncy, int32_t ncz, int32_t *row_ptr, int32_t *col_idx,
+                                      double *val)
+{
+    const int32_t nx = 2 * ncx + 1, ny = 2 * ncy + 1, nz = 2 * ncz + 1;
+    int64_t nnz = 0;
+    row_ptr[0] = 0;
+    for (int32_t z = 0; z < nz; ++z)
+        for (int32_t y = 0; y < ny; ++y)
+            for (int32_t x = 0; x < nx; ++x) {
+                const int64_t row = x + (int64_t)nx * (y + (int64_t)ny * z);
+                /* coarse parents per axis: odd fine index 2I+1 -> I (weight 1);
+                   even fine index 2I -> I-1 and I (weight 1/2 each, when inside) */
+                int32_t pk[2], pj[2], pi[2];
+                double wk[2], wj[2], wi[2];
+                int nk = 0, nj = 0, ni = 0;
+                if (z % 2) { pk[nk] = (z - 1) / 2; wk[nk++] = 1.0; }
+                else {
+                    if (z / 2 - 1 >= 0) { pk[nk] = z / 2 - 1; wk[nk++] = 0.5; }
+                    if (z / 2 < ncz) { pk[nk] = z / 2; wk[nk++] = 0.5; }
+                }
+                if (y % 2) { pj[nj] = (y - 1) / 2; wj[nj++] = 1.0; }
+                else {
+                    if (y / 2 - 1 >= 0) { pj[nj] = y / 2 - 1; wj[nj++] = 0.5; }
+                    if (y / 2 < ncy) { pj[nj] = y / 2; wj[nj++] = 0.5; }
+                }
+                if (x % 2) { pi[ni] = (x - 1) / 2; wi[ni++] = 1.0; }
+                else {
+                    if (x / 2 - 1 >= 0) { pi[ni] = x / 2 - 1; wi[ni++] = 0.5; }
+                    if (x / 2 < ncx) { pi[ni] = x / 2; wi[ni++] = 0.5; }
+                }
+                for (int a = 0; a < nk; ++a)
+                    for (int b = 0; b < nj; ++b)
+                        for (int c = 0; c < ni; ++c) {
+                            col_idx[nnz] = (int32_t)(pi[c] + (int64_t)ncx * (pj[b] + (int64_t)ncy * pk[a]));
+                            val[nnz++] = (wk[a] * wj[b]) * wi[c];
+                        }
+                row_ptr[row + 1] = (int32_t)nnz;
+            }
+    return nnz;
+}
+
+/* nu forward Gauss-Seidel sweeps on A u = f from u = 0, unknowns in ascending
+ * order, each update
+ *     u_j = (f_j - sum_{i != j} A_ji u_i) / A_jj
+ * with the already-updated u_i for i < j (Sec. 6: FGS as the coarse-grid
+ * solver, nu = 10-30).  Returns ORACLE_E_ARG if a diagonal entry is missing
+ * or not positive. */
+int oracle_gs(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val, const double *f, int nu,
+              double *u)
+{
+    if (n < 1 || nu < 0 || !row_ptr || !col_idx || !val || !f || !u)
+        return ORACLE_E_ARG;
+    for (int64_t j = 0; j < n; ++j)
+        u[j] = 0.0;
+    for (int sweep = 0; sweep < nu; ++sweep)
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = f[j], diag = 0.0;
+            for (int32_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+                if (col_idx[k] == j)
+                    diag = val[k];
+                else
+                    acc -= val[k] * u[col_idx[k]];
+            }
+            if (!(diag > 0.0))
+                return ORACLE_E_ARG;
+            u[j] = acc / diag;
+        }
+    return ORACLE_OK;
+}

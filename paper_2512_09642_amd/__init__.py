@@ -9,7 +9,7 @@ argument-marshalling layer over that ABI; torch provides device memory and
 streams.
 """
 from ._native import SStepError, STATUS_NAMES, KT_NAMES, LIB_PATH, load  # noqa: F401
-from .solver import BatchedSolver, Operator, Solver, SolveStats, require_gpu  # noqa: F401
+from .solver import BatchedSolver, CoarseSolver, Operator, Solver, SolveStats, require_gpu  # noqa: F401
 from .autograd import SStepSolve, sstep_solve  # noqa: F401
 
-__all__ = ["Operator", "Solver", "BatchedSolver", "SolveStats", "SStepSolve", "sstep_solve", "SStepError", "require_gpu", "load"]
+__all__ = ["Operator", "Solver", "BatchedSolver", "CoarseSolver", "SolveStats", "SStepSolve", "sstep_solve", "SStepError", "require_gpu", "load"]

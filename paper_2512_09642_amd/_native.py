@@ -21,7 +21,8 @@ EXPORTS = (
     "sstep_default_options", "sstep_setup", "sstep_update_coefficients", "sstep_apply", "sstep_solve",
     "sstep_solve_adjoint", "sstep_grad_operator", "sstep_grad_size", "sstep_n", "sstep_step",
     "sstep_lanczos", "sstep_set_bounds", "sstep_lanczos_bounds", "sstep_last_iteration", "sstep_kernel_times", "sstep_gram_mode", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
-    "sstep_status_string", "sstep_destroy", "sstep_solve_noalloc",
+    "sstep_status_string", "sstep_destroy", "sstep_solve_noalloc", "sstep_coarse_setup", "sstep_coarse_fgs",
+    "sstep_coarse_info",
 )
 
 
@@ -109,6 +110,12 @@ def load():
     lib.sstep_solve_noalloc.argtypes = [C.POINTER(Operator), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                         C.POINTER(Options), P, P, C.c_double, C.POINTER(Stats)]
     lib.sstep_solve_noalloc.restype = st
+    lib.sstep_coarse_setup.argtypes = [C.POINTER(P), C.POINTER(Operator), C.c_int32, C.POINTER(Options)]
+    lib.sstep_coarse_setup.restype = st
+    lib.sstep_coarse_fgs.argtypes = [P, P, P, C.c_int32]
+    lib.sstep_coarse_fgs.restype = st
+    lib.sstep_coarse_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.sstep_coarse_info.restype = st
     lib.sstep_last_error.argtypes = [P]
     lib.sstep_last_error.restype = C.c_char_p
     lib.sstep_status_string.argtypes = [C.c_int]

@@ -51,6 +51,8 @@ struct sstep_ctx {
     LzArgs lz;                     // Lanczos workspace (vectors: P's storage, or allocated on first use)
     double *lz_vecs = nullptr;
     struct Batched *batch = nullptr;  // set for contexts made by sstep_setup_batched
+    CoarseArgs *coarse = nullptr;     // set for contexts made by sstep_coarse_setup
+    int64_t coarse_bytes = 0;
     std::string err;
 };
 
@@ -676,6 +678,7 @@ void sstep_destroy(sstep_ctx *ctx)
             (void)hipEventDestroy(e);
     if (ctx->stream)
         (void)hipStreamDestroy(ctx->stream);
+    delete ctx->coarse;
     if (ctx->batch) {
         if (ctx->batch->pairs_host)
             (void)hipHostFree(ctx->batch->pairs_host);
@@ -1511,6 +1514,128 @@ sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double 
     }
     if (first_bad != SSTEP_OK)
         return fail(ctx, first_bad, std::string("a batched pair stopped with ") + sstep_status_string(first_bad));
+    return SSTEP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Two-level coarse solve (Sec. 6; Sec. 8).
+// ---------------------------------------------------------------------------
+static sstep_status coarse_setup_impl(sstep_ctx *ctx, const sstep_operator *Af, int32_t formed,
+                                      const sstep_options *opt)
+{
+    if (opt)
+        ctx->opt = *opt;
+    else
+        sstep_default_options(&ctx->opt);
+    OKCHK(check_operator(ctx, Af));
+    if (Af->kind != SSTEP_OP_STENCIL7)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "the coarse solve takes a 7-point fine-grid operator");
+    if (Af->nx % 2 == 0 || Af->ny % 2 == 0 || Af->nz % 2 == 0 || Af->nx < 3 || Af->ny < 3 || Af->nz < 3)
+        return fail(ctx, SSTEP_E_ARG, "fine grid sides must be odd, 2 nc + 1 with nc >= 1");
+    if (formed != 0 && formed != 1)
+        return fail(ctx, SSTEP_E_ARG, "formed must be 0 (streamed) or 1 (A_c formed)");
+    HIPCHK(ctx, hipGetDevice(&ctx->device));
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    ctx->user = static_cast<hipStream_t>(ctx->opt.stream);
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+    ctx->coarse = new (std::nothrow) CoarseArgs();
+    if (!ctx->coarse)
+        return fail(ctx, SSTEP_E_NOMEM, "out of host memory");
+    CoarseArgs &c = *ctx->coarse;
+    c.nfx = Af->nx, c.nfy = Af->ny, c.nfz = Af->nz;
+    c.ncx = (Af->nx - 1) / 2, c.ncy = (Af->ny - 1) / 2, c.ncz = (Af->nz - 1) / 2;
+    const int64_t nc = int64_t(c.ncx) * c.ncy * c.ncz;
+    const int64_t nf = int64_t(c.nfx) * c.nfy * c.nfz;
+    int64_t bytes = 0;
+    if (Af->kx) {
+        const int64_t nfx = faces_x(Af), nfy = faces_y(Af), nfz = faces_z(Af);
+        double *k = nullptr;
+        OKCHK(dalloc(ctx, &k, size_t(nfx + nfy + nfz)));
+        OKCHK(overwrite_device(ctx, k, Af->kx, size_t(nfx), Af->ptr_space));
+        OKCHK(overwrite_device(ctx, k + nfx, Af->ky, size_t(nfy), Af->ptr_space));
+        OKCHK(overwrite_device(ctx, k + nfx + nfy, Af->kz, size_t(nfz), Af->ptr_space));
+        c.kx = k, c.ky = k + nfx, c.kz = k + nfx + nfy;
+    }
+    // wavefronts t = I + 2J + 4K, unknowns ascending within each
+    c.nwf = c.ncx + 2 * c.ncy + 4 * c.ncz - 6;
+    std::vector<int32_t> count(static_cast<size_t>(c.nwf) + 1, 0), order(static_cast<size_t>(nc), 0),
+        wf(static_cast<size_t>(c.nwf) + 1, 0);
+    for (int64_t j = 0; j < nc; ++j) {
+        const int I = int(j % c.ncx), J = int((j / c.ncx) % c.ncy), K = int(j / (int64_t(c.ncx) * c.ncy));
+        ++count[size_t(I + 2 * J + 4 * K) + 1];
+    }
+    for (int t = 0; t < c.nwf; ++t)
+        wf[size_t(t) + 1] = wf[size_t(t)] + count[size_t(t) + 1];
+    std::vector<int32_t> fill(wf.begin(), wf.end() - 1);
+    for (int64_t j = 0; j < nc; ++j) {
+        const int I = int(j % c.ncx), J = int((j / c.ncx) % c.ncy), K = int(j / (int64_t(c.ncx) * c.ncy));
+        order[size_t(fill[size_t(I + 2 * J + 4 * K)]++)] = int32_t(j);
+    }
+    int32_t *dorder = nullptr, *dwf = nullptr;
+    OKCHK(to_device(ctx, &dorder, order.data(), order.size(), 0));
+    OKCHK(to_device(ctx, &dwf, wf.data(), wf.size(), 0));
+    c.order = dorder, c.wf = dwf;
+    bytes += int64_t(order.size() + wf.size()) * int64_t(sizeof(int32_t));
+    OKCHK(dalloc(ctx, &c.diag, size_t(nc)));
+    bytes += nc * int64_t(sizeof(double));
+    if (formed) {
+        OKCHK(dalloc(ctx, &c.rows, size_t(27 * nc)));
+        bytes += 27 * nc * int64_t(sizeof(double));
+    } else {
+        OKCHK(dalloc(ctx, &c.v, size_t(nf)));
+        bytes += nf * int64_t(sizeof(double));
+    }
+    ctx->coarse_bytes = bytes;
+    HIPCHK(ctx, launch_coarse_prepare(c, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_coarse_setup(sstep_ctx **out, const sstep_operator *Af, int32_t formed, const sstep_options *opt)
+{
+    if (!out)
+        return fail(nullptr, SSTEP_E_ARG, "out is NULL");
+    *out = nullptr;
+    sstep_ctx *ctx = new (std::nothrow) sstep_ctx();
+    if (!ctx)
+        return fail(nullptr, SSTEP_E_NOMEM, "out of host memory");
+    const sstep_status st = coarse_setup_impl(ctx, Af, formed, opt);
+    if (st != SSTEP_OK) {
+        g_setup_error = ctx->err;
+        sstep_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return SSTEP_OK;
+}
+
+sstep_status sstep_coarse_fgs(sstep_ctx *ctx, const double *f, double *u, int32_t nu)
+{
+    if (!ctx)
+        return SSTEP_E_ARG;
+    if (!ctx->coarse)
+        return fail(ctx, SSTEP_E_ARG, "this context was not made by sstep_coarse_setup");
+    if (!f || !u || f == u)
+        return fail(ctx, SSTEP_E_ARG, "f and u must be distinct non-NULL device pointers");
+    if (nu < 0)
+        return fail(ctx, SSTEP_E_ARG, "nu must be >= 0");
+    HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
+    HIPCHK(ctx, launch_coarse_fgs(*ctx->coarse, f, u, nu, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SSTEP_OK;
+}
+
+sstep_status sstep_coarse_info(const sstep_ctx *ctx, int64_t *n_coarse, int64_t *workspace_bytes)
+{
+    if (!ctx || !ctx->coarse)
+        return SSTEP_E_ARG;
+    const CoarseArgs &c = *ctx->coarse;
+    if (n_coarse)
+        *n_coarse = int64_t(c.ncx) * c.ncy * c.ncz;
+    if (workspace_bytes)
+        *workspace_bytes = ctx->coarse_bytes;
     return SSTEP_OK;
 }
 

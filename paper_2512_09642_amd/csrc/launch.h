@@ -173,6 +173,23 @@ hipError_t launch_init_state(DevState *s, const double *b, double *x, double tol
 hipError_t launch_check_csr_rows(const int32_t *rp, int64_t n, int64_t nnz, int *bad, hipStream_t st);
 hipError_t launch_check_csr_cols(const int32_t *rp, const int32_t *ci, int64_t n, int *bad, hipStream_t st);
 
+// Two-level coarse solve (kernels_coarse.hip).
+struct CoarseArgs {
+    int ncx = 0, ncy = 0, ncz = 0;       // coarse grid
+    int nfx = 0, nfy = 0, nfz = 0;       // fine grid, 2 nc + 1 per axis
+    const double *kx = nullptr, *ky = nullptr, *kz = nullptr;  // fine face coefficients (null: all 1)
+    double *diag = nullptr;               // a_jj [n_c]
+    double *rows = nullptr;               // formed A_c rows [27 n_c], or null (streamed)
+    double *v = nullptr;                  // streamed: the fine vector P u [n_f]
+    const int32_t *order = nullptr;       // coarse unknowns by wavefront [n_c]
+    const int32_t *wf = nullptr;          // wavefront starts [nwf + 1]
+    int nwf = 0;
+};
+// a_jj and, when formed, the rows of A_c.
+hipError_t launch_coarse_prepare(const CoarseArgs &c, hipStream_t st);
+// u = nu forward Gauss-Seidel sweeps on A_c u = f from u = 0.
+hipError_t launch_coarse_fgs(const CoarseArgs &c, const double *f, double *u, int nu, hipStream_t st);
+
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);

@@ -373,3 +373,51 @@ class BatchedSolver:
         if raise_on_error:
             _check(st, self._ctx)
         return x, out
+
+
+class CoarseSolver:
+    """Coarse-grid solve of a two-level hierarchy: ``nu`` forward Gauss-Seidel
+    sweeps on A_c = P^T A_f P (trilinear P) from zero, with A_c never formed
+    (``formed=False``) or formed on the device at setup (``formed=True``).
+    ``fine_op`` is a 7-point stencil Operator on the (2 nc + 1)-point grid."""
+
+    def __init__(self, fine_op: Operator, formed: bool = False, stream=None):
+        self._lib = N.load()
+        opt = N.Options()
+        self._lib.sstep_default_options(C.byref(opt))
+        opt.stream = stream.cuda_stream if stream is not None else (
+            torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None)
+        cop = fine_op.to_c()
+        ctx = C.c_void_p()
+        st = self._lib.sstep_coarse_setup(C.byref(ctx), C.byref(cop), 1 if formed else 0, C.byref(opt))
+        fine_op._keep = []
+        _check(st, None)
+        self._ctx = ctx
+        nc, nb = C.c_int64(0), C.c_int64(0)
+        _check(self._lib.sstep_coarse_info(ctx, C.byref(nc), C.byref(nb)), ctx)
+        self.n = nc.value
+        self.workspace_bytes = nb.value
+        self.formed = formed
+
+    def fgs(self, f: torch.Tensor, nu: int, u: torch.Tensor | None = None) -> torch.Tensor:
+        u = torch.empty_like(f) if u is None else u
+        _check(self._lib.sstep_coarse_fgs(self._ctx, _dev_ptr(f, self.n, "f"), _dev_ptr(u, self.n, "u"), nu),
+               self._ctx)
+        return u
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.sstep_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

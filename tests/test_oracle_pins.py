@@ -812,3 +812,88 @@ def test_monomial_gram_condition_grows_exponentially():
     for s0 in (4, 6):
         gm, gc = km[s0 + 2] / km[s0], kc[s0 + 2] / kc[s0]
         assert gm >= 100 and gm >= 10 * gc, (s0, gm, gc)
+
+
+# ---------------------------------------------------------------------------
+# Two-level hierarchy and the coarse FGS solve (Sec. 6; Sec. 8)
+# ---------------------------------------------------------------------------
+
+def _face_energy(nx, ny, nz, kx, ky, kz, v):
+    """sum over faces of k_f (v_p - v_q)^2, v = 0 outside (Dirichlet)."""
+    V = np.zeros((nz + 2, ny + 2, nx + 2))
+    V[1:-1, 1:-1, 1:-1] = v.reshape(nz, ny, nx)
+    kx = kx.reshape(nz, ny, nx + 1)
+    ky = ky.reshape(nz, ny + 1, nx)
+    kz = kz.reshape(nz + 1, ny, nx)
+    ex = np.sum(kx * (V[1:-1, 1:-1, 1:] - V[1:-1, 1:-1, :-1]) ** 2)
+    ey = np.sum(ky * (V[1:-1, 1:, 1:-1] - V[1:-1, :-1, 1:-1]) ** 2)
+    ez = np.sum(kz * (V[1:, 1:-1, 1:-1] - V[:-1, 1:-1, 1:-1]) ** 2)
+    return ex + ey + ez
+
+
+@pytest.mark.parametrize("nc", [(3, 2, 4), (5, 5, 5)])
+def test_prolongation_row_and_column_sums(nc):
+    """Trilinear hats: every coarse column sums to (1/2 + 1 + 1/2)^3 = 8 and
+    carries 27 entries; P 1 = 1 at fine points off the boundary layer, and
+    1/2 per axis on which the point lies next to the boundary."""
+    rp, ci, v = oracle.prolongation(*nc)
+    nf = [2 * c + 1 for c in nc]
+    n_f, n_c = int(np.prod(nf)), int(np.prod(nc))
+    assert rp.size == n_f + 1
+    colsum = np.bincount(ci, weights=v, minlength=n_c)
+    assert np.all(colsum == 8.0) and np.all(np.bincount(ci, minlength=n_c) == 27)
+    ones = np.add.reduceat(v, rp[:-1]) * (np.diff(rp) > 0)
+    want = np.ones(nf[::-1])
+    for axis, n in zip((2, 1, 0), nf):
+        sl = [slice(None)] * 3
+        for edge in (0, n - 1):
+            sl[axis] = edge
+            want[tuple(sl)] *= 0.5
+    assert np.array_equal(ones, want.ravel())
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_galerkin_energy_identity(seed):
+    """u^T A_c u = (P u)^T A_f (P u) = sum_f k_f ((Pu)_p - (Pu)_q)^2 (the face
+    energy, computed from P u alone); A_c is symmetric positive definite with
+    the 27-point coarse pattern."""
+    tl = gen.two_level(seed, nc=(4, 3, 5), sigma=1.0)
+    nx, ny, nz = tl.nf
+    P = oracle.prolongation(*tl.nc)
+    Af = oracle.assemble_stencil7(nx, ny, nz, tl.kx, tl.ky, tl.kz)
+    Ac = oracle.galerkin(Af, P, tl.n_coarse)
+    D = dense(Ac)
+    assert np.array_equal(D, D.T) or np.max(np.abs(D - D.T)) <= 1e-14 * np.abs(D).max()
+    np.linalg.cholesky(D)
+    assert Ac[0][-1] == (3 * 4 - 2) * (3 * 3 - 2) * (3 * 5 - 2)
+    Pd = np.zeros((nx * ny * nz, tl.n_coarse))
+    for r in range(nx * ny * nz):
+        Pd[r, P[1][P[0][r]:P[0][r + 1]]] = P[2][P[0][r]:P[0][r + 1]]
+    for k in range(3):
+        u = gen.uniform(gen.rng(10 + k), tl.n_coarse)
+        e = _face_energy(nx, ny, nz, tl.kx, tl.ky, tl.kz, Pd @ u)
+        assert abs(u @ D @ u - e) <= 1e-12 * e
+
+
+def test_gs_converges_and_descends():
+    """Forward GS is coordinate descent on E(u) = u^T A u / 2 - f^T u: E never
+    grows from one sweep to the next, and many sweeps reach the dense direct
+    solution of the coarse system."""
+    tl = gen.two_level(2, nc=(5, 4, 3), sigma=0.5)
+    u, Ac = oracle.coarse_fgs(tl.nc, tl.kx, tl.ky, tl.kz, tl.f, 1)
+    D = dense(Ac)
+    energy = [0.0]
+    for nu in range(1, 8):
+        u = oracle.gs(Ac, tl.f, nu)
+        energy.append(0.5 * u @ D @ u - tl.f @ u)
+    assert all(b <= a + 1e-14 for a, b in zip(energy, energy[1:])), energy
+    u = oracle.gs(Ac, tl.f, 3000)
+    assert rel(u, np.linalg.solve(D, tl.f)) <= 1e-10
+
+
+def test_gs_two_by_two_closed_form():
+    """One sweep on [[a, b], [b, c]]: u0 = f0 / a, u1 = (f1 - b u0) / c."""
+    A = (np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([4.0, -1.5, -1.5, 3.0]))
+    f = np.array([2.0, 1.0])
+    u = oracle.gs(A, f, 1)
+    assert u[0] == 0.5 and u[1] == (1.0 + 1.5 * 0.5) / 3.0
