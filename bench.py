@@ -42,39 +42,46 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stencil_bytes_per_outer(n: int, s: int, w: int, fused: bool = False) -> float:
-    """Bytes an outer iteration must move, constant-coefficient stencil.
-    Stored AP: residual 16 + w, basis w(4s - 3), Gram 2sw, update sw + 16.
-    Gram forming A p_j itself (fused): the s - 1 basis launches move
-    w(3s - 4) (no AP), the Gram reads P only (sw)."""
-    if fused:
+def stencil_bytes_per_outer(n: int, s: int, w: int, kind: str = "stored") -> float:
+    """Bytes an outer iteration must move, constant-coefficient stencil, by
+    Gram kind.  stored: residual 16 + w, basis w(4s - 3) (AP written), Gram
+    2sw (P and AP), update sw + 16.  apply (the Gram kernel forms A p_j
+    itself): the s - 1 basis launches move w(3s - 4), the Gram reads P (sw).
+    recurrence: the s basis launches move w(3s - 1) (the last one writes
+    p_s), the Gram reads the s + 1 columns."""
+    if kind == "apply":
         return float(n) * (32 + w * (1 + max(0, 3 * s - 4) + 2 * s))
+    if kind == "recurrence":
+        return float(n) * (32 + w * (5 * s + 1))
     return float(n) * (32 + w * (7 * s - 2))
 
 
-def csr_bytes_per_outer(n: int, nnz: int, s: int, w: int) -> float:
+def csr_bytes_per_outer(n: int, nnz: int, s: int, w: int, kind: str = "stored") -> float:
     """The stencil figure plus the matrix (values and column indices, row
     pointers) read by s basis SpMVs in precision w and one FP64 residual SpMV,
     and the M-diagonal read by the Gram right-hand side."""
-    mat_w = float(nnz) * (w + 4) + 4.0 * (n + 1)
+    mat_w = float(nnz) * (4 + w) + 4.0 * (n + 1)
     mat_64 = float(nnz) * 12 + 4.0 * (n + 1)
-    return stencil_bytes_per_outer(n, s, w) + s * mat_w + mat_64 + float(n) * w
+    return stencil_bytes_per_outer(n, s, w, kind) + s * mat_w + mat_64 + float(n) * w
 
 
-def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, fused: bool = False) -> float:
+def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, kind: str = "stored") -> float:
     """Stencil figure per right-hand side plus the three face arrays read by the
     FP64 residual and s more times (the s basis steps, or the s - 1 basis
     steps and the Gram when it forms A p_j itself), shared by nrhs right-hand
     sides, and the M-diagonal read by the Gram right-hand side."""
-    return nrhs * (stencil_bytes_per_outer(n, s, w, fused) + float(n) * w) + float(n) * 3 * (8 + s * w)
+    return nrhs * (stencil_bytes_per_outer(n, s, w, kind) + float(n) * w) + float(n) * 3 * (8 + s * w)
 
 
-def basis_bytes_per_launch(n: int, s: int, w: int, fused: bool = False) -> float:
+def basis_bytes_per_launch(n: int, s: int, w: int, kind: str = "stored") -> float:
     """Average algorithmic bytes of one basis launch: the s launches of an
-    outer iteration move w(4s - 3) bytes per unknown in total; without AP
-    (fused Gram) the s - 1 launches move w(3s - 4)."""
-    if fused:
+    outer iteration move w(4s - 3) bytes per unknown in total with AP stored;
+    the s - 1 launches of the apply kind move w(3s - 4); the s launches of the
+    recurrence kind w(3s - 1)."""
+    if kind == "apply":
         return float(n) * w * (3 * s - 4) / (s - 1)
+    if kind == "recurrence":
+        return float(n) * w * (3 * s - 1) / s
     return float(n) * w * (4 * s - 3) / s
 
 
@@ -184,7 +191,7 @@ class Leg:
         self.iters = it
 
 
-def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
+def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
     import gen
 
     dev = torch.device("cuda:0")
@@ -194,7 +201,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
         pr = gen.config2(0, N=N, s=s, nu=nu)
         op = lib.Operator.stencil(N, N, N)
         xstar = torch.as_tensor(pr.xstar, device=dev)
-        base = lib.Solver(op, s, nu, pr.lmin, pr.lmax)
+        base = lib.Solver(op, s, nu, pr.lmin, pr.lmax, gram=gram)
         b = base.apply(xstar)
         for name, prec in (("c2_fp64", "fp64"), ("c2_fp32ir", "fp32ir")):
             if name not in legs:
@@ -210,13 +217,14 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
 
             leg.run = run
             leg.bytes_per_outer = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4,
-                                                          leg.solver.gram_applies_operator)
+                                                          leg.solver.gram_kind)
             leg.n = pr.n
             out[name] = leg
         if "c2_csr_fp64" in legs:
             rp, ci, v = gen.poisson3d_csr(N, N, N)
             leg = Leg("c2_csr_fp64")
-            leg.solver = lib.Solver(lib.Operator.csr(rp, ci, v), s, nu, pr.lmin, pr.lmax)
+            leg.solver = lib.Solver(lib.Operator.csr(rp, ci, v), s, nu, pr.lmin, pr.lmax,
+                                    gram="stored" if gram == "apply" else gram)
             leg.b, leg.x = b, torch.zeros_like(b)
 
             def run(leg=leg):
@@ -225,7 +233,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
                 return st.outer_iters
 
             leg.run = run
-            leg.bytes_per_outer = csr_bytes_per_outer(pr.n, ci.size, s, 8)
+            leg.bytes_per_outer = csr_bytes_per_outer(pr.n, ci.size, s, 8, leg.solver.gram_kind)
             leg.n = pr.n
             out["c2_csr_fp64"] = leg
         log("c2 legs ready")
@@ -274,7 +282,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys):
             return leg.solver.last_forward_stats.outer_iters
 
         leg.run = run
-        leg.bytes_per_outer = faces_bytes_per_outer(pr.n, pr.s, 8, fused=leg.solver.gram_applies_operator)
+        leg.bytes_per_outer = faces_bytes_per_outer(pr.n, pr.s, 8, kind=leg.solver.gram_kind)
         leg.n = pr.n
         out["c5_adjoint"] = leg
 
@@ -329,6 +337,8 @@ def main():
                     help="skip the one-time measurements after the timed steps (C3 sweep, Lanczos bounds, the "
                          "27-point table, the coarse solve)")
     ap.add_argument("--N27", type=int, default=230, help="grid edge of the paper's 27-point workload")
+    ap.add_argument("--gram", default="auto", choices=["auto", "stored", "apply", "recurrence"],
+                    help="Gram kind of the FP64 legs of the 224^3 problem (default: the library's choice)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of n doubles (calibrates traffic counters)")
     ap.add_argument("--sweep", action="store_true",
@@ -355,7 +365,7 @@ def main():
         log(f"calibration copy: {args.N ** 3} doubles ({16 * args.N ** 3} bytes read + written)")
         del src, dst
     legs_wanted = [x for x in args.legs.split(",") if x]
-    legs = build_legs(lib, torch, legs_wanted, args.N, args.s, args.nu, args.c4_nsys)
+    legs = build_legs(lib, torch, legs_wanted, args.N, args.s, args.nu, args.c4_nsys, args.gram)
     torch.cuda.synchronize()
     sync = torch.cuda.synchronize
     order = [name for name in ALL_LEGS if name in legs]
@@ -435,13 +445,14 @@ def main():
         if "c2_fp32ir" in legs:
             results["c2_fp32ir"]["kernel_ms"] = legs["c2_fp32ir"].solver.kernel_times(
                 main_leg.b, torch.zeros_like(main_leg.b), reps=args.kernel_reps)
-        fused = main_leg.solver.gram_applies_operator
-        per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8, fused)
+        kind = main_leg.solver.gram_kind
+        per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8, kind)
         achieved = per_launch / (kt["basis"] * 1e-3) / 1e9
         out["roofline"] = {
             "bound": "hbm",
             "kernel": "k_basis_p2 (7-point stencil + Jacobi + Chebyshev step, FP64), average of the "
-                      + ("s - 1 launches (AP not written)" if fused else "s launches"),
+                      + {"apply": "s - 1 launches (AP not written)", "recurrence": "s launches (the last writes p_s)",
+                         "stored": "s launches (AP written)"}[kind],
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -523,8 +534,8 @@ def extra_c3(lib, torch, N):
                     b = sv.apply(torch.as_tensor(pr.xstar, device=dev))
                 x = torch.zeros_like(b)
                 t, st = _timed_solve(sv, b, x, 1e-8, torch)
-                bpo = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4, sv.gram_applies_operator)
-                row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "status": st.status,
+                bpo = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4, sv.gram_kind)
+                row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "status": st.status, "gram": sv.gram_kind,
                              "gbps_effective": bpo * st.outer_iters / (t * 1e-3) / 1e9}
                 x.zero_()
                 steps[prec] = sv.step(b, x)
@@ -698,9 +709,9 @@ def sweep(lib, torch, args):
                         ts.append(1e3 * (time.perf_counter() - t0))
                     w = 8 if prec == "fp64" else 4
                     t = float(np.median(ts))
-                    bpo = stencil_bytes_per_outer(pr.n, s, w, sv.gram_applies_operator)
+                    bpo = stencil_bytes_per_outer(pr.n, s, w, sv.gram_kind)
                     row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "rel_res": st.rel_res,
-                                 "gram": "apply_op" if sv.gram_applies_operator else "stored_ap",
+                                 "gram": sv.gram_kind,
                                  "gbps_effective": bpo * st.outer_iters / (t * 1e-3) / 1e9}
             row["fp32ir_speedup"] = row["fp64"]["time_ms"] / row["fp32ir"]["time_ms"]
             rows.append(row)

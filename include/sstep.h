@@ -102,8 +102,20 @@ typedef struct {
  * s <= 16, a basis column under 4 GiB, i.e. n < 2^29 in FP64): the Gram
  * kernel forms A p_j from P itself, so AP is neither written nor allocated
  * and the basis makes s - 1 launches per outer iteration; asking for it
- * otherwise gives SSTEP_E_UNSUPPORTED. */
-typedef enum { SSTEP_GRAM_AUTO = 0, SSTEP_GRAM_STORED_AP = 1, SSTEP_GRAM_APPLY_OP = 2 } sstep_gram_kind;
+ * otherwise gives SSTEP_E_UNSUPPORTED.  RECURRENCE (any operator, s <= 31):
+ * the basis makes s launches, the last one computing p_s instead of A p_{s-1},
+ * and the Gram kernel forms the M-weighted Gram H = P^T M P of the s + 1
+ * columns p_0 .. p_s; the basis recurrence (Sec. 2, Definition) turns it into
+ * G_raw = P^T A P exactly: M^{-1} A p_j = (p_{j+1} + p_{j-1}) / (2 theta)
+ * + sigma p_j (j >= 1), M^{-1} A p_0 = p_1 / theta + sigma p_0 (monomial
+ * basis: M^{-1} A p_j = p_{j+1}).  AP is neither written nor allocated and A
+ * is not applied in the Gram kernel. */
+typedef enum {
+    SSTEP_GRAM_AUTO = 0,
+    SSTEP_GRAM_STORED_AP = 1,
+    SSTEP_GRAM_APPLY_OP = 2,
+    SSTEP_GRAM_RECURRENCE = 3
+} sstep_gram_kind;
 
 typedef struct {
     int32_t precision;      /* sstep_precision, default SSTEP_FP64 */

@@ -42,7 +42,8 @@ def _load(path=None):
     global _lib
     if path is None and _lib is not None:
         return _lib
-    path = path or LIB
+    # a sanitizer build of the same source, for the instrumented test run
+    path = path or os.environ.get("SSTEP_ORACLE_LIB") or LIB
     if path in _libs:
         _lib = _libs[path]
         return _lib

@@ -306,8 +306,14 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
 // The operator-applying Gram kernel: 7-point stencil operators, s <= 16,
 // columns under 4 GiB (32-bit byte offsets); by default for FP64 only (in
 // FP32+IR the stored-AP kernel is as fast).
-sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, const sstep_options &o, bool *gram_op)
+sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, const sstep_options &o, int *kind)
 {
+    if (o.gram == SSTEP_GRAM_RECURRENCE) {
+        if (s > kRecMaxS)
+            return fail(ctx, SSTEP_E_UNSUPPORTED, "the recurrence Gram kind needs s <= 31");
+        *kind = SSTEP_GRAM_RECURRENCE;
+        return SSTEP_OK;
+    }
     const int64_t n = A->kind == SSTEP_OP_CSR ? A->n : int64_t(A->nx) * A->ny * A->nz;
     const uint64_t wbytes = o.precision == SSTEP_FP32_IR ? sizeof(float) : sizeof(double);
     const bool op_ok = A->kind == SSTEP_OP_STENCIL7 && s <= kGoMaxS &&
@@ -316,8 +322,22 @@ sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, co
         return fail(ctx, SSTEP_E_UNSUPPORTED,
                     "the operator-applying Gram kernel needs a 7-point stencil operator, s <= 16 and columns "
                     "under 4 GiB");
-    *gram_op = o.gram == SSTEP_GRAM_APPLY_OP || (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
+    const bool gram_op = o.gram == SSTEP_GRAM_APPLY_OP ||
+                         (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
+    *kind = gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP;
     return SSTEP_OK;
+}
+
+// The Gram kind's launch arguments.  Recurrence kind: the Gram kernel weights
+// its second operand by the M diagonal array when M is not a constant
+// multiple of I, else the FGS kernel applies the constant (6, 26, or 1 without
+// preconditioning).
+void set_gram_kind(IterArgs &it, int kind, int precond, bool const_diag)
+{
+    it.gram_op = kind == SSTEP_GRAM_APPLY_OP;
+    it.gram_rec = kind == SSTEP_GRAM_RECURRENCE;
+    it.rec_wap = it.gram_rec && precond && !const_diag;
+    it.rec_hscale = (it.gram_rec && precond && const_diag) ? (it.op.kind == kOpPoisson27 ? 26.0 : 6.0) : 1.0;
 }
 
 // Residual kernel schedule: at most 1024 row chunks (one partial each), or
@@ -471,6 +491,8 @@ std::string tune_key(const IterArgs &it)
       << " wd=" << it.wdvec;
     if (it.gram_op)
         k << " op2=" << it.op.kind << " grid=" << it.op.g.nx << "x" << it.op.g.ny << "x" << it.op.g.nz;
+    if (it.gram_rec)
+        k << " rec wap=" << it.rec_wap;
     return k.str();
 }
 
@@ -718,10 +740,10 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     OKCHK(check_operator(ctx, A));
     if (A->kind == SSTEP_OP_CSR)
         OKCHK(check_csr_pattern(ctx, A));
-    if (o.gram != SSTEP_GRAM_AUTO && o.gram != SSTEP_GRAM_STORED_AP && o.gram != SSTEP_GRAM_APPLY_OP)
+    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_RECURRENCE)
         return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
-    bool gram_op = false;
-    OKCHK(choose_gram_kind(ctx, A, s, o, &gram_op));
+    int gram_kind = SSTEP_GRAM_STORED_AP;
+    OKCHK(choose_gram_kind(ctx, A, s, o, &gram_kind));
 
     HIPCHK(ctx, hipGetDevice(&ctx->device));
     HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -785,12 +807,14 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     // operator itself, and AP is not kept
     const int64_t n = op.n;
     const size_t w = it.fp32 ? sizeof(float) : sizeof(double);
-    it.gram_op = gram_op;
+    set_gram_kind(it, gram_kind, o.precond, const_diag);
     {
+        // the recurrence kind keeps one more column, p_s
+        const int pcols = s + it.gram_rec;
         char *P = nullptr, *AP = nullptr;
-        OKCHK(dalloc(ctx, &P, size_t(it.ld) * s * w));
-        HIPCHK(ctx, hipMemsetAsync(P, 0, size_t(it.ld) * s * w, ctx->stream));
-        if (!it.gram_op) {
+        OKCHK(dalloc(ctx, &P, size_t(it.ld) * pcols * w));
+        HIPCHK(ctx, hipMemsetAsync(P, 0, size_t(it.ld) * pcols * w, ctx->stream));
+        if (!it.gram_op && !it.gram_rec) {
             OKCHK(dalloc(ctx, &AP, size_t(it.ld) * s * w));
             HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(it.ld) * s * w, ctx->stream));
         }
@@ -799,8 +823,8 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     }
     set_residual_schedule(it);
     OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
-    OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s)) * kMaxGramBlocks));
-    OKCHK(dalloc(ctx, &it.gsum, size_t(gram_entries(s)) + 1));
+    OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s + it.gram_rec)) * kMaxGramBlocks));
+    OKCHK(dalloc(ctx, &it.gsum, size_t(gram_entries(s + it.gram_rec)) + 1));
     OKCHK(dalloc(ctx, &it.st, 1));
     OKCHK(dalloc(ctx, &it.dbg, size_t(dbg_size(s))));
     it.hist_cap = o.record_history ? o.max_outer + 1 : 0;
@@ -885,7 +909,9 @@ sstep_status sstep_apply(sstep_ctx *ctx, const double *x, double *y)
 
 int32_t sstep_gram_mode(const sstep_ctx *ctx)
 {
-    return ctx ? (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP) : -1;
+    if (!ctx)
+        return -1;
+    return ctx->it.gram_rec ? SSTEP_GRAM_RECURRENCE : (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP);
 }
 
 sstep_status sstep_solve(sstep_ctx *ctx, const double *b, double *x, double tol, sstep_stats *st)
@@ -929,7 +955,7 @@ sstep_status sstep_step(sstep_ctx *ctx, const double *b, double *x, double *alph
     if (P_out)
         HIPCHK(ctx, launch_copy_cols(it.P, it.ld, it.fp32, s, it.op.n, P_out, ctx->stream));
     if (AP_out) {
-        if (it.gram_op) {
+        if (!it.AP) {
             // AP is not kept: form A p_j with the basis kernels' product step
             // into a buffer allocated on first use.
             if (!ctx->ap_step) {
@@ -1691,7 +1717,7 @@ NoallocLayout noalloc_layout(const IterArgs &it)
         o += (bytes + 255) / 256 * 256;
         return at;
     };
-    const size_t E = size_t(gram_entries(it.s));
+    const size_t E = size_t(gram_entries(it.s + it.gram_rec));
     const size_t ld = size_t(it.ld);
     L.st = take(sizeof(DevState));
     L.rpart = take(size_t(it.nbr) * sizeof(double));
@@ -1703,8 +1729,8 @@ NoallocLayout noalloc_layout(const IterArgs &it)
     const bool faces = it.op.kind == kOpFaces, csr = it.op.kind == kOpCsr;
     L.dvec = take(faces || csr ? ld * sizeof(double) : 0);
     L.invd = take(csr ? ld * sizeof(double) : 0);
-    L.P = take(ld * size_t(it.s) * sizeof(double));
-    L.AP = take(it.gram_op ? 0 : ld * size_t(it.s) * sizeof(double));
+    L.P = take(ld * size_t(it.s + it.gram_rec) * sizeof(double));
+    L.AP = take(it.gram_op || it.gram_rec ? 0 : ld * size_t(it.s) * sizeof(double));
     L.total = o;
     return L;
 }
@@ -1728,7 +1754,7 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0 ||
         (o.basis != 0 && o.basis != 1))
         return fail(nullptr, SSTEP_E_ARG, "invalid options");
-    if (o.gram != SSTEP_GRAM_AUTO && o.gram != SSTEP_GRAM_STORED_AP && o.gram != SSTEP_GRAM_APPLY_OP)
+    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_RECURRENCE)
         return fail(nullptr, SSTEP_E_ARG, "unknown gram kind");
     if (!b || !x)
         return fail(nullptr, SSTEP_E_ARG, "b and x must not be NULL");
@@ -1738,8 +1764,8 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     const bool has_arrays = A->kind == SSTEP_OP_CSR || (A->kind == SSTEP_OP_STENCIL7 && A->kx);
     if (has_arrays && A->ptr_space != 1)
         return fail(nullptr, SSTEP_E_ARG, "the allocation-free solve takes operator arrays in device memory");
-    bool gram_op = false;
-    OKCHK(choose_gram_kind(nullptr, A, s, o, &gram_op));
+    int gram_kind = SSTEP_GRAM_STORED_AP;
+    OKCHK(choose_gram_kind(nullptr, A, s, o, &gram_kind));
 
     IterArgs it;
     OpDev &op = it.op;
@@ -1772,9 +1798,9 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     it.theta = 2.0 / (lmax - lmin);
     it.sigma = (lmax + lmin) / 2.0;
     it.ld = round_up(op.n, kPad);
-    it.gram_op = gram_op;
     const bool jac_p0 = o.precond == 1 && o.p0_mode == 0;
     const bool const_diag = op.kind == kOpPoisson || op.kind == kOpPoisson27;
+    set_gram_kind(it, gram_kind, o.precond, const_diag);
     it.wdvec = jac_p0 && !const_diag;
     it.cscale = (jac_p0 && const_diag) ? (op.kind == kOpPoisson27 ? 26.0 : 6.0) : 1.0;
     it.inv_sqrt_n = 1.0 / std::sqrt(double(op.n));
@@ -1797,7 +1823,7 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     it.hist = reinterpret_cast<double *>(base + L.hist);
     int *bad = reinterpret_cast<int *>(base + L.bad);
     it.P = base + L.P;
-    it.AP = it.gram_op ? nullptr : base + L.AP;
+    it.AP = it.gram_op || it.gram_rec ? nullptr : base + L.AP;
 
     hipStream_t st = static_cast<hipStream_t>(o.stream);
     // the array keeps the previous call's contents: clear everything that is

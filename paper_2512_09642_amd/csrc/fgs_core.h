@@ -182,6 +182,69 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
     fgs_wave<s>(st, sg, nu, cscale, fp32, inv_sqrt_n, dbg, hist, hist_cap);
 }
 
+// The recurrence kind: the sums hold the M-weighted Gram H = P^T M P of the
+// s + 1 columns p_0 .. p_s (lower triangle, canonical order) and c'_i (s + 1
+// entries).  The Chebyshev recurrence of the basis (Sec. 2, Definition) gives
+//     M^{-1} A p_0 = p_1 / theta + sigma p_0,
+//     M^{-1} A p_j = (p_{j+1} + p_{j-1}) / (2 theta) + sigma p_j,   j >= 1,
+// (the monomial basis: M^{-1} A p_j = p_{j+1}), hence
+//     G_raw,ij = p_i^T A p_j = H_i1 / theta + sigma H_i0                (j = 0)
+//              = (H_i,j+1 + H_i,j-1) / (2 theta) + sigma H_ij          (j >= 1),
+// the same matrix P^T (A P) without applying A.  hscale is the constant M
+// diagonal (6, 26 or 1) when the kernel did not weight by M itself.  The
+// block writes G_raw (lower triangle) and c' for the s columns into LDS in
+// the layout of k_fgs, then wave 0 runs fgs_wave.
+template <int s>
+__global__ __launch_bounds__(kFgsThreads) void k_fgs_rec(DevState *__restrict__ st, const double *__restrict__ sums,
+                                                         int nu, double cscale, int fp32, double inv_sqrt_n,
+                                                         double *__restrict__ dbg, double *__restrict__ hist,
+                                                         int hist_cap, double theta, double sigma, double hscale,
+                                                         int monomial)
+{
+    if (st->done)
+        return;
+    constexpr int S1 = s + 1;
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    constexpr int T0 = s * (s + 1) / 2;
+    __shared__ double h[E1];
+    __shared__ double sg[T0 + s];
+    for (int t = threadIdx.x; t < E1; t += kFgsThreads)
+        h[t] = sums[t];
+    __syncthreads();
+    auto H = [&](int a, int b) { return a >= b ? h[tri_index(a, b)] : h[tri_index(b, a)]; };
+    for (int e = threadIdx.x; e < T0; e += kFgsThreads) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= e)
+            ++i;
+        const int j = e - i * (i + 1) / 2;
+        double g;
+        if (monomial)
+            g = H(i, j + 1);
+        else if (j == 0)
+            g = H(i, 1) / theta + sigma * H(i, 0);
+        else
+            g = (H(i, j + 1) + H(i, j - 1)) / (2.0 * theta) + sigma * H(i, j);
+        sg[e] = hscale * g;
+    }
+    for (int i = threadIdx.x; i < s; i += kFgsThreads)
+        sg[T0 + i] = h[S1 * (S1 + 1) / 2 + i];
+    __syncthreads();
+    if (threadIdx.x / kWave != 0)
+        return;
+    fgs_wave<s>(st, sg, nu, cscale, fp32, inv_sqrt_n, dbg, hist, hist_cap);
+}
+
+template <int s>
+hipError_t fgs_rec_launch_s(const IterArgs &a, hipStream_t st)
+{
+    constexpr int S1 = s + 1;
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    hipLaunchKernelGGL(k_partial_sums<S1>, dim3(E1), dim3(kSumThreads), 0, st, a.st, a.gpart, a.nbg, a.gsum);
+    hipLaunchKernelGGL(k_fgs_rec<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.gsum, a.nu, a.cscale, a.fp32,
+                       a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap, a.theta, a.sigma, a.rec_hscale, a.monomial);
+    return hipGetLastError();
+}
+
 template <int s>
 hipError_t fgs_launch_s(const IterArgs &a, hipStream_t st)
 {

@@ -9,8 +9,18 @@ namespace sstep {
 #define SSTEP_CASES_17_32(F) \
     F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31) F(32)
 
+#define SSTEP_CASES_17_31(F) \
+    F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31)
+
 hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 {
+    if (a.gram_rec) {
+#define SSTEP_GR(S)                                                                          \
+    case S:                                                                                  \
+        return a.fp32 ? gram_rec_launch_s<float, S>(a, st) : gram_rec_launch_s<double, S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_GR) SSTEP_CASES_17_31(SSTEP_GR) default: return hipErrorInvalidValue; }
+#undef SSTEP_GR
+    }
     if (a.gram_op) {
 #define SSTEP_GO(S)                                                                          \
     case S:                                                                                  \
@@ -27,6 +37,13 @@ hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_fgs(const IterArgs &a, hipStream_t st)
 {
+    if (a.gram_rec) {
+#define SSTEP_FR(S) \
+    case S:         \
+        return fgs_rec_launch_s<S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_FR) SSTEP_CASES_17_31(SSTEP_FR) default: return hipErrorInvalidValue; }
+#undef SSTEP_FR
+    }
 #define SSTEP_F(S) \
     case S:        \
         return fgs_launch_s<S>(a, st);

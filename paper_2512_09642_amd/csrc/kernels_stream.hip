@@ -548,7 +548,7 @@ hipError_t basis_for(const IterArgs &a, const Op &op, int j, int step, hipStream
     const T *pj = P + j * a.ld;
     const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
     T *apj = AP ? AP + j * a.ld : nullptr;
-    T *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
+    T *pnext = j + 1 < a.s || a.gram_rec ? P + (j + 1) * a.ld : nullptr;
     const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
     if (step == 2)
         hipLaunchKernelGGL((k_basis<Op, T, 2>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
@@ -574,7 +574,7 @@ hipError_t basis_poisson_pairs(const IterArgs &a, int j, int step, hipStream_t s
     const double *pj = P + j * a.ld;
     const double *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
     double *apj = AP ? AP + j * a.ld : nullptr;
-    double *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
+    double *pnext = j + 1 < a.s || a.gram_rec ? P + (j + 1) * a.ld : nullptr;
     const double minv = a.op.precond ? 1.0 / 6.0 : 1.0;
     if (step == 2)
         hipLaunchKernelGGL(k_basis_p2<2>, grid, dim3(kP2Block), 0, st, a.st, a.op.g, minv, pj, pprev, apj, pnext,
@@ -597,7 +597,7 @@ hipError_t basis_csr(const IterArgs &a, int j, int step, hipStream_t st)
     const T *pj = P + j * a.ld;
     const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
     T *apj = AP ? AP + j * a.ld : nullptr;
-    T *pnext = j + 1 < a.s ? P + (j + 1) * a.ld : nullptr;
+    T *pnext = j + 1 < a.s || a.gram_rec ? P + (j + 1) * a.ld : nullptr;
     const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
     const OpCsr<T> op = Ops<T>::csr(a.op);
     if (step == 2)
@@ -734,15 +734,17 @@ hipError_t launch_p0scale(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st)
 {
+    // the last launch forms only A p_{s-1} (stored AP), or p_s (recurrence kind)
+    const bool last_product = j + 1 >= a.s && !a.gram_rec;
     if (a.monomial) {
         // p_{j+1} = theta (M^{-1} A p_j - sigma p_j) with theta = 1, sigma = 0
         IterArgs m = a;
         m.theta = 1.0;
         m.sigma = 0.0;
-        const int step = j + 1 >= a.s ? 2 : 0;
+        const int step = last_product ? 2 : 0;
         return a.fp32 ? basis_t<float>(m, j, step, st) : basis_t<double>(m, j, step, st);
     }
-    const int step = j + 1 >= a.s ? 2 : (j == 0 ? 0 : 1);
+    const int step = last_product ? 2 : (j == 0 ? 0 : 1);
     return a.fp32 ? basis_t<float>(a, j, step, st) : basis_t<double>(a, j, step, st);
 }
 

@@ -17,6 +17,8 @@ constexpr int64_t kPad = 256;
 constexpr int kMaxGramBlocks = 2048;
 // Widest basis served by the Gram kernel that applies a stencil operator itself.
 constexpr int kGoMaxS = 16;
+// Widest basis of the recurrence Gram kind (it needs the Gram of s + 1 columns).
+constexpr int kRecMaxS = 31;
 // Smallest row chunk of a batched tile; the tile tables and partial buffers
 // are sized for it.
 constexpr int64_t kMinBatchChunk = 2048;
@@ -78,6 +80,11 @@ struct IterArgs {
     int go_tiles[2] = {0, 0};           // tiles of the full-tile and edge-tile launches
     int go_items[2] = {0, 0};           // work items (tile, z-range) of each launch
     int go_blocks[2] = {0, 0};          // blocks (= partial slots) of each launch
+    // Recurrence kind (G_raw from the M-weighted Gram of p_0 .. p_s): the basis
+    // makes s launches, the last writing p_s into column s of P:
+    int gram_rec = 0;
+    int rec_wap = 0;          // the Gram kernel weights by the M diagonal array
+    double rec_hscale = 1.0;  // constant M diagonal applied by the FGS kernel otherwise
 };
 
 // Debug block layout written by the FGS kernel.

@@ -164,6 +164,8 @@ class Solver:
         self.grad_size = int(self._lib.sstep_grad_size(ctx))
         # True when the Gram kernel forms A p_j itself (AP not kept, s - 1 basis launches)
         self.gram_applies_operator = bool(self._lib.sstep_gram_mode(ctx) == N.GRAM_KINDS["apply"])
+        # "stored", "apply" or "recurrence": how this context forms G = P^T A P
+        self.gram_kind = {v: k for k, v in N.GRAM_KINDS.items()}[int(self._lib.sstep_gram_mode(ctx))]
 
     def _stream_ptr(self):
         if self._stream is not None:
