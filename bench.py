@@ -207,7 +207,8 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
             if name not in legs:
                 continue
             leg = Leg(name)
-            leg.solver = base if prec == "fp64" else lib.Solver(op, s, nu, pr.lmin, pr.lmax, precision=prec)
+            leg.solver = base if prec == "fp64" else lib.Solver(op, s, nu, pr.lmin, pr.lmax, precision=prec,
+                                                                gram="stored" if gram == "apply" else gram)
             leg.b, leg.x = b, torch.zeros_like(b)
 
             def run(leg=leg):
@@ -242,7 +243,8 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
         pr = gen.config1(0)
         rp, ci, v = pr.csr()
         leg = Leg("c1_csr_fp64")
-        leg.solver = lib.Solver(lib.Operator.csr(rp, ci, v), pr.s, pr.nu, pr.lmin, pr.lmax)
+        leg.solver = lib.Solver(lib.Operator.csr(rp, ci, v), pr.s, pr.nu, pr.lmin, pr.lmax,
+                                gram="stored" if gram == "apply" else gram)
         leg.b = leg.solver.apply(torch.as_tensor(pr.xstar, device=dev))
         leg.x = torch.zeros_like(leg.b)
 
@@ -259,7 +261,8 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
     if "c5_adjoint" in legs:
         pr = gen.config5(0)
         leg = Leg("c5_adjoint")
-        leg.solver = lib.Solver(lib.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz), pr.s, pr.nu, pr.lmin, pr.lmax)
+        leg.solver = lib.Solver(lib.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz), pr.s, pr.nu, pr.lmin, pr.lmax,
+                                gram=gram)
         leg.coeffs = torch.as_tensor(np.concatenate([pr.kx, pr.ky, pr.kz]), device=dev)
         leg.b = torch.as_tensor(pr.rhs[0], device=dev)
         leg.xt = torch.as_tensor(pr.xtarget, device=dev)
@@ -315,6 +318,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
         leg.bytes_per_outer = None
         leg.n = sum(sizes)
         leg.nsys = len(probs)
+        leg.sides = [p.dims[0] for p in probs]
         out[name] = leg
         log(f"{name} ready: {len(probs)} systems, {leg.n} unknowns x 8 rhs")
     return out
@@ -338,7 +342,8 @@ def main():
                          "27-point table, the coarse solve)")
     ap.add_argument("--N27", type=int, default=230, help="grid edge of the paper's 27-point workload")
     ap.add_argument("--gram", default="auto", choices=["auto", "stored", "apply", "recurrence"],
-                    help="Gram kind of the FP64 legs of the 224^3 problem (default: the library's choice)")
+                    help="Gram kind of the single-system legs (default: the library's choice; 'apply' falls back "
+                         "to 'stored' where the operator-applying kernel does not exist)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of n doubles (calibrates traffic counters)")
     ap.add_argument("--sweep", action="store_true",
@@ -398,9 +403,16 @@ def main():
                 its = leg.pair_iters[q * 8:(q + 1) * 8]
                 per_rhs, faces = leg.pair_bytes[q]
                 tot_bytes += per_rhs * sum(its) + faces * max(its)
+            per_sys = [max(leg.pair_iters[q * 8:(q + 1) * 8]) for q in range(leg.nsys)]
             r.update(outer_iters_min=min(leg.pair_iters), outer_iters_max=max(leg.pair_iters),
                      pairs=len(leg.pair_iters), unknown_rhs=leg.n * 8,
-                     max_rel_res=max(leg.pair_relres), gbps_effective=tot_bytes / (t * 1e-3) / 1e9)
+                     max_rel_res=max(leg.pair_relres), gbps_effective=tot_bytes / (t * 1e-3) / 1e9,
+                     # the spread of iteration counts against the grid side N of each system (cubic N^3 grids):
+                     # Spearman rank correlation and the slowest system
+                     iters_vs_side_spearman=float(np.corrcoef(np.argsort(np.argsort(leg.sides)),
+                                                              np.argsort(np.argsort(per_sys)))[0, 1]),
+                     slowest_system={"side": leg.sides[int(np.argmax(per_sys))], "outer_iters": max(per_sys)},
+                     system_side_and_iters=[[int(a), int(b)] for a, b in zip(leg.sides, per_sys)])
         elif name == "c5_adjoint":
             f, bw = float(np.median(leg.fwd)), float(np.median(leg.bwd))
             fi = leg.solver.last_forward_stats.outer_iters

@@ -322,9 +322,13 @@ sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, co
         return fail(ctx, SSTEP_E_UNSUPPORTED,
                     "the operator-applying Gram kernel needs a 7-point stencil operator, s <= 16 and columns "
                     "under 4 GiB");
-    const bool gram_op = o.gram == SSTEP_GRAM_APPLY_OP ||
-                         (o.gram == SSTEP_GRAM_AUTO && op_ok && o.precision == SSTEP_FP64);
-    *kind = gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP;
+    if (o.gram == SSTEP_GRAM_APPLY_OP)
+        *kind = SSTEP_GRAM_APPLY_OP;
+    else if (o.gram == SSTEP_GRAM_STORED_AP)
+        *kind = SSTEP_GRAM_STORED_AP;
+    else  // AUTO: the recurrence kind was measured fastest for every operator, precision and s <= 31
+        *kind = s <= kRecMaxS ? SSTEP_GRAM_RECURRENCE : (op_ok && o.precision == SSTEP_FP64 ? SSTEP_GRAM_APPLY_OP
+                                                                                               : SSTEP_GRAM_STORED_AP);
     return SSTEP_OK;
 }
 
@@ -417,6 +421,8 @@ GramSchedule default_gram_schedule(const IterArgs &it)
     // per CU, FP32 prefers grid-strided 2048-row slabs.
     if (it.gram_op)
         return GramSchedule{1024, 0, 0.0};
+    if (it.gram_rec)
+        return GramSchedule{kMaxGramBlocks, 0, 0.0};  // matrix-core Gram: many small blocks, contiguous rows
     return it.fp32 ? GramSchedule{256, 2048, 0.0} : GramSchedule{256, 0, 0.0};
 }
 
@@ -519,6 +525,9 @@ sstep_status tune_gram(sstep_ctx *ctx)
         // partials grows with their number and is not part of this timing
         for (int cap : {256, 384, 512, 768, 1024})
             cand.push_back({cap, 0, 0.0});
+    } else if (it.gram_rec) {
+        for (int nbg : {512, 1024, 1536, 2048})  // contiguous row chunks only
+            cand.push_back({nbg, 0, 0.0});
     } else {
         for (int nbg : {256, 384, 512, 1024, 2048})
             cand.push_back({nbg, 0, 0.0});

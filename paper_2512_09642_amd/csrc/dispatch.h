@@ -15,10 +15,10 @@ template <typename T, int S>
 hipError_t gram_op_launch_s(const IterArgs &a, hipStream_t st);
 template <int S>
 hipError_t fgs_launch_s(const IterArgs &a, hipStream_t st);
-template <typename T, int S>
-hipError_t gram_rec_launch_s(const IterArgs &a, hipStream_t st);
 template <int S>
 hipError_t fgs_rec_launch_s(const IterArgs &a, hipStream_t st);
+template <typename T, int S>
+hipError_t gram_sym_launch_s(const IterArgs &a, hipStream_t st);
 template <typename T, int S>
 hipError_t bgram_launch_s(const BatchArgs &a, hipStream_t st);
 template <int S>

@@ -114,26 +114,9 @@ __device__ __forceinline__ T lanepart(const typename VecT<T, RPL>::t &v, int r)
         return r == 0 ? v.x : r == 1 ? v.y : r == 2 ? v.z : v.w;
 }
 
-template <typename T, int RPL>
-__device__ __forceinline__ void vmul(typename VecT<T, RPL>::t &a, const typename VecT<T, RPL>::t &b)
-{
-    if constexpr (RPL == 1) {
-        a *= b;
-    } else {
-        a.x *= b.x;
-        a.y *= b.y;
-        if constexpr (RPL == 4) {
-            a.z *= b.z;
-            a.w *= b.w;
-        }
-    }
-}
-
 // Rows SPL of group G for the RPL rows starting at m (no guard: rows past the
-// end of the matrix are zero padding).  WAP: the second operand is weighted
-// by the M diagonal, AP[:, j] := M AP[:, j] (the M-weighted Gram of the
-// recurrence kind, called with AP = P).
-template <typename T, int S, int G, int RPL, bool WD, bool WAP = false>
+// end of the matrix are zero padding).
+template <typename T, int S, int G, int RPL, bool WD>
 __device__ __forceinline__ void gram_rows(const T *__restrict__ P, const T *__restrict__ AP,
                                           const T *__restrict__ dvec, int64_t cs, int64_t m, T *acc)
 {
@@ -145,17 +128,22 @@ __device__ __forceinline__ void gram_rows(const T *__restrict__ P, const T *__re
 #pragma unroll
     for (int j = C0; j < C1; ++j)  // P and AP are read once per launch: non-temporal loads
         ap[j - C0] = nt_load<T, RPL>(AP + j * cs + m);
-    if constexpr (WAP) {
-        const V dw = *reinterpret_cast<const V *>(dvec + m);
-#pragma unroll
-        for (int j = C0; j < C1; ++j)
-            vmul<T, RPL>(ap[j - C0], dw);
-    }
     V w{};
     if constexpr (HC) {
         w = *reinterpret_cast<const V *>(P + m);
-        if constexpr (WD)
-            vmul<T, RPL>(w, *reinterpret_cast<const V *>(dvec + m));
+        if constexpr (WD) {
+            const V dv = *reinterpret_cast<const V *>(dvec + m);
+            if constexpr (RPL == 1) {
+                w *= dv;
+            } else {
+                w.x *= dv.x;
+                w.y *= dv.y;
+                if constexpr (RPL == 4) {
+                    w.z *= dv.z;
+                    w.w *= dv.w;
+                }
+            }
+        }
     }
     int a = 0;
 #pragma unroll
@@ -209,7 +197,7 @@ __device__ __forceinline__ void gram_store(const T *acc, double *__restrict__ gp
 // Group G over rows [beg, end) in slabs of SL rows taken every `stride`
 // rows (contiguous schedule: one slab, SL = end - beg).  beg, SL and stride
 // are multiples of 64 * RPL.
-template <typename T, int S, int G, int RPL, bool WD, bool WAP>
+template <typename T, int S, int G, int RPL, bool WD>
 __device__ __forceinline__ void gram_group(const T *__restrict__ P, const T *__restrict__ AP,
                                            const T *__restrict__ dvec, int64_t cs, int64_t beg, int64_t end,
                                            int64_t SL, int64_t stride, double *__restrict__ gpart, int64_t estride,
@@ -226,33 +214,32 @@ __device__ __forceinline__ void gram_group(const T *__restrict__ P, const T *__r
     for (int64_t s0 = beg; s0 < end; s0 += stride) {
         const int64_t e0 = s0 + SL < end ? s0 + SL : end;
         for (int64_t base = s0; base < e0; base += STEP)
-            gram_rows<T, S, G, RPL, WD, WAP>(P, AP, dvec, cs, base + lane * RPL, acc);
+            gram_rows<T, S, G, RPL, WD>(P, AP, dvec, cs, base + lane * RPL, acc);
     }
     gram_store<T, S, G>(acc, gpart, estride, slot);
 }
 
-template <typename T, int S, int RPL, bool WD, bool WAP, int G>
+template <typename T, int S, int RPL, bool WD, int G>
 __device__ __forceinline__ void gram_dispatch(int w, const T *P, const T *AP, const T *dvec, int64_t cs, int64_t beg,
                                               int64_t end, int64_t SL, int64_t stride, double *gpart,
                                               int64_t estride, int64_t slot)
 {
     if constexpr (G < GramPlan<S>::NG) {
         if (w == G)
-            gram_group<T, S, G, RPL, WD, WAP>(P, AP, dvec, cs, beg, end, SL, stride, gpart, estride, slot);
+            gram_group<T, S, G, RPL, WD>(P, AP, dvec, cs, beg, end, SL, stride, gpart, estride, slot);
         else
-            gram_dispatch<T, S, RPL, WD, WAP, G + 1>(w, P, AP, dvec, cs, beg, end, SL, stride, gpart, estride,
-                                                     slot);
+            gram_dispatch<T, S, RPL, WD, G + 1>(w, P, AP, dvec, cs, beg, end, SL, stride, gpart, estride, slot);
     }
 }
 
 // The whole block's share (wave w owns group w).
-template <typename T, int S, int RPL, bool WD, bool WAP = false>
+template <typename T, int S, int RPL, bool WD>
 __device__ __forceinline__ void gram_tile(const T *P, const T *AP, const T *dvec, int64_t cs, int64_t beg,
                                           int64_t end, int64_t SL, int64_t stride, double *gpart, int64_t estride,
                                           int64_t slot)
 {
-    gram_dispatch<T, S, RPL, WD, WAP, 0>(static_cast<int>(threadIdx.x / kWave), P, AP, dvec, cs, beg, end, SL,
-                                         stride, gpart, estride, slot);
+    gram_dispatch<T, S, RPL, WD, 0>(static_cast<int>(threadIdx.x / kWave), P, AP, dvec, cs, beg, end, SL, stride,
+                                    gpart, estride, slot);
 }
 
 // Rows per lane: 16-byte loads, except FP64 with 16 waves per block (s > 24),
@@ -266,7 +253,7 @@ constexpr int gram_rpl()
 // Single system: rows [0, rows) with rows a multiple of 256 (zero padding).
 //   contiguous: block b owns [b*chunk, (b+1)*chunk)
 //   strided:    block b owns slabs [b*SL + q*nbg*SL, ... + SL)
-template <typename T, int S, bool WD, bool WAP = false>
+template <typename T, int S, bool WD>
 __global__ __launch_bounds__(kWave * GramPlan<S>::NG) void k_gram(const DevState *__restrict__ st,
                                                                   const T *__restrict__ P, const T *__restrict__ AP,
                                                                   const T *__restrict__ dvec, int64_t ld,
@@ -277,13 +264,12 @@ __global__ __launch_bounds__(kWave * GramPlan<S>::NG) void k_gram(const DevState
         return;
     const int64_t b = blockIdx.x;
     if (slab > 0) {  // strided
-        gram_tile<T, S, gram_rpl<T, S>(), WD, WAP>(P, AP, dvec, ld, b * slab, rows, slab, int64_t(nbg) * slab,
-                                                gpart, nbg, b);
+        gram_tile<T, S, gram_rpl<T, S>(), WD>(P, AP, dvec, ld, b * slab, rows, slab, int64_t(nbg) * slab, gpart, nbg,
+                                           b);
     } else {  // contiguous
         const int64_t beg = b * chunk;
         const int64_t end = beg + chunk < rows ? beg + chunk : rows;
-        gram_tile<T, S, gram_rpl<T, S>(), WD, WAP>(P, AP, dvec, ld, beg, end, end - beg, end - beg + 1, gpart, nbg,
-                                                b);
+        gram_tile<T, S, gram_rpl<T, S>(), WD>(P, AP, dvec, ld, beg, end, end - beg, end - beg + 1, gpart, nbg, b);
     }
 }
 
@@ -303,34 +289,6 @@ hipError_t gram_launch_s(const IterArgs &a, hipStream_t st)
     else
         hipLaunchKernelGGL((k_gram<T, S, false>), dim3(a.nbg), block, 0, st, a.st, P, AP, dv, a.ld, a.ld, a.gchunk,
                            a.gslab, a.gpart, a.nbg);
-    return hipGetLastError();
-}
-
-// The recurrence kind for basis width S: the M-weighted Gram H = P^T M P of
-// the S + 1 columns p_0 .. p_S (lower triangle) and the right-hand side
-// entries c'_i = p_i^T W, by the same kernel with AP = P (M applied to the
-// second operand when the diagonal is not a constant; a constant diagonal is
-// applied by the FGS kernel).
-template <typename T, int S>
-hipError_t gram_rec_launch_s(const IterArgs &a, hipStream_t st)
-{
-    constexpr int S1 = S + 1;
-    const dim3 block(kWave * GramPlan<S1>::NG);
-    const T *P = static_cast<const T *>(a.P);
-    const T *dv = reinterpret_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(a.op.dvec)
-                                                             : static_cast<const void *>(a.op.dvec32));
-    if (a.wdvec && a.rec_wap)
-        hipLaunchKernelGGL((k_gram<T, S1, true, true>), dim3(a.nbg), block, 0, st, a.st, P, P, dv, a.ld, a.ld,
-                           a.gchunk, a.gslab, a.gpart, a.nbg);
-    else if (a.wdvec)
-        hipLaunchKernelGGL((k_gram<T, S1, true, false>), dim3(a.nbg), block, 0, st, a.st, P, P, dv, a.ld, a.ld,
-                           a.gchunk, a.gslab, a.gpart, a.nbg);
-    else if (a.rec_wap)
-        hipLaunchKernelGGL((k_gram<T, S1, false, true>), dim3(a.nbg), block, 0, st, a.st, P, P, dv, a.ld, a.ld,
-                           a.gchunk, a.gslab, a.gpart, a.nbg);
-    else
-        hipLaunchKernelGGL((k_gram<T, S1, false, false>), dim3(a.nbg), block, 0, st, a.st, P, P, dv, a.ld, a.ld,
-                           a.gchunk, a.gslab, a.gpart, a.nbg);
     return hipGetLastError();
 }
 

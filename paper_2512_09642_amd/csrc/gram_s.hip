@@ -4,6 +4,7 @@
 #include "batched_impl.h"
 #include "dispatch.h"
 #include "gram_op_impl.h"
+#include "gram_sym_impl.h"
 
 #ifndef SSTEP_S
 #error "compile with -DSSTEP_S=<basis width>"
@@ -23,8 +24,8 @@ template hipError_t bgram_launch_s<double, SSTEP_S>(const BatchArgs &, hipStream
 template hipError_t bgram_launch_s<float, SSTEP_S>(const BatchArgs &, hipStream_t);
 template hipError_t bfgs_launch_s<SSTEP_S>(const BatchArgs &, hipStream_t);
 #if SSTEP_S <= SSTEP_REC_MAX_S
-template hipError_t gram_rec_launch_s<double, SSTEP_S>(const IterArgs &, hipStream_t);
-template hipError_t gram_rec_launch_s<float, SSTEP_S>(const IterArgs &, hipStream_t);
+template hipError_t gram_sym_launch_s<double, SSTEP_S>(const IterArgs &, hipStream_t);
+template hipError_t gram_sym_launch_s<float, SSTEP_S>(const IterArgs &, hipStream_t);
 template hipError_t fgs_rec_launch_s<SSTEP_S>(const IterArgs &, hipStream_t);
 #endif
 #if SSTEP_S <= 16

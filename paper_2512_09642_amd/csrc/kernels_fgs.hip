@@ -15,11 +15,11 @@ namespace sstep {
 hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 {
     if (a.gram_rec) {
-#define SSTEP_GR(S)                                                                          \
+#define SSTEP_GS(S)                                                                          \
     case S:                                                                                  \
-        return a.fp32 ? gram_rec_launch_s<float, S>(a, st) : gram_rec_launch_s<double, S>(a, st);
-        switch (a.s) { SSTEP_CASES_1_16(SSTEP_GR) SSTEP_CASES_17_31(SSTEP_GR) default: return hipErrorInvalidValue; }
-#undef SSTEP_GR
+        return a.fp32 ? gram_sym_launch_s<float, S>(a, st) : gram_sym_launch_s<double, S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_GS) SSTEP_CASES_17_31(SSTEP_GS) default: return hipErrorInvalidValue; }
+#undef SSTEP_GS
     }
     if (a.gram_op) {
 #define SSTEP_GO(S)                                                                          \

@@ -300,7 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_basis_csr(const DevState *__restrict
     }
     const T pc = pj[c];
     const T dinv = op.invd[c];
-    __builtin_nontemporal_store(acc, apj + c);
+    if (apj)  // AP is not kept by the recurrence Gram kind
+        __builtin_nontemporal_store(acc, apj + c);
     if constexpr (STEP == 0) {
         pnext[c] = theta * (dinv * acc - sigma * pc);
     } else if constexpr (STEP == 1) {

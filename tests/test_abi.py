@@ -122,8 +122,9 @@ def test_batched_entry_points_report_status(native):
 
 def test_setup_rejects_unavailable_gram_kinds(native):
     """The operator-applying Gram kernel needs a stencil operator, s <= 16 and
-    columns under 4 GiB; asking for it otherwise is unsupported, an unknown
-    kind is an argument error.  Checked before any device work."""
+    columns under 4 GiB, the recurrence kind s <= 31; asking for them
+    otherwise is unsupported, an unknown kind is an argument error.  Checked
+    before any device work."""
     lib = native.load()
 
     def setup(op, s, gram):
@@ -140,8 +141,11 @@ def test_setup_rejects_unavailable_gram_kinds(native):
     op, keep = _csr(native, rp, ci, v)
     st, ctx = setup(op, 4, apply_op)
     assert st == 7 and not ctx.value
-    st, ctx = setup(_poisson(native), 4, 3)
+    st, ctx = setup(_poisson(native), 4, 9)
     assert st == 1 and not ctx.value
+    # the recurrence kind needs the Gram of s + 1 <= 32 columns
+    st, ctx = setup(_poisson(native), 32, native.GRAM_KINDS["recurrence"])
+    assert st == 7 and not ctx.value
     # 820^3 doubles per column exceed the kernel's 32-bit byte offsets
     st, ctx = setup(_poisson(native, 820, 820, 820), 4, apply_op)
     assert st == 7 and not ctx.value

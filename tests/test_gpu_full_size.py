@@ -1,7 +1,7 @@
 """The headline workload at its full size: 224^3 Poisson (11,239,424 unknowns),
 s = 16, nu = 25, matrix-free stencil, FP64, with the solver built exactly as
-the benchmark builds it (default options, so the Gram kernel that applies the
-operator itself, the autotuned schedule and the graph-chunked solve).
+the benchmark builds it (default options, so the recurrence Gram kind, the
+autotuned schedule and the graph-chunked solve).
 
 Two checks against the oracle:
 - lockstep: two outer iterations from the same x_k, each compared with the
@@ -59,7 +59,7 @@ def test_full_size_lockstep_matches_oracle(hip, c2):
     bt = t64(b)
     x = np.zeros(pr.n)
     with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax) as sv:
-        assert sv.gram_applies_operator
+        assert sv.gram_kind == "recurrence"
         for k in range(2):
             g = sv.step(bt, t64(x))
             o = oracle.step(A, b, x, S, NU, pr.lmin, pr.lmax)
@@ -80,7 +80,7 @@ def test_full_size_solve_follows_oracle(hip, c2):
         ref = json.load(f)
     assert ref["status"] == 0
     with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax, record_history=True) as sv:
-        assert sv.gram_applies_operator
+        assert sv.gram_kind == "recurrence"
         x, st = sv.solve(t64(b), None, 1e-8, history=True)
     assert st.status == 0
     assert abs(st.outer_iters - ref["iters"]) <= max(1, int(0.05 * ref["iters"])), (st.outer_iters, ref["iters"])

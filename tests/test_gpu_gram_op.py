@@ -34,20 +34,27 @@ PROBLEMS = {
 
 
 def test_gram_mode_selection(hip):
+    """The default is the recurrence kind for s <= 31 (every operator and
+    precision), the stored-AP kind at s = 32; the operator-applying kind on
+    request for 7-point stencils with s <= 16."""
     pr = ragged_poisson(0)
     op = make_operator(hip, pr, "stencil")
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax) as sv:
-        assert sv.gram_applies_operator
+        assert sv.gram_kind == "recurrence" and not sv.gram_applies_operator
+    with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, gram="apply") as sv:
+        assert sv.gram_kind == "apply" and sv.gram_applies_operator
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, gram="stored") as sv:
-        assert not sv.gram_applies_operator
+        assert sv.gram_kind == "stored"
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, precision="fp32ir") as sv:
-        assert not sv.gram_applies_operator
+        assert sv.gram_kind == "recurrence"
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, precision="fp32ir", gram="apply") as sv:
-        assert sv.gram_applies_operator
+        assert sv.gram_kind == "apply"
     with hip.Solver(op, 17, 5, pr.lmin, pr.lmax) as sv:
-        assert not sv.gram_applies_operator
+        assert sv.gram_kind == "recurrence"
+    with hip.Solver(op, 32, 5, pr.lmin, pr.lmax) as sv:
+        assert sv.gram_kind == "stored"
     with hip.Solver(make_operator(hip, pr, "csr"), 8, 5, pr.lmin, pr.lmax) as sv:
-        assert not sv.gram_applies_operator
+        assert sv.gram_kind == "recurrence"
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))
@@ -59,16 +66,19 @@ def test_lockstep_matches_stored_ap_and_oracle(hip, name, s):
     bt = t64(b)
     x = np.zeros(pr.n)
     op = make_operator(hip, pr, "stencil")
-    with hip.Solver(op, s, nu, pr.lmin, pr.lmax) as fused, \
-            hip.Solver(op, s, nu, pr.lmin, pr.lmax, gram="stored") as stored:
+    with hip.Solver(op, s, nu, pr.lmin, pr.lmax, gram="apply") as fused, \
+            hip.Solver(op, s, nu, pr.lmin, pr.lmax, gram="stored") as stored, \
+            hip.Solver(op, s, nu, pr.lmin, pr.lmax, gram="recurrence") as recur:
         assert fused.gram_applies_operator and not stored.gram_applies_operator
         for k in range(3):
             gf = fused.step(bt, t64(x), want_basis=(k == 0))
             gs = stored.step(bt, t64(x), want_basis=(k == 0))
+            gr = recur.step(bt, t64(x))
             o = oracle.step(A, b, x, s, nu, pr.lmin, pr.lmax, want_basis=(k == 0))
             assert o["status"] == 0
             for key in ("G", "ctil", "atil"):
                 assert rel(gf[key], gs[key]) <= 1e-12, (k, key, rel(gf[key], gs[key]))
+                assert rel(gr[key], gs[key]) <= 1e-12, (k, key, rel(gr[key], gs[key]))
                 assert rel(gf[key], o[key]) <= 1e-10, (k, key, rel(gf[key], o[key]))
             xf = host(gf["x"])
             assert rel(xf, host(gs["x"])) <= 1e-12, k
@@ -87,7 +97,7 @@ def test_grid_strided_blocks_match_oracle(hip):
     pr = gen.small_poisson3d(512, 520, 2, seed=7)
     s, nu = 16, 25
     A, b = oracle_rhs(pr)
-    with hip.Solver(make_operator(hip, pr, "stencil"), s, nu, pr.lmin, pr.lmax, autotune=False) as sv:
+    with hip.Solver(make_operator(hip, pr, "stencil"), s, nu, pr.lmin, pr.lmax, autotune=False, gram="apply") as sv:
         assert sv.gram_applies_operator
         g = sv.step(t64(b), t64(np.zeros(pr.n)))
     o = oracle.step(A, b, np.zeros(pr.n), s, nu, pr.lmin, pr.lmax)
@@ -105,7 +115,7 @@ def test_ragged_tiles_with_multiplane_ranges(hip, faces):
     s, nu = 16, 25
     A, b = oracle_rhs(pr)
     x = np.zeros(pr.n)
-    with hip.Solver(make_operator(hip, pr, "stencil"), s, nu, pr.lmin, pr.lmax, autotune=False) as sv:
+    with hip.Solver(make_operator(hip, pr, "stencil"), s, nu, pr.lmin, pr.lmax, autotune=False, gram="apply") as sv:
         assert sv.gram_applies_operator
         for k in range(2):
             g = sv.step(t64(b), t64(x))

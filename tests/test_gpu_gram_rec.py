@@ -38,6 +38,12 @@ CASES = {
     "poisson27_s20": (lambda: gen.small_poisson27(19, 21, 9, seed=2), "stencil", 20, 30, {}),
     "poisson_s1": (lambda: gen.small_poisson3d(9, 8, 7, seed=5), "stencil", 1, 3, {}),
     "poisson_s31": (lambda: gen.small_poisson3d(20, 18, 16, seed=4), "stencil", 31, 30, {}),
+    # widths at the kernel's column-block boundaries: 16 basis columns (s = 15),
+    # 17 (s = 16, one column beside the matrix-core block), 18 (s = 17, the
+    # second block's first width), 25 (s = 24) with a varying diagonal on CSR
+    "poisson_s15": (lambda: gen.small_poisson3d(13, 11, 9, seed=12), "stencil", 15, 20, {}),
+    "faces_stencil_s17": (lambda: gen.small_faces3d(17, 13, 11, seed=13, sigma=1.0), "stencil", 17, 25, {}),
+    "faces_csr_s24": (lambda: gen.small_faces3d(14, 15, 9, seed=14, sigma=0.5), "csr", 24, 30, {}),
     "faces_no_precond": (lambda: gen.small_faces3d(15, 13, 11, seed=7, sigma=0.5), "stencil", 6, 20,
                          {"precond": False}),
     "faces_p0_mode1": (lambda: gen.small_faces3d(15, 13, 11, seed=8, sigma=1.0), "stencil", 8, 20, {"p0_mode": 1}),

@@ -58,14 +58,14 @@ def reference(hip, pr, form, s, nu, b):
 
 PAIRS = {
     # (first problem, second smaller problem), operator form, s, nu
-    "poisson7_apply_op": ((lambda: gen.small_poisson3d(48, 40, 36, seed=1),
+    "poisson7_s16": ((lambda: gen.small_poisson3d(48, 40, 36, seed=1),
                            lambda: gen.small_poisson3d(21, 17, 13, seed=2)), "stencil", 16, 25),
-    "faces7_apply_op": ((lambda: gen.small_faces3d(40, 33, 30, seed=3, sigma=1.0),
+    "faces7_s8": ((lambda: gen.small_faces3d(40, 33, 30, seed=3, sigma=1.0),
                          lambda: gen.small_faces3d(17, 11, 9, seed=4, sigma=0.5)), "stencil", 8, 25),
-    "csr2d_stored_ap": ((lambda: gen.config1(0),
+    "csr2d_s8": ((lambda: gen.config1(0),
                          lambda: gen.Problem("p2d", "csr", (20, 13), 8, 20, *gen.jacobi_poisson_bounds(20, 13),
                                              xstar=gen.uniform(gen.rng(5), 260))), "csr", 8, 20),
-    "poisson27_stored_ap": ((lambda: gen.small_poisson27(30, 28, 26, seed=6),
+    "poisson27_s20": ((lambda: gen.small_poisson27(30, 28, 26, seed=6),
                              lambda: gen.small_poisson27(9, 8, 7, seed=7)), "stencil", 20, 30),
 }
 
