@@ -42,27 +42,41 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stencil_bytes_per_outer(n: int, s: int, w: int, kind: str = "stored") -> float:
-    """Bytes an outer iteration must move, constant-coefficient stencil, by
-    Gram kind.  stored: residual 16 + w, basis w(4s - 3) (AP written), Gram
-    2sw (P and AP), update sw + 16.  apply (the Gram kernel forms A p_j
-    itself): the s - 1 basis launches move w(3s - 4), the Gram reads P (sw).
-    recurrence: the s basis launches move w(3s - 1) (the last one writes
-    p_s), the Gram reads the s + 1 columns."""
+def basis_vectors(s: int, kind: str = "stored", pairs: int = 0) -> int:
+    """Vectors one basis moves per unknown, each read or write of a column
+    counted once.  Single steps: the first reads p_0 and writes p_1 (2), each
+    later one reads p_j, p_{j-1} and writes p_{j+1} (3); the apply kind takes
+    s - 1 steps (3s - 4), the recurrence kind s (3s - 1); with AP stored every
+    launch also writes A p_j and the last writes only that (4s - 3).  Two
+    steps per launch (pairs > 0): the first pair reads p_0 and writes p_1, p_2
+    (3), each later pair reads two columns and writes two (4), and an odd
+    column count ends with one single step (3)."""
+    m = s - 1 if kind == "apply" else s
+    if pairs > 0:
+        return 3 + 4 * (pairs - 1) + 3 * (m - 2 * pairs)
     if kind == "apply":
-        return float(n) * (32 + w * (1 + max(0, 3 * s - 4) + 2 * s))
+        return 3 * s - 4
     if kind == "recurrence":
-        return float(n) * (32 + w * (5 * s + 1))
-    return float(n) * (32 + w * (7 * s - 2))
+        return 3 * s - 1
+    return 4 * s - 3
 
 
-def csr_bytes_per_outer(n: int, nnz: int, s: int, w: int, kind: str = "stored") -> float:
+def stencil_bytes_per_outer(n: int, s: int, w: int, kind: str = "stored", pairs: int = 0) -> float:
+    """Bytes an outer iteration must move, constant-coefficient stencil:
+    residual 16 + w (x, b read in FP64, p_0 written), the basis (above), the
+    Gram reading its columns (stored: P and AP, 2s; apply: P, s; recurrence:
+    p_0 .. p_s, s + 1), the update sw + 16 (P read, x read and written)."""
+    gram_cols = {"stored": 2 * s, "apply": s, "recurrence": s + 1}[kind]
+    return float(n) * (32 + w * (1 + basis_vectors(s, kind, pairs) + gram_cols + s))
+
+
+def csr_bytes_per_outer(n: int, nnz: int, s: int, w: int, kind: str = "stored", pairs: int = 0) -> float:
     """The stencil figure plus the matrix (values and column indices, row
     pointers) read by s basis SpMVs in precision w and one FP64 residual SpMV,
     and the M-diagonal read by the Gram right-hand side."""
     mat_w = float(nnz) * (4 + w) + 4.0 * (n + 1)
     mat_64 = float(nnz) * 12 + 4.0 * (n + 1)
-    return stencil_bytes_per_outer(n, s, w, kind) + s * mat_w + mat_64 + float(n) * w
+    return stencil_bytes_per_outer(n, s, w, kind, pairs) + s * mat_w + mat_64 + float(n) * w
 
 
 def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, kind: str = "stored") -> float:
@@ -73,16 +87,13 @@ def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, kind: str = "st
     return nrhs * (stencil_bytes_per_outer(n, s, w, kind) + float(n) * w) + float(n) * 3 * (8 + s * w)
 
 
-def basis_bytes_per_launch(n: int, s: int, w: int, kind: str = "stored") -> float:
-    """Average algorithmic bytes of one basis launch: the s launches of an
-    outer iteration move w(4s - 3) bytes per unknown in total with AP stored;
-    the s - 1 launches of the apply kind move w(3s - 4); the s launches of the
-    recurrence kind w(3s - 1)."""
-    if kind == "apply":
-        return float(n) * w * (3 * s - 4) / (s - 1)
-    if kind == "recurrence":
-        return float(n) * w * (3 * s - 1) / s
-    return float(n) * w * (4 * s - 3) / s
+def basis_bytes_per_launch(n: int, s: int, w: int, kind: str = "stored", pairs: int = 0,
+                           launches: int = 0) -> float:
+    """Average algorithmic bytes of one basis launch: basis_vectors over the
+    launches of one basis (s, or s - 1 for the apply kind, with single steps)."""
+    if launches <= 0:
+        launches = s - 1 if kind == "apply" else s
+    return float(n) * w * basis_vectors(s, kind, pairs) / launches
 
 
 def measured_traffic(N: int, s: int, nu: int):
@@ -218,7 +229,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
 
             leg.run = run
             leg.bytes_per_outer = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4,
-                                                          leg.solver.gram_kind)
+                                                          leg.solver.gram_kind, leg.solver.basis_pairs)
             leg.n = pr.n
             out[name] = leg
         if "c2_csr_fp64" in legs:
@@ -234,7 +245,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
                 return st.outer_iters
 
             leg.run = run
-            leg.bytes_per_outer = csr_bytes_per_outer(pr.n, ci.size, s, 8, leg.solver.gram_kind)
+            leg.bytes_per_outer = csr_bytes_per_outer(pr.n, ci.size, s, 8, leg.solver.gram_kind, leg.solver.basis_pairs)
             leg.n = pr.n
             out["c2_csr_fp64"] = leg
         log("c2 legs ready")
@@ -458,13 +469,20 @@ def main():
             results["c2_fp32ir"]["kernel_ms"] = legs["c2_fp32ir"].solver.kernel_times(
                 main_leg.b, torch.zeros_like(main_leg.b), reps=args.kernel_reps)
         kind = main_leg.solver.gram_kind
-        per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8, kind)
+        sv0 = main_leg.solver
+        per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8, kind, sv0.basis_pairs, sv0.basis_launches)
         achieved = per_launch / (kt["basis"] * 1e-3) / 1e9
+        if sv0.basis_pairs:
+            kname = (f"k_basis_f2 (7-point stencil + Jacobi + two Chebyshev steps per launch, FP64), average of the "
+                     f"{sv0.basis_launches} basis launches ({sv0.basis_pairs} pairs"
+                     + (", one single step" if sv0.basis_launches > sv0.basis_pairs else "") + ")")
+        else:
+            kname = ("k_basis_p2 (7-point stencil + Jacobi + Chebyshev step, FP64), average of the "
+                     + {"apply": "s - 1 launches (AP not written)", "recurrence": "s launches (the last writes p_s)",
+                        "stored": "s launches (AP written)"}[kind])
         out["roofline"] = {
             "bound": "hbm",
-            "kernel": "k_basis_p2 (7-point stencil + Jacobi + Chebyshev step, FP64), average of the "
-                      + {"apply": "s - 1 launches (AP not written)", "recurrence": "s launches (the last writes p_s)",
-                         "stored": "s launches (AP written)"}[kind],
+            "kernel": kname,
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -473,6 +491,9 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 read requests by size + WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": per_launch,
             "avg_launch_ms": kt["basis"],
+            # the whole FP64 solve: algorithmic bytes of its outer iterations over its time
+            "solve_achieved": results["c2_fp64"].get("gbps_effective"),
+            "solve_frac": results["c2_fp64"].get("frac_of_hbm_peak"),
         }
         r = main_leg.b - main_leg.solver.apply(main_leg.x)
         results["c2_fp64"]["rel_res_true"] = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(main_leg.b))
@@ -546,7 +567,7 @@ def extra_c3(lib, torch, N):
                     b = sv.apply(torch.as_tensor(pr.xstar, device=dev))
                 x = torch.zeros_like(b)
                 t, st = _timed_solve(sv, b, x, 1e-8, torch)
-                bpo = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4, sv.gram_kind)
+                bpo = stencil_bytes_per_outer(pr.n, s, 8 if prec == "fp64" else 4, sv.gram_kind, sv.basis_pairs)
                 row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "status": st.status, "gram": sv.gram_kind,
                              "gbps_effective": bpo * st.outer_iters / (t * 1e-3) / 1e9}
                 x.zero_()
@@ -721,7 +742,7 @@ def sweep(lib, torch, args):
                         ts.append(1e3 * (time.perf_counter() - t0))
                     w = 8 if prec == "fp64" else 4
                     t = float(np.median(ts))
-                    bpo = stencil_bytes_per_outer(pr.n, s, w, sv.gram_kind)
+                    bpo = stencil_bytes_per_outer(pr.n, s, w, sv.gram_kind, sv.basis_pairs)
                     row[prec] = {"time_ms": t, "outer_iters": st.outer_iters, "rel_res": st.rel_res,
                                  "gram": sv.gram_kind,
                                  "gbps_effective": bpo * st.outer_iters / (t * 1e-3) / 1e9}

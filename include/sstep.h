@@ -257,13 +257,23 @@ enum { SSTEP_KT_RESIDUAL = 0, SSTEP_KT_BASIS = 1, SSTEP_KT_GRAM = 2, SSTEP_KT_FG
  * outer iteration (the same kernels, grids and arguments a solve uses),
  * measured with HIP events on the library stream over reps repetitions of
  * the class; the basis figure is the average over the launches of one basis
- * (s launches, or s - 1 with SSTEP_GRAM_APPLY_OP).  b is read; x is used as
- * scratch and overwritten. */
+ * (sstep_basis_launches of them).  b is read; x is used as scratch and
+ * overwritten. */
 sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int32_t reps, double *ms_out);
 
-/* The sstep_gram_kind a context uses (SSTEP_GRAM_STORED_AP or
- * SSTEP_GRAM_APPLY_OP), -1 for a NULL context. */
+/* The sstep_gram_kind a context uses (SSTEP_GRAM_STORED_AP,
+ * SSTEP_GRAM_APPLY_OP or SSTEP_GRAM_RECURRENCE), -1 for a NULL context. */
 int32_t sstep_gram_mode(const sstep_ctx *ctx);
+
+/* Kernel launches that form the basis p_1 .. p_m of one outer iteration of a
+ * context made by sstep_setup (Sec. 2, Definition; m = s - 1 with
+ * SSTEP_GRAM_APPLY_OP, else s).  For the constant 7-point operator with the
+ * Chebyshev basis and AP not stored, one launch forms two consecutive
+ * columns (p_{j+1} and p_{j+2} from p_{j-1} and p_j, exactly as two single
+ * steps would), and *pairs (if pairs is not NULL) receives how many launches
+ * do so; an odd m ends with a single step.  Otherwise every launch forms one
+ * column and *pairs is 0.  Returns -1 for a NULL or batched context. */
+int32_t sstep_basis_launches(const sstep_ctx *ctx, int32_t *pairs);
 
 /* Batched solves: nsys independent operators (each its own size), nrhs
  * right-hand sides per operator, one shared s and nu, per-system bounds

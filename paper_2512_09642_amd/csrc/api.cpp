@@ -363,10 +363,6 @@ void set_residual_schedule(IterArgs &it)
     }
 }
 
-// Basis launches per outer iteration: s, or s - 1 when the Gram kernel forms
-// the products itself (the last launch would only compute A p_{s-1}).
-int basis_launches(const IterArgs &a) { return a.gram_op ? a.s - 1 : a.s; }
-
 // Enqueues one outer iteration: residual + p_0, the basis steps, Gram
 // partials, FGS, update.
 hipError_t enqueue_iteration(const IterArgs &a, hipStream_t s)
@@ -374,9 +370,8 @@ hipError_t enqueue_iteration(const IterArgs &a, hipStream_t s)
     hipError_t e;
     if ((e = launch_residual(a, s, true)) != hipSuccess)
         return e;
-    for (int j = 0; j < basis_launches(a); ++j)
-        if ((e = launch_basis(a, j, s)) != hipSuccess)
-            return e;
+    if ((e = launch_basis_all(a, s)) != hipSuccess)
+        return e;
     if ((e = launch_gram(a, s)) != hipSuccess)
         return e;
     if ((e = launch_fgs(a, s)) != hipSuccess)
@@ -923,6 +918,17 @@ int32_t sstep_gram_mode(const sstep_ctx *ctx)
     return ctx->it.gram_rec ? SSTEP_GRAM_RECURRENCE : (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP);
 }
 
+int32_t sstep_basis_launches(const sstep_ctx *ctx, int32_t *pairs)
+{
+    if (!ctx || ctx->batch)
+        return -1;
+    int np = 0;
+    const int n = basis_kernel_count(ctx->it, &np);
+    if (pairs)
+        *pairs = np;
+    return n;
+}
+
 sstep_status sstep_solve(sstep_ctx *ctx, const double *b, double *x, double tol, sstep_stats *st)
 {
     return run_solve(ctx, b, x, tol, st);
@@ -1130,8 +1136,7 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
                 HIPCHK(ctx, launch_residual(it, s, true));
                 break;
             case SSTEP_KT_BASIS:
-                for (int j = 0; j < basis_launches(it); ++j)
-                    HIPCHK(ctx, launch_basis(it, j, s));
+                HIPCHK(ctx, launch_basis_all(it, s));
                 break;
             case SSTEP_KT_GRAM:
                 HIPCHK(ctx, launch_gram(it, s));
@@ -1147,7 +1152,7 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
         HIPCHK(ctx, hipEventSynchronize(ctx->ev_t1));
         float ms = 0.f;
         HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
-        const int per = cls == SSTEP_KT_BASIS ? basis_launches(it) : 1;
+        const int per = cls == SSTEP_KT_BASIS ? basis_kernel_count(it, nullptr) : 1;
         ms_out[cls] = per > 0 ? double(ms) / (double(reps) * per) : 0.0;
     }
     HIPCHK(ctx, hipStreamSynchronize(s));

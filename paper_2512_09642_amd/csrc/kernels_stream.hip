@@ -3,6 +3,7 @@
 // All of them are bound by HBM bandwidth (well under one flop per byte).
 #include <algorithm>
 
+#include "basis_f2.h"
 #include "launch.h"
 #include "opsel.h"
 #include "stop.h"
@@ -632,6 +633,75 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
     }
 }
 
+// Two basis steps per launch (basis_f2.h) for the constant 7-point operator,
+// shapes measured fastest on MI355X at 224^3: FP64 56-point tile rows
+// (64-byte aligned stores), 3 planes of loads in flight; FP32 62-point rows,
+// 6 planes.  Ranges of 28 planes give 2 blocks per CU in one wave there;
+// smaller grids take thinner ranges to keep some 512 blocks.
+constexpr int kF2Rows = 16;
+template <typename T>
+struct F2Shape;
+template <>
+struct F2Shape<double> {
+    static constexpr int D = 3, TXI = 56;
+};
+template <>
+struct F2Shape<float> {
+    static constexpr int D = 6, TXI = 62;
+};
+
+template <typename T>
+F2Plan f2_plan(const Grid3 &g)
+{
+    constexpr int TXI = F2Shape<T>::TXI;
+    const int64_t tiles = ((g.nx + TXI - 1) / TXI) * ((g.ny + kF2Rows - 3) / (kF2Rows - 2));
+    int kz = 28;
+    if (tiles * ((g.nz + kz - 1) / kz) < 512)
+        kz = static_cast<int>(std::max<int64_t>(4, std::min<int64_t>(28, g.nz * tiles / 512)));
+    return plan_f2<kF2Rows, TXI>(g, kz, 0);
+}
+
+template <typename T>
+bool f2_fits(const IterArgs &a)
+{
+    return f2_window_bytes(a.op.g, f2_plan<T>(a.op.g).kz, sizeof(T)) < (int64_t(1) << 31);
+}
+
+// The two-step kernel serves the Chebyshev basis of the constant 7-point
+// operator when AP is not stored (recurrence and operator-applying Gram kinds).
+bool basis_pairs_apply(const IterArgs &a)
+{
+    if (a.op.kind != kOpPoisson || a.AP || a.monomial)
+        return false;
+    return a.fp32 ? f2_fits<float>(a) : f2_fits<double>(a);
+}
+
+// Columns p_1 .. p_m a basis forms: m = s - 1 when the Gram kernel applies the
+// operator itself, else s (with AP stored, the last launch forms A p_{s-1}
+// only; the recurrence kind forms p_s).
+int basis_columns(const IterArgs &a) { return a.gram_op ? a.s - 1 : a.s; }
+
+template <typename T>
+hipError_t basis_pair(const IterArgs &a, int j, hipStream_t st)
+{
+    constexpr int D = F2Shape<T>::D, TXI = F2Shape<T>::TXI;
+    const F2Plan plan = f2_plan<T>(a.op.g);
+    T *P = static_cast<T *>(a.P);
+    const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
+    const T *pj = P + j * a.ld;
+    T *q = P + (j + 1) * a.ld, *p2 = P + (j + 2) * a.ld;
+    const T minv = a.op.precond ? T(1) / T(6) : T(1);
+    const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
+    const dim3 grid(plan.per * kNumXcd), block(kF2Lanes * kF2Rows);
+    if (j == 0)
+        hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, true, D, 8, TXI>), grid, block, 0, st, a.st, a.op.g, minv, pprev,
+                           pj, q, p2, theta, sigma, plan);
+    else
+        hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, false, D, 8, TXI>), grid, block, 0, st, a.st, a.op.g, minv,
+                           pprev, pj, q, p2, theta, sigma, plan);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_zero(uint64_t *__restrict__ p, int64_t words)
 {
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < words;
@@ -747,6 +817,36 @@ hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st)
     }
     const int step = last_product ? 2 : (j == 0 ? 0 : 1);
     return a.fp32 ? basis_t<float>(a, j, step, st) : basis_t<double>(a, j, step, st);
+}
+
+int basis_kernel_count(const IterArgs &a, int *pairs)
+{
+    const int m = basis_columns(a);
+    if (!basis_pairs_apply(a)) {
+        if (pairs)
+            *pairs = 0;
+        return a.gram_op ? a.s - 1 : a.s;
+    }
+    if (pairs)
+        *pairs = m / 2;
+    return m / 2 + m % 2;
+}
+
+hipError_t launch_basis_all(const IterArgs &a, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (!basis_pairs_apply(a)) {
+        for (int j = 0; j < basis_kernel_count(a, nullptr) && e == hipSuccess; ++j)
+            e = launch_basis(a, j, st);
+        return e;
+    }
+    const int m = basis_columns(a);
+    int j = 0;
+    for (; j + 2 <= m && e == hipSuccess; j += 2)
+        e = a.fp32 ? basis_pair<float>(a, j, st) : basis_pair<double>(a, j, st);
+    if (j < m && e == hipSuccess)
+        e = launch_basis(a, j, st);  // an odd count: the last column alone
+    return e;
 }
 
 hipError_t launch_product(const IterArgs &a, int j, hipStream_t st)

@@ -200,6 +200,12 @@ hipError_t launch_coarse_fgs(const CoarseArgs &c, const double *f, double *u, in
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);
+// The whole basis p_1 .. p_m of one outer iteration: two steps per launch
+// for the constant 7-point operator without stored AP, else one per launch.
+hipError_t launch_basis_all(const IterArgs &a, hipStream_t st);
+// Launches launch_basis_all makes, and (if pairs is not NULL) how many of
+// them form two columns.
+int basis_kernel_count(const IterArgs &a, int *pairs);
 // AP[:, j] = A p_j alone (into a.AP, which must be set).
 hipError_t launch_product(const IterArgs &a, int j, hipStream_t st);
 hipError_t launch_gram(const IterArgs &a, hipStream_t st);

@@ -166,6 +166,10 @@ class Solver:
         self.gram_applies_operator = bool(self._lib.sstep_gram_mode(ctx) == N.GRAM_KINDS["apply"])
         # "stored", "apply" or "recurrence": how this context forms G = P^T A P
         self.gram_kind = {v: k for k, v in N.GRAM_KINDS.items()}[int(self._lib.sstep_gram_mode(ctx))]
+        pairs = C.c_int32(0)
+        #: kernel launches per basis and how many of them form two columns
+        self.basis_launches = int(self._lib.sstep_basis_launches(ctx, C.byref(pairs)))
+        self.basis_pairs = int(pairs.value)
 
     def _stream_ptr(self):
         if self._stream is not None:

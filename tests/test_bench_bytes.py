@@ -1,0 +1,53 @@
+"""The benchmark's algorithmic byte counts, pinned to counts made by hand
+from the kernels' reads and writes (every column read or written once per
+launch; FP64 w = 8, FP32 w = 4).  These figures are the numerators of every
+bandwidth the benchmark reports, including the roofline's."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import bench  # noqa: E402
+
+
+def test_basis_vectors_single_steps():
+    # s = 4, stored AP: p1 <- p0 (r1 w2: p1, Ap0), p2 <- p1, p0 (r2 w2),
+    # p3 <- p2, p1 (r2 w2), Ap3 <- p3 (r1 w1): 3 + 4 + 4 + 2 = 13 = 4s - 3
+    assert bench.basis_vectors(4, "stored") == 13
+    # apply kind, s = 4: p1 (2), p2 (3), p3 (3) = 8 = 3s - 4
+    assert bench.basis_vectors(4, "apply") == 8
+    # recurrence kind, s = 4: p1 (2), p2, p3, p4 (3 each) = 11 = 3s - 1
+    assert bench.basis_vectors(4, "recurrence") == 11
+
+
+def test_basis_vectors_pairs():
+    # recurrence, s = 16: (p1, p2) <- p0 (3), seven pairs (4 each) = 31
+    assert bench.basis_vectors(16, "recurrence", pairs=8) == 31
+    # apply, s = 16: 15 columns = seven pairs (3 + 6 * 4) + one single step (3)
+    assert bench.basis_vectors(16, "apply", pairs=7) == 30
+    # recurrence, s = 7: three pairs (3 + 4 + 4) + one single step (3)
+    assert bench.basis_vectors(7, "recurrence", pairs=3) == 14
+    # s = 2: the first pair only
+    assert bench.basis_vectors(2, "recurrence", pairs=1) == 3
+
+
+@pytest.mark.parametrize("kind,pairs,expect", [
+    # 32 = x read by the residual (8), b (8), x read and written by the update (16)
+    ("stored", 0, 32 + 8 * (1 + 61 + 32 + 16)),
+    ("apply", 0, 32 + 8 * (1 + 44 + 16 + 16)),
+    ("recurrence", 0, 32 + 8 * (1 + 47 + 17 + 16)),
+    ("recurrence", 8, 32 + 8 * (1 + 31 + 17 + 16)),
+    ("apply", 7, 32 + 8 * (1 + 30 + 16 + 16)),
+])
+def test_stencil_bytes_per_outer(kind, pairs, expect):
+    assert bench.stencil_bytes_per_outer(1, 16, 8, kind, pairs) == expect
+
+
+def test_basis_bytes_per_launch():
+    n = 224 ** 3
+    # the headline basis: 8 pair launches moving 31 vectors of n doubles
+    assert bench.basis_bytes_per_launch(n, 16, 8, "recurrence", pairs=8, launches=8) == n * 8 * 31 / 8
+    # single steps of the recurrence kind: 16 launches, 47 vectors
+    assert bench.basis_bytes_per_launch(n, 16, 8, "recurrence") == n * 8 * 47 / 16
