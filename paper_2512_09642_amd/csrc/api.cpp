@@ -219,6 +219,47 @@ sstep_status check_csr_pattern(sstep_ctx *ctx, const sstep_operator *A)
     return SSTEP_OK;
 }
 
+// The sliced ELL copy of a CSR pattern (OpEll): slice widths from the
+// (validated) row pointers, slice offsets uploaded, columns filled on the
+// device; the values are filled by load_coefficients.
+sstep_status setup_ell(sstep_ctx *ctx, const sstep_operator *A)
+{
+    OpDev &op = ctx->it.op;
+    hipError_t e = hipSuccess;
+    const std::vector<int32_t> rp = to_host(A->row_ptr, size_t(A->n + 1), A->ptr_space, &e);
+    if (e != hipSuccess)
+        return hip_fail(ctx, "hipMemcpy(row_ptr)", e);
+    const int64_t nslice = (op.n + kEllSlice - 1) / kEllSlice;
+    std::vector<int64_t> off(size_t(nslice) + 1, 0);
+    for (int64_t q = 0; q < nslice; ++q) {
+        int32_t w = 0;
+        for (int64_t r = q * kEllSlice; r < std::min<int64_t>(op.n, (q + 1) * kEllSlice); ++r)
+            w = std::max(w, rp[size_t(r) + 1] - rp[size_t(r)]);
+        off[size_t(q) + 1] = off[size_t(q)] + int64_t(w) * kEllSlice;
+    }
+    const size_t total = size_t(off[size_t(nslice)]);
+    int64_t *doff = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    OKCHK(dalloc(ctx, &doff, size_t(nslice) + 1));
+    OKCHK(dalloc(ctx, &col, total));
+    OKCHK(dalloc(ctx, &val, total));
+    HIPCHK(ctx, hipMemcpyAsync(doff, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    op.ell_off = doff;
+    op.ell_nslice = nslice;
+    op.ell_col = col;
+    op.ell_val = val;
+    HIPCHK(ctx, launch_ell_fill_col(op, col, ctx->stream));
+    if (ctx->it.fp32) {
+        float *val32 = nullptr;
+        OKCHK(dalloc(ctx, &val32, total));
+        op.ell_val32 = val32;
+    }
+    // off must stay alive until the copy has run
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return SSTEP_OK;
+}
+
 // Loads (or reloads) the operator's coefficients and everything derived from
 // them: M diagonal, its inverse, FP32 copies.
 sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool first)
@@ -247,6 +288,8 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
         }
         HIPCHK(ctx, launch_diag_from_csr(op, dvec, bad, s));
         HIPCHK(ctx, launch_invert(dvec, invd, op.n, op.precond, s));
+        if (op.ell_col)
+            HIPCHK(ctx, launch_ell_fill_val(op, op.val, const_cast<double *>(op.ell_val), s));
         if (fp32) {
             float *val32 = const_cast<float *>(op.val32), *invd32 = const_cast<float *>(op.invd32);
             float *dvec32 = const_cast<float *>(op.dvec32);
@@ -262,6 +305,8 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
             HIPCHK(ctx, launch_to_fp32(val, val32, op.nnz, s));
             HIPCHK(ctx, launch_to_fp32(invd, invd32, op.n, s));
             HIPCHK(ctx, launch_to_fp32(dvec, dvec32, op.n, s));
+            if (op.ell_val32)
+                HIPCHK(ctx, launch_ell_fill_val(op, op.val32, const_cast<float *>(op.ell_val32), s));
         }
     } else if (op.kind == kOpFaces) {
         const int64_t nfx = faces_x(A), nfy = faces_y(A), nfz = faces_z(A);
@@ -795,6 +840,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         op.rp = rp;
         op.ci = ci;
         ctx->grad_size = A->nnz;
+        OKCHK(setup_ell(ctx, A));
     }
     it.ld = round_up(op.n, kPad);
     OKCHK(load_coefficients(ctx, A, true));

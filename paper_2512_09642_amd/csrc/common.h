@@ -212,4 +212,59 @@ struct OpCsr {
     }
 };
 
+// The same CSR operator stored as sliced ELL: rows in slices of kEllSlice
+// consecutive rows; slice q holds w_q = (off[q+1] - off[q]) / kEllSlice
+// entries per row (the longest row of the slice), column-major inside the
+// slice, so entry k of row r = q kEllSlice + l sits at off[q] + k kEllSlice +
+// l and the lanes of a wave that takes one slice read each entry index with
+// one coalesced load.  A row keeps its CSR entries in their order; the
+// padding has column -1 and is skipped, so the sum is formed with the same
+// operations in the same order as by OpCsr.
+constexpr int kEllSlice = 64;
+//
+// In FP64 the Jacobi weight is formed from the row's own diagonal entry,
+// precond ? 1 / a_cc : 1 (the value the M^{-1} vector holds, to the bit),
+// which saves reading that vector; FP32 reads its rounded copy.
+template <typename T>
+struct OpEll {
+    const int32_t *__restrict__ col;
+    const T *__restrict__ val;
+    const int64_t *__restrict__ off;
+    const T *__restrict__ invd;  // M^{-1} diagonal (all ones without preconditioning); FP32 only
+    int precond;
+
+    __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
+    {
+        const int64_t q = c / kEllSlice;
+        const int64_t o0 = off[q];
+        const int w = static_cast<int>((off[q + 1] - o0) / kEllSlice);
+        const int64_t b = o0 + (c - q * kEllSlice);
+        T acc = T(0), diag = T(1);
+        constexpr int U = 8;  // entries whose loads are issued together
+        for (int k0 = 0; k0 < w; k0 += U) {
+            int32_t j[U];
+            T v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < w) {  // read once per product: non-temporal
+                    j[u] = __builtin_nontemporal_load(col + b + int64_t(k0 + u) * kEllSlice);
+                    v[u] = __builtin_nontemporal_load(val + b + int64_t(k0 + u) * kEllSlice);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < w && j[u] >= 0) {
+                    acc += v[u] * p[j[u]];
+                    if (j[u] == c)
+                        diag = v[u];
+                }
+        }
+        pc = p[c];
+        y = acc;
+        if constexpr (sizeof(T) == 8)
+            dinv = precond ? T(1) / diag : T(1);
+        else
+            dinv = invd[c];
+    }
+};
+
 }  // namespace sstep

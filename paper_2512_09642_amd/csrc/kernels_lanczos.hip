@@ -257,6 +257,8 @@ hipError_t launch_lanczos(const LzArgs &l, const OpDev &op, const double *u, int
             e = apply_step(l, make_poisson27<double>(op), z, y, st);
         else if (op.kind == kOpFaces)
             e = apply_step(l, Ops<double>::faces(op), z, y, st);
+        else if (op.ell_col)
+            e = apply_step(l, Ops<double>::ell(op), z, y, st);
         else
             e = apply_step(l, Ops<double>::csr(op), z, y, st);
         if (e != hipSuccess)

@@ -537,6 +537,8 @@ hipError_t residual_t(const IterArgs &a, hipStream_t st, bool write_p0)
     case kOpPoisson27:
         return residual_for<OpPoisson27<double>, TP>(a, make_poisson27<double>(a.op), st, write_p0);
     default:
+        if (a.op.ell_col)
+            return residual_for<OpEll<double>, TP>(a, Ops<double>::ell(a.op), st, write_p0);
         return residual_for<OpCsr<double>, TP>(a, Ops<double>::csr(a.op), st, write_p0);
     }
 }
@@ -629,6 +631,8 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
     case kOpPoisson27:
         return basis_for<OpPoisson27<T>, T>(a, make_poisson27<T>(a.op), j, step, st);
     default:
+        if (a.op.ell_col)
+            return basis_for<OpEll<T>, T>(a, Ops<T>::ell(a.op), j, step, st);
         return basis_csr<T>(a, j, step, st);
     }
 }
@@ -702,6 +706,41 @@ hipError_t basis_pair(const IterArgs &a, int j, hipStream_t st)
     return hipGetLastError();
 }
 
+// Sliced ELL from CSR (OpEll, common.h): one thread per row slot of every
+// slice (rows at or beyond n are all padding).
+__global__ __launch_bounds__(kBlock) void k_ell_fill_col(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                        const int64_t *__restrict__ off, int64_t n, int64_t nslice,
+                                                        int32_t *__restrict__ col)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (r >= nslice * kEllSlice)
+        return;
+    const int64_t q = r / kEllSlice;
+    const int64_t b = off[q] + (r - q * kEllSlice);
+    const int w = static_cast<int>((off[q + 1] - off[q]) / kEllSlice);
+    const int32_t k0 = r < n ? rp[r] : 0;
+    const int len = r < n ? rp[r + 1] - k0 : 0;
+    for (int k = 0; k < w; ++k)
+        col[b + int64_t(k) * kEllSlice] = k < len ? ci[k0 + k] : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ell_fill_val(const int32_t *__restrict__ rp, const T *__restrict__ val,
+                                                        const int64_t *__restrict__ off, int64_t n, int64_t nslice,
+                                                        T *__restrict__ ev)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (r >= nslice * kEllSlice)
+        return;
+    const int64_t q = r / kEllSlice;
+    const int64_t b = off[q] + (r - q * kEllSlice);
+    const int w = static_cast<int>((off[q + 1] - off[q]) / kEllSlice);
+    const int32_t k0 = r < n ? rp[r] : 0;
+    const int len = r < n ? rp[r + 1] - k0 : 0;
+    for (int k = 0; k < w; ++k)
+        ev[b + int64_t(k) * kEllSlice] = k < len ? val[k0 + k] : T(0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_zero(uint64_t *__restrict__ p, int64_t words)
 {
     for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < words;
@@ -758,6 +797,30 @@ __global__ __launch_bounds__(kBlock) void k_check_csr_cols(const int32_t *__rest
 }
 
 }  // namespace
+
+hipError_t launch_ell_fill_col(const OpDev &op, int32_t *col, hipStream_t st)
+{
+    const uint32_t grid = blocks_for(op.ell_nslice * kEllSlice);
+    hipLaunchKernelGGL(k_ell_fill_col, dim3(grid), dim3(kBlock), 0, st, op.rp, op.ci, op.ell_off, op.n,
+                       op.ell_nslice, col);
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_fill_val(const OpDev &op, const double *val, double *ev, hipStream_t st)
+{
+    const uint32_t grid = blocks_for(op.ell_nslice * kEllSlice);
+    hipLaunchKernelGGL(k_ell_fill_val<double>, dim3(grid), dim3(kBlock), 0, st, op.rp, val, op.ell_off, op.n,
+                       op.ell_nslice, ev);
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_fill_val(const OpDev &op, const float *val, float *ev, hipStream_t st)
+{
+    const uint32_t grid = blocks_for(op.ell_nslice * kEllSlice);
+    hipLaunchKernelGGL(k_ell_fill_val<float>, dim3(grid), dim3(kBlock), 0, st, op.rp, val, op.ell_off, op.n,
+                       op.ell_nslice, ev);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st)
 {
@@ -883,8 +946,12 @@ hipError_t launch_apply(const OpDev &op, const double *x, double *y, hipStream_t
                            make_poisson27<double>(op), x, y, op.n, l.per, l.nbl);
         break;
     default:
-        hipLaunchKernelGGL(k_apply<OpCsr<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::csr(op), x, y,
-                           op.n, l.per, l.nbl);
+        if (op.ell_col)
+            hipLaunchKernelGGL(k_apply<OpEll<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::ell(op), x,
+                               y, op.n, l.per, l.nbl);
+        else
+            hipLaunchKernelGGL(k_apply<OpCsr<double>>, dim3(l.grid), dim3(kBlock), 0, st, Ops<double>::csr(op), x,
+                               y, op.n, l.per, l.nbl);
     }
     return hipGetLastError();
 }

@@ -41,6 +41,12 @@ struct OpDev {
     const float *invd32 = nullptr;
     const double *dvec = nullptr;  // M diagonal (Jacobi, non-constant diagonal)
     const float *dvec32 = nullptr;
+    // CSR also stored as sliced ELL (OpEll, common.h) when ell_col is set
+    const int32_t *ell_col = nullptr;
+    const double *ell_val = nullptr;
+    const float *ell_val32 = nullptr;
+    const int64_t *ell_off = nullptr;  // [nslice + 1]
+    int64_t ell_nslice = 0;
 };
 
 // Everything one outer iteration needs; all pointers are device memory.
@@ -200,6 +206,11 @@ hipError_t launch_coarse_fgs(const CoarseArgs &c, const double *f, double *u, in
 hipError_t launch_residual(const IterArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_p0scale(const IterArgs &a, hipStream_t st);
 hipError_t launch_basis(const IterArgs &a, int j, hipStream_t st);
+// Sliced ELL copy of a CSR operator: the columns (pattern) and the values in
+// FP64 or FP32 (from the CSR arrays rp, ci, val of the same precision).
+hipError_t launch_ell_fill_col(const OpDev &op, int32_t *col, hipStream_t st);
+hipError_t launch_ell_fill_val(const OpDev &op, const double *val, double *ev, hipStream_t st);
+hipError_t launch_ell_fill_val(const OpDev &op, const float *val, float *ev, hipStream_t st);
 // The whole basis p_1 .. p_m of one outer iteration: two steps per launch
 // for the constant 7-point operator without stored AP, else one per launch.
 hipError_t launch_basis_all(const IterArgs &a, hipStream_t st);

@@ -24,11 +24,13 @@ template <>
 struct Ops<double> {
     static OpFaces7<double> faces(const OpDev &op) { return {op.g, op.kx, op.ky, op.kz, op.precond}; }
     static OpCsr<double> csr(const OpDev &op) { return {op.rp, op.ci, op.val, op.invd}; }
+    static OpEll<double> ell(const OpDev &op) { return {op.ell_col, op.ell_val, op.ell_off, nullptr, op.precond}; }
 };
 template <>
 struct Ops<float> {
     static OpFaces7<float> faces(const OpDev &op) { return {op.g, op.kx32, op.ky32, op.kz32, op.precond}; }
     static OpCsr<float> csr(const OpDev &op) { return {op.rp, op.ci, op.val32, op.invd32}; }
+    static OpEll<float> ell(const OpDev &op) { return {op.ell_col, op.ell_val32, op.ell_off, op.invd32, op.precond}; }
 };
 
 }  // namespace sstep
