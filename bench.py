@@ -323,8 +323,10 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
         leg.run = run
         w = 8 if prec == "fp64" else 4
         sizes = [p.n for p in probs]
-        # per system: (bytes per right-hand side per outer iteration, face-array bytes shared by the rhs)
-        leg.pair_bytes = [(stencil_bytes_per_outer(nq, 16, w) + float(nq) * w, float(nq) * 3 * (8 + 16 * w))
+        # per system: (bytes per right-hand side per outer iteration, face-array bytes shared by the rhs),
+        # for the Gram kind the batched solver uses
+        kind = leg.solver.gram_kind
+        leg.pair_bytes = [(stencil_bytes_per_outer(nq, 16, w, kind) + float(nq) * w, float(nq) * 3 * (8 + 16 * w))
                           for nq in sizes]
         leg.bytes_per_outer = None
         leg.n = sum(sizes)
@@ -415,6 +417,8 @@ def main():
                 per_rhs, faces = leg.pair_bytes[q]
                 tot_bytes += per_rhs * sum(its) + faces * max(its)
             per_sys = [max(leg.pair_iters[q * 8:(q + 1) * 8]) for q in range(leg.nsys)]
+            g = tot_bytes / (t * 1e-3) / 1e9
+            r.update(frac_of_hbm_peak=g / HBM_PEAK_GBPS)
             r.update(outer_iters_min=min(leg.pair_iters), outer_iters_max=max(leg.pair_iters),
                      pairs=len(leg.pair_iters), unknown_rhs=leg.n * 8,
                      max_rel_res=max(leg.pair_relres), gbps_effective=tot_bytes / (t * 1e-3) / 1e9,
@@ -437,6 +441,8 @@ def main():
                 g = leg.bytes_per_outer * leg.iters / (t * 1e-3) / 1e9
                 r.update(gbps_effective=g, frac_of_hbm_peak=g / HBM_PEAK_GBPS,
                          algorithmic_bytes_per_outer=leg.bytes_per_outer)
+        if getattr(leg.solver, "gram_kind", None):
+            r["gram"] = leg.solver.gram_kind
         results[name] = r
 
     out = {

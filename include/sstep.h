@@ -129,8 +129,9 @@ typedef struct {
                                $SSTEP_TUNE_CACHE or ~/.cache/sstep/tune.json; systems under 2^20
                                unknowns use the defaults; 0 = defaults */
     int32_t gram;           /* sstep_gram_kind: how G = P^T A P (Sec. 2) is formed.  SSTEP_GRAM_AUTO
-                               (default) = SSTEP_GRAM_APPLY_OP for FP64 stencil operators with
-                               s <= 16 and n < 2^29, SSTEP_GRAM_STORED_AP otherwise */
+                               (default) = SSTEP_GRAM_RECURRENCE for s <= 31, SSTEP_GRAM_STORED_AP at
+                               s = 32.  Batched contexts take AUTO, RECURRENCE or STORED_AP
+                               (SSTEP_E_UNSUPPORTED for APPLY_OP) */
     int32_t basis;          /* 0 = Chebyshev basis (default, Sec. 2); 1 = monomial basis
                                p_{j+1} = M^{-1} A p_j of the same Krylov space, the comparison of
                                Sec. 4 (a diagnostic: its Gram matrix is badly conditioned; the
@@ -262,7 +263,8 @@ enum { SSTEP_KT_RESIDUAL = 0, SSTEP_KT_BASIS = 1, SSTEP_KT_GRAM = 2, SSTEP_KT_FG
 sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int32_t reps, double *ms_out);
 
 /* The sstep_gram_kind a context uses (SSTEP_GRAM_STORED_AP,
- * SSTEP_GRAM_APPLY_OP or SSTEP_GRAM_RECURRENCE), -1 for a NULL context. */
+ * SSTEP_GRAM_APPLY_OP or SSTEP_GRAM_RECURRENCE), batched contexts included;
+ * -1 for a NULL context. */
 int32_t sstep_gram_mode(const sstep_ctx *ctx);
 
 /* Kernel launches that form the basis p_1 .. p_m of one outer iteration of a

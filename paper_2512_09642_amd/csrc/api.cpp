@@ -961,6 +961,8 @@ int32_t sstep_gram_mode(const sstep_ctx *ctx)
 {
     if (!ctx)
         return -1;
+    if (ctx->batch)
+        return ctx->batch->ba.rec ? SSTEP_GRAM_RECURRENCE : SSTEP_GRAM_STORED_AP;
     return ctx->it.gram_rec ? SSTEP_GRAM_RECURRENCE : (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP);
 }
 
@@ -1211,7 +1213,7 @@ static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bo
         return fail(ctx, SSTEP_E_ARG, "batched tile schedule out of range");
     Batched &B = *ctx->batch;
     BatchArgs &a = B.ba;
-    const int E = gram_entries(a.s);
+    const int E = gram_entries(a.s + a.rec);
     std::vector<BTile> bt;
     std::vector<PTile> pt;
     std::vector<GTile> gt;
@@ -1276,7 +1278,7 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     for (int64_t v : B.n)
         h = (h ^ uint64_t(v)) * 1099511628211ull;
     key << kTuneSchema << " gfx950 batched s=" << a.s << " prec=" << (a.fp32 ? "fp32" : "fp64") << " nrhs=" << a.nrhs
-        << " nsys=" << a.nsys << " faces=" << a.faces << " sizes=" << std::hex << h;
+        << " nsys=" << a.nsys << " faces=" << a.faces << " rec=" << a.rec << " sizes=" << std::hex << h;
     const std::string path = tune_cache_path();
     std::map<std::string, GramSchedule> cache;
     if (!path.empty()) {
@@ -1340,6 +1342,12 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         return fail(ctx, SSTEP_E_ARG, "invalid options");
     if (o.basis != 0)
         return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves use the Chebyshev basis");
+    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_RECURRENCE)
+        return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
+    if (o.gram == SSTEP_GRAM_APPLY_OP)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves take the recurrence or the stored-AP Gram kind");
+    if (o.gram == SSTEP_GRAM_RECURRENCE && s > kRecMaxS)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "the recurrence Gram kind needs s <= 31");
     if (o.graph_chunk <= 0)
         o.graph_chunk = 4;
     for (int q = 0; q < nsys; ++q) {
@@ -1388,6 +1396,11 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     const bool jac_p0 = o.precond == 1 && o.p0_mode == 0;
     a.wdvec = jac_p0 && a.faces;
     a.cscale = (jac_p0 && !a.faces) ? 6.0 : 1.0;
+    // recurrence kind by default for s <= 31: H = P^T M P with M the face
+    // diagonals, or 6 I (constant Poisson with Jacobi), or I (no Jacobi)
+    a.rec = o.gram == SSTEP_GRAM_RECURRENCE || (o.gram == SSTEP_GRAM_AUTO && s <= kRecMaxS);
+    a.rec_wap = a.rec && o.precond == 1 && a.faces;
+    a.rec_hscale = (a.rec && o.precond == 1 && !a.faces) ? 6.0 : 1.0;
     OKCHK(dalloc(ctx, &ctx->bad_flag, 1));
     HIPCHK(ctx, hipMemsetAsync(ctx->bad_flag, 0, sizeof(int), ctx->stream));
     const size_t w = a.fp32 ? sizeof(float) : sizeof(double);
@@ -1404,7 +1417,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         S.n = S.g.nxy * Aq.nz;
         S.ld = round_up(S.n, kPad);
         S.pofs = pofs;
-        pofs += int64_t(s) * nrhs * S.ld;
+        pofs += int64_t(s + a.rec) * nrhs * S.ld;  // p_0 .. p_{s-1} (and p_s with the recurrence kind)
         S.theta = 2.0 / (lmax[q] - lmin[q]);
         S.sigma = (lmax[q] + lmin[q]) / 2.0;
         S.inv_sqrt_n = 1.0 / std::sqrt(double(S.n));
@@ -1449,9 +1462,11 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     {
         char *P = nullptr, *AP = nullptr;
         OKCHK(dalloc(ctx, &P, size_t(pofs) * w));
-        OKCHK(dalloc(ctx, &AP, size_t(pofs) * w));
         HIPCHK(ctx, hipMemsetAsync(P, 0, size_t(pofs) * w, ctx->stream));
-        HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(pofs) * w, ctx->stream));
+        if (!a.rec) {
+            OKCHK(dalloc(ctx, &AP, size_t(pofs) * w));
+            HIPCHK(ctx, hipMemsetAsync(AP, 0, size_t(pofs) * w, ctx->stream));
+        }
         a.P = P;
         a.AP = AP;
     }
@@ -1466,7 +1481,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     OKCHK(dalloc(ctx, &B.dpt, size_t(max_pt)));
     OKCHK(dalloc(ctx, &B.dgt, size_t(max_nch) * nrhs));
     OKCHK(dalloc(ctx, &a.rpart, size_t(max_nch) * nrhs));
-    OKCHK(dalloc(ctx, &a.gpart, size_t(max_nch) * nrhs * gram_entries(s)));
+    OKCHK(dalloc(ctx, &a.gpart, size_t(max_nch) * nrhs * gram_entries(s + a.rec)));
     OKCHK(dalloc(ctx, &a.pairs, size_t(a.npairs)));
     OKCHK(dalloc(ctx, &a.gl, 1));
     OKCHK(dalloc(ctx, &a.dbg, size_t(a.npairs) * dbg_size(s)));

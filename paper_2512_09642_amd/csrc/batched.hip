@@ -124,8 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_bp0scale(const BSys *__restrict__ sy
     pairs[p].p0scale = (rms > 0.0 && isfinite(rms)) ? ldexp(1.0, -ilogb(rms)) : 1.0;
 }
 
-// Basis step j for every active pair (Sec. 2, Definition): y = A p_j -> AP,
-// p_{j+1} from the three-term recurrence.
+// Basis step j for every active pair (Sec. 2, Definition): y = A p_j -> AP
+// (when AP is kept), p_{j+1} from the three-term recurrence.
 template <typename T, bool FACES, int STEP>
 __global__ __launch_bounds__(kBlock) void k_bbasis(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                    const PTile *__restrict__ tiles, int ntiles,
@@ -177,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_bbasis(const BGlob *__restrict__ gl,
                 if (!act[u])
                     continue;
                 const int64_t col = S.pofs + (static_cast<int64_t>(j) * nrhs + r0 + u) * S.ld;
-                __builtin_nontemporal_store(y[u], AP + col + c);
+                if (AP)  // not kept by the recurrence Gram kind
+                    __builtin_nontemporal_store(y[u], AP + col + c);
                 if constexpr (STEP == 0) {
                     P[col + step + c] = theta * (op.dinv * y[u] - sigma * pc[u]);
                 } else if constexpr (STEP == 1) {
@@ -271,7 +272,7 @@ template <typename T, bool FACES>
 hipError_t bbasis_t(const BatchArgs &a, int j, hipStream_t st)
 {
     T *P = static_cast<T *>(a.P), *AP = static_cast<T *>(a.AP);
-    if (j + 1 >= a.s)
+    if (j + 1 >= a.s && !a.rec)  // the last step forms A p_{s-1} only, unless p_s is kept
         hipLaunchKernelGGL((k_bbasis<T, FACES, 2>), dim3(a.grid_pt), dim3(kBlock), 0, st, a.gl, a.sys, a.ptiles,
                            a.npt, a.pairs, a.nrhs, a.precond, j, P, AP);
     else if (j == 0)

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "fgs_core.h"
+#include "gram_sym_impl.h"
 
 namespace sstep {
 
@@ -51,6 +52,56 @@ hipError_t bgram_launch_s(const BatchArgs &a, hipStream_t st)
     else
         hipLaunchKernelGGL((k_bgram<T, S, false>), dim3(a.grid_gt), block, 0, st, a.gl, a.sys, a.gtiles, a.ngt,
                            a.pairs, a.nrhs, P, AP, a.gpart);
+    return hipGetLastError();
+}
+
+// Recurrence Gram kind: tile (q, chunk, r) forms the partial of
+// H = P^T M P over p_0 .. p_s and of c' for rows [chunk*gchunk,
+// (chunk+1)*gchunk) of pair (q, r) on the matrix cores (gram_sym_rows), into
+// gpart[gofs + r*E1*nch + e*nch + chunk].
+template <typename T, int S1, bool WAP, bool WD>
+__global__ __launch_bounds__(kGsThreads) void k_bgram_sym(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
+                                                           const GTile *__restrict__ tiles, int ntiles,
+                                                           const DevState *__restrict__ pairs, int nrhs,
+                                                           const T *__restrict__ P, double *__restrict__ gpart)
+{
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    if (gl->ndone == gl->npairs)
+        return;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const GTile tl = tiles[t];
+        const BSys &Q = sys[tl.q];
+        if (pairs[Q.pair0 + tl.r].done)
+            continue;  // the whole block: gram_sym_rows has barriers
+        const int64_t off = Q.pofs + static_cast<int64_t>(tl.r) * Q.ld;
+        const int64_t cs = static_cast<int64_t>(nrhs) * Q.ld;
+        const int64_t beg = static_cast<int64_t>(tl.chunk) * Q.gchunk;
+        const int64_t end = beg + Q.gchunk < Q.ld ? beg + Q.gchunk : Q.ld;
+        const T *dv = reinterpret_cast<const T *>(sizeof(T) == 8 ? static_cast<const void *>(Q.dvec)
+                                                                 : static_cast<const void *>(Q.dvec32));
+        gram_sym_rows<T, S1, WAP, WD>(P + off, cs, dv, beg, end,
+                                      gpart + Q.gofs + static_cast<int64_t>(tl.r) * E1 * Q.nch, Q.nch, tl.chunk);
+    }
+}
+
+template <typename T, int S>
+hipError_t bgram_sym_launch_s(const BatchArgs &a, hipStream_t st)
+{
+    constexpr int S1 = S + 1;
+    const T *P = static_cast<const T *>(a.P);
+    const dim3 grid(a.grid_gt), block(kGsThreads);
+    if (a.rec_wap && a.wdvec)
+        hipLaunchKernelGGL((k_bgram_sym<T, S1, true, true>), grid, block, 0, st, a.gl, a.sys, a.gtiles, a.ngt, a.pairs,
+                           a.nrhs, P, a.gpart);
+    else if (a.rec_wap)
+        hipLaunchKernelGGL((k_bgram_sym<T, S1, true, false>), grid, block, 0, st, a.gl, a.sys, a.gtiles, a.ngt,
+                           a.pairs, a.nrhs, P, a.gpart);
+    else if (a.wdvec)
+        hipLaunchKernelGGL((k_bgram_sym<T, S1, false, true>), grid, block, 0, st, a.gl, a.sys, a.gtiles, a.ngt,
+                           a.pairs, a.nrhs, P, a.gpart);
+    else
+        hipLaunchKernelGGL((k_bgram_sym<T, S1, false, false>), grid, block, 0, st, a.gl, a.sys, a.gtiles, a.ngt,
+                           a.pairs, a.nrhs, P, a.gpart);
     return hipGetLastError();
 }
 
@@ -111,6 +162,84 @@ hipError_t bfgs_launch_s(const BatchArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfgs<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs, a.rpart,
                        a.gpart, a.nu, a.cscale, a.fp32, a.dbg);
+    return hipGetLastError();
+}
+
+// Recurrence Gram kind: the pair's sums of H and c', the stopping test, then
+// H mapped onto G_raw = P^T A P with the system's theta, sigma (as k_fgs_rec
+// does) and the FGS wave.
+template <int S>
+__global__ __launch_bounds__(kBFgsThreads) void k_bfgs_rec(BGlob *__restrict__ gl, const BSys *__restrict__ sys,
+                                                           DevState *__restrict__ pairs, int nrhs,
+                                                           const double *__restrict__ rpart,
+                                                           const double *__restrict__ gpart, int nu, double cscale,
+                                                           int fp32, double hscale, double *__restrict__ dbg)
+{
+    constexpr int S1 = S + 1;
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    constexpr int T0 = S * (S + 1) / 2;
+    const int p = blockIdx.x;
+    DevState *ps = pairs + p;
+    if (ps->done)
+        return;
+    const BSys &Q = sys[p / nrhs];
+    const int r = p % nrhs;
+    __shared__ double h[E1 + 1];
+    __shared__ double sg[T0 + S];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const double *gp = gpart + Q.gofs + static_cast<int64_t>(r) * E1 * Q.nch;
+    const double *rp = rpart + Q.rofs + static_cast<int64_t>(r) * Q.nch;
+    for (int t = wave; t <= E1; t += kBFgsThreads / kWave) {
+        const double *src = t < E1 ? gp + static_cast<int64_t>(t) * Q.nch : rp;
+        double a0 = 0.0, a1 = 0.0;
+        int q = lane;
+        for (; q + kWave < Q.nch; q += 2 * kWave) {
+            a0 += src[q];
+            a1 += src[q + kWave];
+        }
+        for (; q < Q.nch; q += kWave)
+            a0 += src[q];
+        const double acc = wave_sum(a0 + a1);
+        if (lane == 0)
+            h[t] = acc;
+    }
+    __shared__ int stopped;
+    __syncthreads();
+    double *pdbg = dbg + static_cast<int64_t>(p) * dbg_size(S);
+    if (threadIdx.x == 0)
+        stopped = stop_test(ps, h[E1], pdbg + dbg_rho(S), nullptr, 0);
+    __syncthreads();
+    if (stopped) {
+        if (threadIdx.x == 0)
+            atomicAdd(&gl->ndone, 1);
+        return;
+    }
+    const double theta = Q.theta, sigma = Q.sigma;
+    auto H = [&](int a, int b) { return a >= b ? h[tri_index(a, b)] : h[tri_index(b, a)]; };
+    for (int e = threadIdx.x; e < T0; e += kBFgsThreads) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= e)
+            ++i;
+        const int j = e - i * (i + 1) / 2;
+        const double g = j == 0 ? H(i, 1) / theta + sigma * H(i, 0)
+                                : (H(i, j + 1) + H(i, j - 1)) / (2.0 * theta) + sigma * H(i, j);
+        sg[e] = hscale * g;
+    }
+    for (int i = threadIdx.x; i < S; i += kBFgsThreads)
+        sg[T0 + i] = h[S1 * (S1 + 1) / 2 + i];
+    __syncthreads();
+    if (wave != 0)
+        return;
+    const int now = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, pdbg, nullptr, 0);
+    if (now && lane == 0)
+        atomicAdd(&gl->ndone, 1);
+}
+
+template <int S>
+hipError_t bfgs_rec_launch_s(const BatchArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bfgs_rec<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs,
+                       a.rpart, a.gpart, a.nu, a.cscale, a.fp32, a.rec_hscale, a.dbg);
     return hipGetLastError();
 }
 

@@ -23,5 +23,9 @@ template <typename T, int S>
 hipError_t bgram_launch_s(const BatchArgs &a, hipStream_t st);
 template <int S>
 hipError_t bfgs_launch_s(const BatchArgs &a, hipStream_t st);
+template <typename T, int S>
+hipError_t bgram_sym_launch_s(const BatchArgs &a, hipStream_t st);
+template <int S>
+hipError_t bfgs_rec_launch_s(const BatchArgs &a, hipStream_t st);
 
 }  // namespace sstep

@@ -57,10 +57,15 @@ __device__ __forceinline__ Vec4<T> ld4(const T *p)
 // matrix-core products per step, H[B][A] and H[B][B].  WAP: weight the second
 // operand by the M diagonal array (non-constant diagonal); WD: the
 // right-hand side uses W = M p_0.
+//
+// One block's share: rows [beg, end) of the columns P + j cs (j = 0..S1-1,
+// 16-byte aligned, rows multiples of 4, zero past the system), the block's
+// partial of entry e written to out[e * estride + slot].  Ends with a
+// barrier, so a block may call it again for another range.
 template <typename T, int S1, bool WAP, bool WD>
-__global__ __launch_bounds__(kGsThreads) void k_gram_sym(const DevState *__restrict__ st, const T *__restrict__ P,
-                                                          int64_t ld, const T *__restrict__ dvec, int64_t chunk,
-                                                          double *__restrict__ gpart, int estride)
+__device__ __forceinline__ void gram_sym_rows(const T *__restrict__ P, int64_t cs, const T *__restrict__ dvec,
+                                              int64_t beg, int64_t end, double *__restrict__ out, int64_t estride,
+                                              int64_t slot)
 {
     static_assert(S1 >= 2 && S1 <= 32, "recurrence Gram: s + 1 <= 32 columns");
     constexpr int SM = S1 < 16 ? S1 : 16;  // columns of block A
@@ -71,16 +76,12 @@ __global__ __launch_bounds__(kGsThreads) void k_gram_sym(const DevState *__restr
     constexpr int T0 = S1 * (S1 + 1) / 2;
     using M = GoMfma<T>;
     __shared__ double red[kGsThreads / kWave][E];
-    if (st->done)
-        return;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
     const int c = lane & 15, gq = lane >> 4;
     const bool ccol = c < SM, bcol = c < SB;
-    const T *colp = P + static_cast<int64_t>(ccol ? c : 0) * ld;
-    const T *colb = P + static_cast<int64_t>(16 + (bcol ? c : 0)) * ld;  // dereferenced only for S1 >= 18
-    const T *xcol = P + 16 * ld;                                         // dereferenced only for S1 == 17
-    const int64_t beg = static_cast<int64_t>(blockIdx.x) * chunk;
-    const int64_t end = beg + chunk < ld ? beg + chunk : ld;
+    const T *colp = P + static_cast<int64_t>(ccol ? c : 0) * cs;
+    const T *colb = P + static_cast<int64_t>(16 + (bcol ? c : 0)) * cs;  // dereferenced only for S1 >= 18
+    const T *xcol = P + 16 * cs;                                         // dereferenced only for S1 == 17
 
     typename M::acc_t gacc = {}, bacc = {}, bbacc = {};
     T cacc = T(0), cbacc = T(0), hx = T(0), hxx = T(0), cx = T(0);
@@ -165,7 +166,20 @@ __global__ __launch_bounds__(kGsThreads) void k_gram_sym(const DevState *__restr
     }
     __syncthreads();
     for (int e = threadIdx.x; e < E; e += kGsThreads)
-        gpart[static_cast<int64_t>(e) * estride + blockIdx.x] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+        out[static_cast<int64_t>(e) * estride + slot] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    __syncthreads();
+}
+
+template <typename T, int S1, bool WAP, bool WD>
+__global__ __launch_bounds__(kGsThreads) void k_gram_sym(const DevState *__restrict__ st, const T *__restrict__ P,
+                                                          int64_t ld, const T *__restrict__ dvec, int64_t chunk,
+                                                          double *__restrict__ gpart, int estride)
+{
+    if (st->done)
+        return;
+    const int64_t beg = static_cast<int64_t>(blockIdx.x) * chunk;
+    const int64_t end = beg + chunk < ld ? beg + chunk : ld;
+    gram_sym_rows<T, S1, WAP, WD>(P, ld, dvec, beg, end, gpart, estride, blockIdx.x);
 }
 
 template <typename T, int S>

@@ -53,6 +53,13 @@ hipError_t launch_fgs(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st)
 {
+    if (a.rec) {
+#define SSTEP_BGS(S)                                                                         \
+    case S:                                                                                  \
+        return a.fp32 ? bgram_sym_launch_s<float, S>(a, st) : bgram_sym_launch_s<double, S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_BGS) SSTEP_CASES_17_31(SSTEP_BGS) default: return hipErrorInvalidValue; }
+#undef SSTEP_BGS
+    }
 #define SSTEP_BG(S)                                                                          \
     case S:                                                                                  \
         return a.fp32 ? bgram_launch_s<float, S>(a, st) : bgram_launch_s<double, S>(a, st);
@@ -62,6 +69,13 @@ hipError_t launch_bgram(const BatchArgs &a, hipStream_t st)
 
 hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st)
 {
+    if (a.rec) {
+#define SSTEP_BFR(S) \
+    case S:          \
+        return bfgs_rec_launch_s<S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_BFR) SSTEP_CASES_17_31(SSTEP_BFR) default: return hipErrorInvalidValue; }
+#undef SSTEP_BFR
+    }
 #define SSTEP_BF(S) \
     case S:         \
         return bfgs_launch_s<S>(a, st);

@@ -149,6 +149,11 @@ struct BatchArgs {
     double *rpart = nullptr, *gpart = nullptr, *dbg = nullptr;
     double cscale = 1.0;
     int wdvec = 0;
+    // recurrence Gram kind: P holds p_0..p_s per pair, no AP; the Gram kernel
+    // forms H = P^T M P (rec_wap: M from the diagonal arrays, else
+    // rec_hscale M = const), the FGS kernel maps H onto P^T A P
+    int rec = 0, rec_wap = 0;
+    double rec_hscale = 1.0;
 };
 
 hipError_t launch_bresidual(const BatchArgs &a, hipStream_t st, bool write_p0);

@@ -315,7 +315,7 @@ class BatchedSolver:
 
     def __init__(self, ops: list, nrhs: int, s: int, nu: int, lmin, lmax, *, precision: str = "fp64",
                  precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
-                 autotune: bool = True, stream=None):
+                 autotune: bool = True, gram: str = "auto", stream=None):
         self._lib = N.load()
         self.ops = list(ops)
         self.nsys = len(self.ops)
@@ -329,6 +329,7 @@ class BatchedSolver:
         opt.max_outer = max_outer
         opt.graph_chunk = graph_chunk
         opt.autotune = 1 if autotune else 0
+        opt.gram = N.GRAM_KINDS[gram]
         self._stream = stream
         opt.stream = stream.cuda_stream if stream is not None else (
             torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None)
@@ -345,6 +346,7 @@ class BatchedSolver:
         _check(st, None)
         self._ctx = ctx
         self.sizes = [op.n for op in self.ops]
+        self.gram_kind = {v: k for k, v in N.GRAM_KINDS.items()}[int(self._lib.sstep_gram_mode(ctx))]
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -1,5 +1,8 @@
 """Batched solves (many uneven stencil systems x several right-hand sides per
-launch) against the FP64 oracle, pair by pair."""
+launch) against the FP64 oracle, pair by pair, with both Gram kinds a
+batched context takes: the recurrence kind (default for s <= 31: the basis
+keeps p_s, the matrix-core kernel forms the M-weighted Gram of p_0 .. p_s
+per pair, the FGS kernel maps it onto P^T A P) and the stored-AP kind."""
 import numpy as np
 import pytest
 import torch
@@ -49,12 +52,13 @@ def run_batched(hip, systems, nrhs, s, nu, tol=1e-8, **kw):
     return [host(xq).reshape(nrhs, -1) for xq in x], st
 
 
+@pytest.mark.parametrize("gram", ["auto", "stored"])
 @pytest.mark.parametrize("faces", [True, False])
-def test_batched_fp64_matches_oracle_per_pair(hip, faces):
+def test_batched_fp64_matches_oracle_per_pair(hip, faces, gram):
     dims = [(10, 9, 8), (13, 12, 11), (7, 7, 7), (16, 5, 9)]
     nrhs, s, nu = 3, 8, 25
     systems = make_batch(1, dims, nrhs, faces=faces)
-    x, st = run_batched(hip, systems, nrhs, s, nu)
+    x, st = run_batched(hip, systems, nrhs, s, nu, gram=gram)
     for q, sy in enumerate(systems):
         for r in range(nrhs):
             b = sy["rhs"][r]
@@ -65,26 +69,42 @@ def test_batched_fp64_matches_oracle_per_pair(hip, faces):
             assert abs(p.outer_iters - ref["iters"]) <= max(1, int(0.05 * ref["iters"])), (q, r)
 
 
-def test_batched_first_iterates_follow_oracle(hip):
+# (s, faces, precond, gram): widths on both sides of the matrix-core column
+# blocks (17 and 20 columns with the recurrence kind), Jacobi off
+FIRST_ITERATES = {
+    "s6_faces_rec": (6, True, True, "auto"),
+    "s6_faces_stored": (6, True, True, "stored"),
+    "s16_poisson_rec": (16, False, True, "auto"),
+    "s19_faces_rec": (19, True, True, "recurrence"),
+    "s8_faces_no_jacobi_rec": (8, True, False, "auto"),
+    "s8_poisson_no_jacobi_rec": (8, False, False, "auto"),
+}
+
+
+@pytest.mark.parametrize("name", list(FIRST_ITERATES))
+def test_batched_first_iterates_follow_oracle(hip, name):
+    s, faces, precond, gram = FIRST_ITERATES[name]
     dims = [(11, 10, 9), (6, 8, 7)]
-    nrhs, s, nu = 2, 6, 20
-    systems = make_batch(2, dims, nrhs)
+    nrhs, nu = 2, 20
+    systems = make_batch(2, dims, nrhs, faces=faces)
     for k in (1, 2, 3):
-        x, st = run_batched(hip, systems, nrhs, s, nu, max_outer=k)
+        x, st = run_batched(hip, systems, nrhs, s, nu, max_outer=k, precond=precond, gram=gram)
         for q, sy in enumerate(systems):
             for r in range(nrhs):
                 assert st[q * nrhs + r].outer_iters == k and st[q * nrhs + r].status == 5
                 xo = np.zeros(sy["rhs"].shape[1])
                 for _ in range(k):
-                    xo = oracle.step(sy["A"], sy["rhs"][r], xo, s, nu, sy["lmin"], sy["lmax"])["x"]
+                    xo = oracle.step(sy["A"], sy["rhs"][r], xo, s, nu, sy["lmin"], sy["lmax"],
+                                     precond=1 if precond else 0)["x"]
                 assert rel(x[q][r], xo) <= 1e-10, (k, q, r)
 
 
-def test_batched_fp32ir_reaches_tolerance(hip):
+@pytest.mark.parametrize("gram", ["auto", "stored"])
+def test_batched_fp32ir_reaches_tolerance(hip, gram):
     dims = [(12, 12, 12), (9, 14, 10), (20, 6, 6)]
     nrhs, s, nu = 4, 16, 25
     systems = make_batch(3, dims, nrhs)
-    x, st = run_batched(hip, systems, nrhs, s, nu, precision="fp32ir")
+    x, st = run_batched(hip, systems, nrhs, s, nu, precision="fp32ir", gram=gram)
     for q, sy in enumerate(systems):
         for r in range(nrhs):
             b = sy["rhs"][r]
@@ -134,3 +154,20 @@ def test_batched_setup_rejects_csr_and_mixed(hip):
         hip.BatchedSolver([hip.Operator.stencil(5, 5, 5, pr.kx, pr.ky, pr.kz), hip.Operator.stencil(4, 4, 4)],
                           1, 4, 5, [0.0, 0.0], [2.0, 2.0])
     assert ei.value.name == "SSTEP_E_ARG"
+
+
+def test_batched_gram_kind_selection(hip):
+    pr = gen.small_faces3d(6, 5, 4)
+    ops = [hip.Operator.stencil(6, 5, 4, pr.kx, pr.ky, pr.kz)]
+    with hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0]) as bs:
+        assert bs.gram_kind == "recurrence"
+    with hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0], gram="stored") as bs:
+        assert bs.gram_kind == "stored"
+    with hip.BatchedSolver(ops, 2, 32, 5, [0.0], [2.0]) as bs:
+        assert bs.gram_kind == "stored"
+    with pytest.raises(hip.SStepError) as ei:
+        hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0], gram="apply")
+    assert ei.value.name == "SSTEP_E_UNSUPPORTED"
+    with pytest.raises(hip.SStepError) as ei:
+        hip.BatchedSolver(ops, 2, 32, 5, [0.0], [2.0], gram="recurrence")
+    assert ei.value.name == "SSTEP_E_UNSUPPORTED"
