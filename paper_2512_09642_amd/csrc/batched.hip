@@ -68,7 +68,11 @@ __device__ __forceinline__ T block_sum(T v)
 }
 
 // r = b - A x (FP64) per pair over a chunk, ||r||^2 partial per (pair, chunk),
-// p_0 = p0scale * (M^{-1} r or r) as column 0 of the pair's basis.
+// p_0 = p0scale * (M^{-1} r or r) as column 0 of the pair's basis.  The
+// right-hand sides go in groups of kRhsGroup: a point's coefficients are
+// loaded once for the group, and each pair's partial is summed in the same
+// order as one pair at a time would.
+constexpr int kRhsGroup = 8;
 template <typename TP, bool FACES>
 __global__ __launch_bounds__(kBlock) void k_bresidual(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                       const BTile *__restrict__ tiles, int ntiles,
@@ -83,27 +87,44 @@ __global__ __launch_bounds__(kBlock) void k_bresidual(const BGlob *__restrict__ 
         const BSys &S = sys[tl.q];
         const int64_t beg = static_cast<int64_t>(tl.chunk) * S.gchunk;
         const int64_t end = beg + S.gchunk < S.n ? beg + S.gchunk : S.n;
-        for (int r = 0; r < nrhs; ++r) {
-            const DevState &ps = pairs[S.pair0 + r];
-            if (ps.done)
-                continue;
-            const double *__restrict__ b = ps.b;
-            const double *__restrict__ x = ps.x;
-            const double scale = ps.p0scale;
-            TP *p0 = P + S.pofs + static_cast<int64_t>(r) * S.ld;
-            double acc = 0.0;
+        for (int r0 = 0; r0 < nrhs; r0 += kRhsGroup) {
+            bool act[kRhsGroup];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < kRhsGroup; ++u) {
+                act[u] = r0 + u < nrhs && !pairs[S.pair0 + r0 + u].done;
+                any = any || act[u];
+            }
+            if (!any)
+                continue;  // the same for the whole block
+            double acc[kRhsGroup];
+#pragma unroll
+            for (int u = 0; u < kRhsGroup; ++u)
+                acc[u] = 0.0;
             for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
                 PointStencil<double, FACES> op;
                 op.init(S, c, precond, S.kx, S.ky, S.kz);
-                double pc;
-                const double rr = b[c] - op.apply(x, pc);
-                acc += rr * rr;
-                if (write_p0)
-                    p0[c] = static_cast<TP>(scale * (p0_mode ? rr : op.dinv * rr));
+#pragma unroll
+                for (int u = 0; u < kRhsGroup; ++u) {
+                    if (!act[u])
+                        continue;
+                    const DevState &ps = pairs[S.pair0 + r0 + u];
+                    double pc;
+                    const double rr = ps.b[c] - op.apply(ps.x, pc);
+                    acc[u] += rr * rr;
+                    if (write_p0)
+                        P[S.pofs + static_cast<int64_t>(r0 + u) * S.ld + c] =
+                            static_cast<TP>(ps.p0scale * (p0_mode ? rr : op.dinv * rr));
+                }
             }
-            acc = block_sum(acc);
-            if (threadIdx.x == 0)
-                rpart[S.rofs + static_cast<int64_t>(r) * S.nch + tl.chunk] = acc;
+#pragma unroll
+            for (int u = 0; u < kRhsGroup; ++u) {
+                if (!act[u])
+                    continue;  // act is the same in every thread
+                const double sum = block_sum(acc[u]);
+                if (threadIdx.x == 0)
+                    rpart[S.rofs + static_cast<int64_t>(r0 + u) * S.nch + tl.chunk] = sum;
+            }
         }
     }
 }
