@@ -97,9 +97,10 @@ def basis_bytes_per_launch(n: int, s: int, w: int, kind: str = "stored", pairs: 
 
 
 def measured_traffic(N: int, s: int, nu: int):
-    """HBM bytes per basis launch recorded from hardware counters for the
-    224^3, s = 16, nu = 25 FP64 workload, or None when the workload differs or
-    the kernel sources have changed since the counters were taken."""
+    """HBM bytes recorded from hardware counters for the 224^3, s = 16, nu = 25
+    FP64 workload (per basis launch and per outer iteration), or None when the
+    workload differs or the kernel sources have changed since the counters
+    were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_poisson224_s16_fp64.json")
     if (N, s, nu) != (224, 16, 25) or not os.path.exists(path):
         return None
@@ -109,7 +110,7 @@ def measured_traffic(N: int, s: int, nu: int):
     for name in rec["source_files"]:
         with open(os.path.join(ROOT, name), "rb") as f:
             h.update(f.read())
-    return rec["basis_avg_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    return rec if h.hexdigest() == rec["source_sha256"] else None
 
 
 def _host_description() -> dict:
@@ -418,7 +419,7 @@ def main():
                 tot_bytes += per_rhs * sum(its) + faces * max(its)
             per_sys = [max(leg.pair_iters[q * 8:(q + 1) * 8]) for q in range(leg.nsys)]
             g = tot_bytes / (t * 1e-3) / 1e9
-            r.update(frac_of_hbm_peak=g / HBM_PEAK_GBPS)
+            r.update(frac_of_hbm_peak=g / HBM_PEAK_GBPS, tiles=leg.solver.tiles)
             r.update(outer_iters_min=min(leg.pair_iters), outer_iters_max=max(leg.pair_iters),
                      pairs=len(leg.pair_iters), unknown_rhs=leg.n * 8,
                      max_rel_res=max(leg.pair_relres), gbps_effective=tot_bytes / (t * 1e-3) / 1e9,
@@ -476,6 +477,9 @@ def main():
                 main_leg.b, torch.zeros_like(main_leg.b), reps=args.kernel_reps)
         kind = main_leg.solver.gram_kind
         sv0 = main_leg.solver
+        traffic = measured_traffic(args.N, args.s, args.nu)
+        # counter-measured HBM bytes of one outer iteration (all its kernels), next to the algorithmic ones
+        results["c2_fp64"]["counter_bytes_per_outer"] = traffic.get("bytes_per_outer") if traffic else None
         per_launch = basis_bytes_per_launch(main_leg.n, args.s, 8, kind, sv0.basis_pairs, sv0.basis_launches)
         achieved = per_launch / (kt["basis"] * 1e-3) / 1e9
         if sv0.basis_pairs:
@@ -493,7 +497,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": measured_traffic(args.N, args.s, args.nu),
+            "traffic": traffic["basis_avg_bytes_per_launch"] if traffic else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 read requests by size + WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": per_launch,
             "avg_launch_ms": kt["basis"],

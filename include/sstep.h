@@ -287,6 +287,12 @@ int32_t sstep_basis_launches(const sstep_ctx *ctx, int32_t *pairs);
 sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_operator *A, int32_t nrhs, int32_t s,
                                  int32_t nu, const double *lmin, const double *lmax, const sstep_options *opt);
 
+/* The tile schedule a batched context runs (chosen by the autotuner at set-up,
+ * or the defaults): rows per chunk tile of the residual, Gram and update
+ * launches, and the persistent grid in blocks per compute unit (host outputs,
+ * each may be NULL).  SSTEP_E_ARG for a NULL or non-batched context. */
+sstep_status sstep_batched_tiles(const sstep_ctx *ctx, int64_t *rows_per_tile, int32_t *grid_factor);
+
 /* b[q], x[q] (host arrays of nsys device pointers): n_q x nrhs FP64,
  * column-major (right-hand side r at offset r*n_q).  st: host array of
  * nsys*nrhs entries (pair (q, r) at q*nrhs + r), may be NULL.  Returns the

@@ -966,6 +966,17 @@ int32_t sstep_gram_mode(const sstep_ctx *ctx)
     return ctx->it.gram_rec ? SSTEP_GRAM_RECURRENCE : (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP);
 }
 
+sstep_status sstep_batched_tiles(const sstep_ctx *ctx, int64_t *rows_per_tile, int32_t *grid_factor)
+{
+    if (!ctx || !ctx->batch)
+        return SSTEP_E_ARG;
+    if (rows_per_tile)
+        *rows_per_tile = ctx->batch->gchunk;
+    if (grid_factor)
+        *grid_factor = ctx->batch->grid_factor;
+    return SSTEP_OK;
+}
+
 int32_t sstep_basis_launches(const sstep_ctx *ctx, int32_t *pairs)
 {
     if (!ctx || ctx->batch)

@@ -347,6 +347,10 @@ class BatchedSolver:
         self._ctx = ctx
         self.sizes = [op.n for op in self.ops]
         self.gram_kind = {v: k for k, v in N.GRAM_KINDS.items()}[int(self._lib.sstep_gram_mode(ctx))]
+        rows, factor = C.c_int64(0), C.c_int32(0)
+        _check(self._lib.sstep_batched_tiles(ctx, C.byref(rows), C.byref(factor)), ctx)
+        #: the tile schedule: rows per chunk tile and persistent blocks per compute unit
+        self.tiles = {"rows_per_tile": int(rows.value), "grid_factor": int(factor.value)}
 
     def close(self):
         if getattr(self, "_ctx", None):
