@@ -19,10 +19,8 @@
 // memory.  HBM traffic per point: p_{j-1} and p_j read, q and p_{j+2}
 // written, 4 vectors for two columns against 6 for two single steps; the
 // ring and the two extra planes of each range are re-reads served mostly by
-// L2.  Both outputs are stored non-temporally: on MI355X the FP64 pair ran
-// at 54 us instead of 88 us at 224^3 with them (loads and stores share one
-// in-order completion counter, and cached stores of this volume are slow to
-// complete); a 56-point interior keeps every FP64 row store 64-byte aligned.
+// L2.  A 56-point interior keeps every FP64 row store 64-byte aligned; the
+// store policy per precision is at buf_store_out.
 #pragma once
 
 #include "common.h"
@@ -88,13 +86,18 @@ __device__ __forceinline__ float buf_load(float, __amdgpu_buffer_rsrc_t r, uint3
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
-__device__ __forceinline__ void buf_store_nt(double v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+// FP64 results are stored non-temporally, FP32 ones through the caches: the
+// 248-byte FP32 row pieces end mid-line, and L2 merges such partial lines
+// only for cached stores (FP32 pair 47 us cached against 62 us
+// non-temporal, FP64 84 us non-temporal against 87 us cached, in the
+// solve's setting at 224^3).
+__device__ __forceinline__ void buf_store_out(double v, __amdgpu_buffer_rsrc_t r, uint32_t off)
 {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, off, 0, kNonTemporal);
 }
-__device__ __forceinline__ void buf_store_nt(float v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ void buf_store_out(float v, __amdgpu_buffer_rsrc_t r, uint32_t off)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kNonTemporal);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
 
 // Largest plane window one block addresses: kz + 4 planes (two below the
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kF2Lanes *EY, MW) void k_basis_f2(const DevState *_
                 else
                     q = two_theta * (minv * y - sigma * p0) - pv;
             }
-            buf_store_nt(q, rq, at(kq, 0, interior, k0, k1 - 1));
+            buf_store_out(q, rq, at(kq, 0, interior, k0, k1 - 1));
             qs[buf][tid] = q;
             // the second step on the plane below: q there is in qs[buf ^ 1]
             // (stored before this plane's barrier), q below it in qb, above in q
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(kF2Lanes *EY, MW) void k_basis_f2(const DevState *_
                 const T y = T(6) * qc - (((((qp[tid - 1] + qp[tid + 1]) + qp[tid - kF2Lanes]) + qp[tid + kF2Lanes]) + qb) + q);
                 p2 = two_theta * (minv * y - sigma * qc) - pm;
             }
-            buf_store_nt(p2, r2, at(kq - 1, 0, interior, k0, k1 - 1));
+            buf_store_out(p2, r2, at(kq - 1, 0, interior, k0, k1 - 1));
             qb = qc;
             qc = q;
             pm = p0;
