@@ -46,7 +46,7 @@ def basis_vectors(s: int, kind: str = "stored", pairs: int = 0) -> int:
     """Vectors one basis moves per unknown, each read or write of a column
     counted once.  Single steps: the first reads p_0 and writes p_1 (2), each
     later one reads p_j, p_{j-1} and writes p_{j+1} (3); the apply kind takes
-    s - 1 steps (3s - 4), the recurrence kind s (3s - 1); with AP stored every
+    s - 1 steps (3s - 4), the recurrence and moments kinds s (3s - 1); with AP stored every
     launch also writes A p_j and the last writes only that (4s - 3).  Two
     steps per launch (pairs > 0): the first pair reads p_0 and writes p_1, p_2
     (3), each later pair reads two columns and writes two (4), and an odd
@@ -56,7 +56,7 @@ def basis_vectors(s: int, kind: str = "stored", pairs: int = 0) -> int:
         return 3 + 4 * (pairs - 1) + 3 * (m - 2 * pairs)
     if kind == "apply":
         return 3 * s - 4
-    if kind == "recurrence":
+    if kind in ("recurrence", "moments"):
         return 3 * s - 1
     return 4 * s - 3
 
@@ -65,26 +65,29 @@ def stencil_bytes_per_outer(n: int, s: int, w: int, kind: str = "stored", pairs:
     """Bytes an outer iteration must move, constant-coefficient stencil:
     residual 16 + w (x, b read in FP64, p_0 written), the basis (above), the
     Gram reading its columns (stored: P and AP, 2s; apply: P, s; recurrence:
-    p_0 .. p_s, s + 1), the update sw + 16 (P read, x read and written)."""
-    gram_cols = {"stored": 2 * s, "apply": s, "recurrence": s + 1}[kind]
+    p_0 .. p_s, s + 1; moments: none, the basis kernels form its products),
+    the update sw + 16 (P read, x read and written)."""
+    gram_cols = {"stored": 2 * s, "apply": s, "recurrence": s + 1, "moments": 0}[kind]
     return float(n) * (32 + w * (1 + basis_vectors(s, kind, pairs) + gram_cols + s))
 
 
 def csr_bytes_per_outer(n: int, nnz: int, s: int, w: int, kind: str = "stored", pairs: int = 0) -> float:
     """The stencil figure plus the matrix (values and column indices, row
     pointers) read by s basis SpMVs in precision w and one FP64 residual SpMV,
-    and the M-diagonal read by the Gram right-hand side."""
+    and the M-diagonal read by the Gram kernel (none with the moments kind)."""
     mat_w = float(nnz) * (4 + w) + 4.0 * (n + 1)
     mat_64 = float(nnz) * 12 + 4.0 * (n + 1)
-    return stencil_bytes_per_outer(n, s, w, kind, pairs) + s * mat_w + mat_64 + float(n) * w
+    dvec = 0.0 if kind == "moments" else float(n) * w
+    return stencil_bytes_per_outer(n, s, w, kind, pairs) + s * mat_w + mat_64 + dvec
 
 
 def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, kind: str = "stored") -> float:
     """Stencil figure per right-hand side plus the three face arrays read by the
     FP64 residual and s more times (the s basis steps, or the s - 1 basis
     steps and the Gram when it forms A p_j itself), shared by nrhs right-hand
-    sides, and the M-diagonal read by the Gram right-hand side."""
-    return nrhs * (stencil_bytes_per_outer(n, s, w, kind) + float(n) * w) + float(n) * 3 * (8 + s * w)
+    sides, and the M-diagonal read by the Gram kernel (none with the moments kind)."""
+    dvec = 0.0 if kind == "moments" else float(n) * w
+    return nrhs * (stencil_bytes_per_outer(n, s, w, kind) + dvec) + float(n) * 3 * (8 + s * w)
 
 
 def basis_bytes_per_launch(n: int, s: int, w: int, kind: str = "stored", pairs: int = 0,
@@ -355,7 +358,7 @@ def main():
                     help="skip the one-time measurements after the timed steps (C3 sweep, Lanczos bounds, the "
                          "27-point table, the coarse solve)")
     ap.add_argument("--N27", type=int, default=230, help="grid edge of the paper's 27-point workload")
-    ap.add_argument("--gram", default="auto", choices=["auto", "stored", "apply", "recurrence"],
+    ap.add_argument("--gram", default="auto", choices=["auto", "stored", "apply", "recurrence", "moments"],
                     help="Gram kind of the single-system legs (default: the library's choice; 'apply' falls back "
                          "to 'stored' where the operator-applying kernel does not exist)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -489,7 +492,7 @@ def main():
         else:
             kname = ("k_basis_p2 (7-point stencil + Jacobi + Chebyshev step, FP64), average of the "
                      + {"apply": "s - 1 launches (AP not written)", "recurrence": "s launches (the last writes p_s)",
-                        "stored": "s launches (AP written)"}[kind])
+                        "moments": "s launches (the last writes p_s)", "stored": "s launches (AP written)"}[kind])
         out["roofline"] = {
             "bound": "hbm",
             "kernel": kname,

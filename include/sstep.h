@@ -109,12 +109,24 @@ typedef struct {
  * G_raw = P^T A P exactly: M^{-1} A p_j = (p_{j+1} + p_{j-1}) / (2 theta)
  * + sigma p_j (j >= 1), M^{-1} A p_0 = p_1 / theta + sigma p_0 (monomial
  * basis: M^{-1} A p_j = p_{j+1}).  AP is neither written nor allocated and A
- * is not applied in the Gram kernel. */
+ * is not applied in the Gram kernel.  MOMENTS (Chebyshev basis, s <= 31,
+ * p_0 = M^{-1} r or no preconditioner, contexts made by sstep_setup): as
+ * RECURRENCE, but no kernel reads the basis back.  While the basis kernels
+ * form p_i, they sum d_i = <p_i, M p_i> and e_i = <p_i, M p_{i-1}>
+ * (fixed-order block partials).  With X = theta (M^{-1} A - sigma I),
+ * p_i = T_i(X) p_0 and M X symmetric, the product rule
+ * T_i T_j = (T_{i+j} + T_{|i-j|}) / 2 gives
+ * H_ij = (mu_{i+j} + mu_{|i-j|}) / 2 with mu_0 = d_0, mu_1 = e_1,
+ * mu_2i = 2 d_i - mu_0, mu_{2i-1} = 2 e_i - mu_1, and c_i = <p_i, r> = mu_i.
+ * The FGS kernel forms H and then G_raw as for RECURRENCE.  Equal to the
+ * directly formed Gram matrix up to rounding; asking for it otherwise gives
+ * SSTEP_E_UNSUPPORTED. */
 typedef enum {
     SSTEP_GRAM_AUTO = 0,
     SSTEP_GRAM_STORED_AP = 1,
     SSTEP_GRAM_APPLY_OP = 2,
-    SSTEP_GRAM_RECURRENCE = 3
+    SSTEP_GRAM_RECURRENCE = 3,
+    SSTEP_GRAM_MOMENTS = 4
 } sstep_gram_kind;
 
 typedef struct {
@@ -129,13 +141,20 @@ typedef struct {
                                $SSTEP_TUNE_CACHE or ~/.cache/sstep/tune.json; systems under 2^20
                                unknowns use the defaults; 0 = defaults */
     int32_t gram;           /* sstep_gram_kind: how G = P^T A P (Sec. 2) is formed.  SSTEP_GRAM_AUTO
-                               (default) = SSTEP_GRAM_RECURRENCE for s <= 31, SSTEP_GRAM_STORED_AP at
-                               s = 32.  Batched contexts take AUTO, RECURRENCE or STORED_AP
-                               (SSTEP_E_UNSUPPORTED for APPLY_OP) */
+                               (default) = SSTEP_GRAM_MOMENTS in FP64 where it applies, else
+                               SSTEP_GRAM_RECURRENCE for s <= 31 (FP32+IR, p_0 = r with Jacobi,
+                               the monomial basis, the allocation-free solve), SSTEP_GRAM_STORED_AP
+                               at s = 32.  Batched contexts take AUTO (= RECURRENCE for s <= 31),
+                               RECURRENCE or STORED_AP (SSTEP_E_UNSUPPORTED for APPLY_OP and
+                               MOMENTS) */
     int32_t basis;          /* 0 = Chebyshev basis (default, Sec. 2); 1 = monomial basis
                                p_{j+1} = M^{-1} A p_j of the same Krylov space, the comparison of
                                Sec. 4 (a diagnostic: its Gram matrix is badly conditioned; the
                                bounds are then unused; not for batched contexts) */
+    int32_t basis_steps;    /* 0 (default) = two basis steps per launch where the kernels allow it
+                               (constant 7-point operator, or batched stencil systems, when AP is
+                               not stored); 1 = one step per launch everywhere.  Both give the
+                               same basis bit for bit */
     void *stream;           /* hipStream_t the caller's data is ordered on (NULL = default) */
 } sstep_options;
 
@@ -267,23 +286,27 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
  * -1 for a NULL context. */
 int32_t sstep_gram_mode(const sstep_ctx *ctx);
 
-/* Kernel launches that form the basis p_1 .. p_m of one outer iteration of a
- * context made by sstep_setup (Sec. 2, Definition; m = s - 1 with
- * SSTEP_GRAM_APPLY_OP, else s).  For the constant 7-point operator with the
- * Chebyshev basis and AP not stored, one launch forms two consecutive
- * columns (p_{j+1} and p_{j+2} from p_{j-1} and p_j, exactly as two single
- * steps would), and *pairs (if pairs is not NULL) receives how many launches
- * do so; an odd m ends with a single step.  Otherwise every launch forms one
- * column and *pairs is 0.  Returns -1 for a NULL or batched context. */
+/* Kernel launches that form the basis p_1 .. p_m of one outer iteration
+ * (Sec. 2, Definition; m = s - 1 with SSTEP_GRAM_APPLY_OP, else s).  With
+ * basis_steps = 0, for the constant 7-point operator with the Chebyshev basis
+ * and AP not stored, and for batched stencil systems with the recurrence Gram
+ * kind, one launch forms two consecutive columns (p_{j+1} and p_{j+2} from
+ * p_{j-1} and p_j, exactly as two single steps would), and *pairs (if pairs
+ * is not NULL) receives how many launches do so; an odd m ends with a single
+ * step.  Otherwise every launch forms one column and *pairs is 0.  A batched
+ * context takes two steps per launch only when every system's grid row fits
+ * a third of a 1024-thread block (or its whole plane fits one block).
+ * Returns -1 for a NULL context. */
 int32_t sstep_basis_launches(const sstep_ctx *ctx, int32_t *pairs);
 
 /* Batched solves: nsys independent operators (each its own size), nrhs
  * right-hand sides per operator, one shared s and nu, per-system bounds
  * lmin[q] < lmax[q] (host arrays).  The outer iteration of every
- * (system, rhs) pair advances together: each step of it (residual, each of
- * the s basis steps, Gram, FGS, update) is one persistent launch over all
- * pairs, s + 4 launches per outer iteration, graph_chunk outer iterations per
- * graph replay; a pair that has stopped is skipped by every launch. */
+ * (system, rhs) pair advances together: each step of it (residual, the basis
+ * steps, Gram, FGS, update) is one launch over all pairs, at most s + 4
+ * launches per outer iteration (fewer when basis launches form two columns,
+ * see sstep_basis_launches), graph_chunk outer iterations per graph replay; a
+ * pair that has stopped is skipped by every launch. */
 sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_operator *A, int32_t nrhs, int32_t s,
                                  int32_t nu, const double *lmin, const double *lmax, const sstep_options *opt);
 

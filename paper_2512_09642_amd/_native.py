@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "SSTEP_OK", 1: "SSTEP_E_ARG", 2: "SSTEP_E_HIP", 3: "SSTEP_E_N
                 5: "SSTEP_E_NOCONV", 6: "SSTEP_E_NONFINITE", 7: "SSTEP_E_UNSUPPORTED"}
 OP_CSR, OP_STENCIL7, OP_STENCIL27 = 0, 1, 2
 FP64, FP32_IR = 0, 1
-GRAM_KINDS = {"auto": 0, "stored": 1, "apply": 2, "recurrence": 3}
+GRAM_KINDS = {"auto": 0, "stored": 1, "apply": 2, "recurrence": 3, "moments": 4}
 KT_NAMES = ("residual", "basis", "gram", "fgs", "update")
 
 # every symbol the header declares
@@ -36,7 +36,8 @@ class Operator(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("p0_mode", C.c_int32),
                 ("max_outer", C.c_int32), ("graph_chunk", C.c_int32), ("record_history", C.c_int32),
-                ("autotune", C.c_int32), ("gram", C.c_int32), ("basis", C.c_int32), ("stream", C.c_void_p)]
+                ("autotune", C.c_int32), ("gram", C.c_int32), ("basis", C.c_int32), ("basis_steps", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class Stats(C.Structure):

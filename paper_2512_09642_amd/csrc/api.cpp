@@ -65,6 +65,7 @@ struct Batched {
     BTile *dbt = nullptr;
     PTile *dpt = nullptr;
     GTile *dgt = nullptr;
+    BF2Tile *df2 = nullptr;
     int64_t gchunk = 8192;
     int grid_factor = 4;
     int cus = 256;
@@ -351,8 +352,30 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
 // The operator-applying Gram kernel: 7-point stencil operators, s <= 16,
 // columns under 4 GiB (32-bit byte offsets); by default for FP64 only (in
 // FP32+IR the stored-AP kernel is as fast).
-sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, const sstep_options &o, int *kind)
+// The moments kind needs the Chebyshev basis and c = P^T r expressible in the
+// same M inner product as H: r = M p_0 (p_0 = M^{-1} r) or M = I.
+bool moments_fit(int s, const sstep_options &o)
 {
+    return s <= kRecMaxS && o.basis == 0 && (o.p0_mode == 0 || o.precond == 0);
+}
+
+sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, const sstep_options &o, int *kind,
+                              bool allow_moments)
+{
+    if (o.gram == SSTEP_GRAM_MOMENTS) {
+        if (!allow_moments || !moments_fit(s, o))
+            return fail(ctx, SSTEP_E_UNSUPPORTED,
+                        "the moments Gram kind needs the Chebyshev basis, s <= 31, p_0 = M^{-1} r or no "
+                        "preconditioner, and a context that may allocate");
+        *kind = SSTEP_GRAM_MOMENTS;
+        return SSTEP_OK;
+    }
+    // AUTO: the moments kind in FP64; in FP32+IR the recurrence kind, whose
+    // solves took fewer outer iterations (52 against 82 at 224^3, s = 16)
+    if (o.gram == SSTEP_GRAM_AUTO && allow_moments && moments_fit(s, o) && o.precision == SSTEP_FP64) {
+        *kind = SSTEP_GRAM_MOMENTS;
+        return SSTEP_OK;
+    }
     if (o.gram == SSTEP_GRAM_RECURRENCE) {
         if (s > kRecMaxS)
             return fail(ctx, SSTEP_E_UNSUPPORTED, "the recurrence Gram kind needs s <= 31");
@@ -384,7 +407,8 @@ sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, co
 void set_gram_kind(IterArgs &it, int kind, int precond, bool const_diag)
 {
     it.gram_op = kind == SSTEP_GRAM_APPLY_OP;
-    it.gram_rec = kind == SSTEP_GRAM_RECURRENCE;
+    it.gram_rec = kind == SSTEP_GRAM_RECURRENCE || kind == SSTEP_GRAM_MOMENTS;
+    it.gram_mom = kind == SSTEP_GRAM_MOMENTS;
     it.rec_wap = it.gram_rec && precond && !const_diag;
     it.rec_hscale = (it.gram_rec && precond && const_diag) ? (it.op.kind == kOpPoisson27 ? 26.0 : 6.0) : 1.0;
 }
@@ -700,6 +724,7 @@ void sstep_default_options(sstep_options *opt)
     opt->autotune = 1;
     opt->gram = SSTEP_GRAM_AUTO;
     opt->basis = 0;
+    opt->basis_steps = 0;
     opt->stream = nullptr;
 }
 
@@ -784,15 +809,17 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
         return fail(ctx, SSTEP_E_ARG, "max_outer must be >= 0");
     if (o.basis != 0 && o.basis != 1)
         return fail(ctx, SSTEP_E_ARG, "basis must be 0 (Chebyshev) or 1 (monomial)");
+    if (o.basis_steps != 0 && o.basis_steps != 1)
+        return fail(ctx, SSTEP_E_ARG, "basis_steps must be 0 or 1");
     if (o.graph_chunk <= 0)
         o.graph_chunk = 4;
     OKCHK(check_operator(ctx, A));
     if (A->kind == SSTEP_OP_CSR)
         OKCHK(check_csr_pattern(ctx, A));
-    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_RECURRENCE)
+    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_MOMENTS)
         return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
     int gram_kind = SSTEP_GRAM_STORED_AP;
-    OKCHK(choose_gram_kind(ctx, A, s, o, &gram_kind));
+    OKCHK(choose_gram_kind(ctx, A, s, o, &gram_kind, true));
 
     HIPCHK(ctx, hipGetDevice(&ctx->device));
     HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
@@ -815,6 +842,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     it.fp32 = o.precision == SSTEP_FP32_IR;
     it.p0_mode = o.p0_mode;
     it.monomial = o.basis;
+    it.one_step = o.basis_steps;
     it.s = s;
     it.nu = nu;
     it.theta = 2.0 / (lmax - lmin);
@@ -873,7 +901,15 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     }
     set_residual_schedule(it);
     OKCHK(dalloc(ctx, &it.rpart, size_t(it.nbr)));
-    OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s + it.gram_rec)) * kMaxGramBlocks));
+    if (it.gram_mom) {
+        std::vector<int32_t> cnt(size_t(2 * s + 1), 0);
+        mom_layout(it, cnt.data(), &it.mstride);
+        OKCHK(dalloc(ctx, &it.mpart, size_t(2 * s + 1) * size_t(it.mstride)));
+        OKCHK(dalloc(ctx, &it.mcnt, cnt.size()));
+        HIPCHK(ctx, hipMemcpy(it.mcnt, cnt.data(), cnt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    } else {
+        OKCHK(dalloc(ctx, &it.gpart, size_t(gram_entries(s + it.gram_rec)) * kMaxGramBlocks));
+    }
     OKCHK(dalloc(ctx, &it.gsum, size_t(gram_entries(s + it.gram_rec)) + 1));
     OKCHK(dalloc(ctx, &it.st, 1));
     OKCHK(dalloc(ctx, &it.dbg, size_t(dbg_size(s))));
@@ -892,7 +928,7 @@ static sstep_status setup_impl(sstep_ctx *ctx, const sstep_operator *A, int32_t 
     HIPCHK(ctx, hipMemsetAsync(it.st, 0, sizeof(DevState), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     set_gram_schedule(it, default_gram_schedule(it));
-    if (o.autotune && n >= (int64_t(1) << 20))
+    if (o.autotune && n >= (int64_t(1) << 20) && !it.gram_mom)  // the moments kind has no Gram kernel
         OKCHK(tune_gram(ctx));
 
     ctx->chunk = o.graph_chunk;
@@ -963,6 +999,8 @@ int32_t sstep_gram_mode(const sstep_ctx *ctx)
         return -1;
     if (ctx->batch)
         return ctx->batch->ba.rec ? SSTEP_GRAM_RECURRENCE : SSTEP_GRAM_STORED_AP;
+    if (ctx->it.gram_mom)
+        return SSTEP_GRAM_MOMENTS;
     return ctx->it.gram_rec ? SSTEP_GRAM_RECURRENCE : (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP);
 }
 
@@ -979,10 +1017,16 @@ sstep_status sstep_batched_tiles(const sstep_ctx *ctx, int64_t *rows_per_tile, i
 
 int32_t sstep_basis_launches(const sstep_ctx *ctx, int32_t *pairs)
 {
-    if (!ctx || ctx->batch)
+    if (!ctx)
         return -1;
-    int np = 0;
-    const int n = basis_kernel_count(ctx->it, &np);
+    int np = 0, n = 0;
+    if (ctx->batch) {
+        const BatchArgs &a = ctx->batch->ba;
+        np = a.f2 ? a.s / 2 : 0;
+        n = a.s - np;
+    } else {
+        n = basis_kernel_count(ctx->it, &np);
+    }
     if (pairs)
         *pairs = np;
     return n;
@@ -1218,6 +1262,43 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
     return SSTEP_OK;
 }
 
+// Bands of the two-step batched basis: each system's rows split into bands
+// of equal height (a band and its two neighbouring rows fill at most one
+// block of kBf2Threads threads; a grid whose planes fit in one block is one
+// band), its planes into ranges of about kBf2Planes.  Empty when some system
+// does not fit that shape (a row wider than a third of a block) or the
+// windows of its buffer accesses would pass 2 GiB: the batch then takes one
+// step per launch.
+static std::vector<BF2Tile> bf2_bands(const std::vector<BSys> &sys, size_t elem, bool faces, int nt, int kzt)
+{
+    std::vector<BF2Tile> out;
+    for (size_t q = 0; q < sys.size(); ++q) {
+        const Grid3 &g = sys[q].g;
+        const int64_t nx = g.nx, ny = g.ny, nz = g.nz;
+        const int64_t lim = (int64_t(1) << 31) - 1;
+        int64_t bytes = sys[q].n;
+        if (faces)
+            bytes = std::max({bytes, nz * ny * (nx + 1), nz * (ny + 1) * nx, (nz + 1) * g.nxy});
+        if (bytes * int64_t(elem) > lim)
+            return {};
+        int64_t bands = 1;
+        if (g.nxy > nt) {
+            const int64_t inner = nt / nx - 2;  // band rows a block can hold
+            if (inner < 1)
+                return {};
+            bands = (ny + inner - 1) / inner;
+        }
+        const int64_t h = (ny + bands - 1) / bands;
+        const int64_t ranges = (nz + kzt - 1) / kzt;
+        const int64_t kz = (nz + ranges - 1) / ranges;
+        for (int64_t y0 = 0; y0 < ny; y0 += h)
+            for (int64_t k0 = 0; k0 < nz; k0 += kz)
+                out.push_back({int32_t(q), int32_t(y0), int32_t(std::min(y0 + h, ny)), int32_t(k0),
+                               int32_t(std::min(k0 + kz, nz)), 0});
+    }
+    return out;
+}
+
 static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bool upload)
 {
     if (gchunk < kMinBatchChunk || gchunk % kPad != 0 || factor < 1)
@@ -1267,7 +1348,12 @@ static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
     hipError_t e;
     if ((e = launch_bresidual(a, s, true)) != hipSuccess)
         return e;
-    for (int j = 0; j < a.s; ++j)
+    int j = 0;
+    if (a.f2)  // two steps per launch, an odd last step alone
+        for (; j + 2 <= a.s; j += 2)
+            if ((e = launch_bbasis_pair(a, j, s)) != hipSuccess)
+                return e;
+    for (; j < a.s; ++j)
         if ((e = launch_bbasis(a, j, s)) != hipSuccess)
             return e;
     if ((e = launch_bgram(a, s)) != hipSuccess)
@@ -1349,13 +1435,14 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         return fail(ctx, SSTEP_E_ARG, "nu must be >= 1");
     if (o.precision != SSTEP_FP64 && o.precision != SSTEP_FP32_IR)
         return fail(ctx, SSTEP_E_ARG, "unknown precision");
-    if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0)
+    if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0 ||
+        (o.basis_steps != 0 && o.basis_steps != 1))
         return fail(ctx, SSTEP_E_ARG, "invalid options");
     if (o.basis != 0)
         return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves use the Chebyshev basis");
-    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_RECURRENCE)
+    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_MOMENTS)
         return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
-    if (o.gram == SSTEP_GRAM_APPLY_OP)
+    if (o.gram == SSTEP_GRAM_APPLY_OP || o.gram == SSTEP_GRAM_MOMENTS)
         return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves take the recurrence or the stored-AP Gram kind");
     if (o.gram == SSTEP_GRAM_RECURRENCE && s > kRecMaxS)
         return fail(ctx, SSTEP_E_UNSUPPORTED, "the recurrence Gram kind needs s <= 31");
@@ -1503,6 +1590,17 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     a.btiles = B.dbt;
     a.ptiles = B.dpt;
     a.gtiles = B.dgt;
+    if (a.rec && o.basis_steps == 0) {
+        const std::vector<BF2Tile> f2 = bf2_bands(B.sys, w, a.faces, a.f2nt, kBf2Planes);
+        if (!f2.empty()) {
+            OKCHK(dalloc(ctx, &B.df2, f2.size()));
+            HIPCHK(ctx, hipMemcpy(B.df2, f2.data(), f2.size() * sizeof(BF2Tile), hipMemcpyHostToDevice));
+            a.f2 = 1;
+            a.nf2 = int(f2.size());
+            a.f2per = uint32_t((int64_t(a.nf2) * a.nrhs + kNumXcd - 1) / kNumXcd);
+            a.f2tiles = B.df2;
+        }
+    }
     // a non-zero npairs with ndone = 0 keeps the kernels active while tuning
     BGlob g0{0, a.npairs};
     HIPCHK(ctx, hipMemcpy(a.gl, &g0, sizeof(BGlob), hipMemcpyHostToDevice));
@@ -1838,9 +1936,9 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     if (o.precision != SSTEP_FP64)
         return fail(nullptr, SSTEP_E_UNSUPPORTED, "the allocation-free solve runs in FP64 only");
     if ((o.precond != 0 && o.precond != 1) || (o.p0_mode != 0 && o.p0_mode != 1) || o.max_outer < 0 ||
-        (o.basis != 0 && o.basis != 1))
+        (o.basis != 0 && o.basis != 1) || (o.basis_steps != 0 && o.basis_steps != 1))
         return fail(nullptr, SSTEP_E_ARG, "invalid options");
-    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_RECURRENCE)
+    if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_MOMENTS)
         return fail(nullptr, SSTEP_E_ARG, "unknown gram kind");
     if (!b || !x)
         return fail(nullptr, SSTEP_E_ARG, "b and x must not be NULL");
@@ -1851,7 +1949,7 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     if (has_arrays && A->ptr_space != 1)
         return fail(nullptr, SSTEP_E_ARG, "the allocation-free solve takes operator arrays in device memory");
     int gram_kind = SSTEP_GRAM_STORED_AP;
-    OKCHK(choose_gram_kind(nullptr, A, s, o, &gram_kind));
+    OKCHK(choose_gram_kind(nullptr, A, s, o, &gram_kind, false));
 
     IterArgs it;
     OpDev &op = it.op;
@@ -1879,6 +1977,7 @@ sstep_status noalloc_impl(const sstep_operator *A, int32_t s, int32_t nu, double
     it.fp32 = 0;
     it.p0_mode = o.p0_mode;
     it.monomial = o.basis;
+    it.one_step = o.basis_steps;
     it.s = s;
     it.nu = nu;
     it.theta = 2.0 / (lmax - lmin);

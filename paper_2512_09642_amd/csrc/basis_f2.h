@@ -113,11 +113,17 @@ inline int64_t f2_window_bytes(const Grid3 &g, int kz, int elem)
 // slot index is a constant).
 // MW: waves per SIMD the register allocation must allow (8 = two blocks of
 // 1024 threads per CU).  TXI: interior points of a tile row.
-template <typename T, int EY, bool FIRST, int D, int MW, int TXI>
+// MOM (moments Gram kind): the block also sums, over the points it stores,
+// <q, p_j>, <q, q>, <p_{j+2}, q>, <p_{j+2}, p_{j+2}> (and <p_0, p_0> first
+// when FIRST), unweighted (the constant diagonal is applied afterwards), and
+// writes them to consecutive slots of mpart, stride mstride, at its logical
+// block index.
+template <typename T, int EY, bool FIRST, int D, int MW, int TXI, bool MOM>
 __global__ __launch_bounds__(kF2Lanes *EY, MW) void k_basis_f2(const DevState *__restrict__ st, Grid3 g, T minv,
                                                             const T *__restrict__ pprev, const T *__restrict__ pj,
                                                             T *__restrict__ qout, T *__restrict__ p2out, T theta,
-                                                            T sigma, F2Plan plan)
+                                                            T sigma, F2Plan plan, double *__restrict__ mpart,
+                                                            int64_t mstride)
 {
     constexpr int NT = kF2Lanes * EY;
     constexpr uint32_t ES = sizeof(T);
@@ -180,6 +186,7 @@ __global__ __launch_bounds__(kF2Lanes *EY, MW) void k_basis_f2(const DevState *_
     T pm = buf_load(T(), rj, at(k0 - 2, 0, true, 0, kj_hi));  // p_j one plane below the current one
     T p0 = buf_load(T(), rj, at(k0 - 1, 0, true, 0, kj_hi));  // p_j on the current plane
     T qb = T(0), qc = T(0);  // q two planes and one plane below the current one
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;  // products (MOM)
     // slot u holds, for plane kq = k0 - 1 + u (mod D): p_j on plane kq + 1,
     // p_{j-1} on plane kq and the ring neighbours on plane kq
     T pjs[D], pps[D], rgs[D];
@@ -224,6 +231,19 @@ __global__ __launch_bounds__(kF2Lanes *EY, MW) void k_basis_f2(const DevState *_
                 p2 = two_theta * (minv * y - sigma * qc) - pm;
             }
             buf_store_out(p2, r2, at(kq - 1, 0, interior, k0, k1 - 1));
+            if constexpr (MOM) {
+                // the plane just stored: p_j, q and p_{j+2} of plane kq - 1
+                const bool own = interior && kq - 1 >= k0 && kq - 1 < k1;
+                const double a = own ? static_cast<double>(pm) : 0.0;
+                const double b = own ? static_cast<double>(qc) : 0.0;
+                const double c2 = own ? static_cast<double>(p2) : 0.0;
+                if constexpr (FIRST)
+                    m0 += a * a;
+                m1 += b * a;
+                m2 += b * b;
+                m3 += c2 * b;
+                m4 += c2 * c2;
+            }
             qb = qc;
             qc = q;
             pm = p0;
@@ -235,6 +255,16 @@ __global__ __launch_bounds__(kF2Lanes *EY, MW) void k_basis_f2(const DevState *_
             if constexpr (!FIRST)
                 pps[u] = buf_load(T(), rv, at(kn, 0, true, 0, kv_hi));
             rgs[u] = buf_load(T(), rj, at(kn, off_r, ring, 0, kv_hi));
+        }
+    }
+    if constexpr (MOM) {
+        double *out = mpart + lb;
+        if constexpr (FIRST) {
+            const double v[5] = {m0, m1, m2, m3, m4};
+            block_partials<5, kF2Lanes * EY>(v, out, mstride);
+        } else {
+            const double v[4] = {m1, m2, m3, m4};
+            block_partials<4, kF2Lanes * EY>(v, out, mstride);
         }
     }
 }

@@ -3,6 +3,7 @@
 // Each kernel is persistent: a fixed grid walks a table of tiles, and the work
 // of pairs whose solve has stopped is skipped.  The Gram and FGS kernels of
 // the batched iteration live with the single-system ones (batched_impl.h).
+#include "basis_f2.h"
 #include "launch.h"
 
 namespace sstep {
@@ -211,6 +212,217 @@ __global__ __launch_bounds__(kBlock) void k_bbasis(const BGlob *__restrict__ gl,
     }
 }
 
+// Two basis steps for one pair per block (Sec. 2, Definition, taken twice):
+//   q       = p_{j+1} from p_j and p_{j-1} (from p_0 alone when j = 0)
+//   p_{j+2} = 2 theta (M^{-1} A q - sigma q) - p_j
+// with every value formed by the operations, in the order, of k_bbasis, so
+// the pair equals two single steps bit for bit.  A block owns a band of whole
+// grid rows [y0, y1) of one system and a range of planes [k0, k1), and forms
+// q on the band and on the row below and the row above it (when the grid has
+// them), so that the second step finds every in-plane neighbour in the
+// block; it marches the range in z with the current plane of p_j and of q in
+// LDS and the planes above and below in registers, as the single-system pair
+// kernel does.  Face coefficients are read once per point and plane (the
+// bottom face is the top face of the plane below); the diagonal is summed
+// from them in the order of the face operator.  Logical blocks take the
+// right-hand sides of one band fastest, so the blocks that read the same
+// coefficients run together on one XCD and share them through its L2.
+// Every memory access is a buffer access whose offset leaves the window when
+// the point, plane or row does not exist (see basis_f2.h).
+template <typename T, bool FACES, bool FIRST, int D, int DF, int NT>
+__global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
+                                                  const BF2Tile *__restrict__ tiles, uint32_t nbl, uint32_t per,
+                                                  const DevState *__restrict__ pairs, int nrhs, int precond, int j,
+                                                  T *__restrict__ P)
+{
+    constexpr uint32_t ES = sizeof(T);
+    __shared__ T ps[2][NT];
+    __shared__ T qs[2][NT];
+    if (gl->ndone == gl->npairs)
+        return;
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;  // whole block: no barrier is skipped by part of it
+    const BF2Tile tl = tiles[lb / static_cast<uint32_t>(nrhs)];
+    const int r = static_cast<int>(lb % static_cast<uint32_t>(nrhs));
+    const BSys &S = sys[tl.q];
+    if (pairs[S.pair0 + r].done)
+        return;
+    const int nx = S.g.nx, ny = S.g.ny, nz = S.g.nz;
+    const uint32_t nxy = static_cast<uint32_t>(S.g.nxy);
+    const int tid = threadIdx.x;
+    // rows of the block: the band and the row on each side of it
+    const int ye0 = tl.y0 > 0 ? tl.y0 - 1 : 0;
+    const int ye1 = tl.y1 < ny ? tl.y1 + 1 : ny;
+    const int er = tid / nx;
+    const int i = tid - er * nx;
+    const int ey = ye0 + er;
+    const bool in_dom = ey < ye1;
+    const bool interior = in_dom && ey >= tl.y0 && ey < tl.y1;
+    const bool hw = i > 0, he = i + 1 < nx, hs = ey > ye0, hn = ey + 1 < ye1;
+    // A point of the first or last row of the block reads its one neighbour
+    // outside the block from global memory (0 where the grid ends there).
+    const bool ring_s = in_dom && !hs && ey > 0;
+    const bool ring = ring_s || (in_dom && !hn && ey + 1 < ny);
+    const int off_r = ring_s ? -nx : nx;
+    const uint32_t pl = in_dom ? static_cast<uint32_t>(ey * nx + i) : 0u;
+    const int k0 = tl.k0, k1 = tl.k1;
+    const int kj_hi = k1 + 1 < nz ? k1 + 1 : nz - 1;  // last plane of p_j the range reads
+    const int kv_hi = k1 < nz ? k1 : nz - 1;          // last plane of q, p_{j-1}, ring values, faces
+    const int64_t step = static_cast<int64_t>(nrhs) * S.ld;
+    T *const col = P + S.pofs + static_cast<int64_t>(r) * S.ld + static_cast<int64_t>(j) * step;
+    const uint32_t cbytes = static_cast<uint32_t>(S.n) * ES;
+    const __amdgpu_buffer_rsrc_t rj = make_window(col, cbytes);
+    const __amdgpu_buffer_rsrc_t rv = make_window(FIRST ? col : col - step, cbytes);
+    const __amdgpu_buffer_rsrc_t rq = make_window(col + step, cbytes);
+    const __amdgpu_buffer_rsrc_t r2 = make_window(col + 2 * step, cbytes);
+    // byte offset of the thread's point (+ d in-plane) on plane k, or
+    // kOutside when the point is outside the grid or k outside [0, khi]
+    auto at = [&](int k, int d, bool ok, int klo, int khi) -> uint32_t {
+        return ok && k >= klo && k <= khi ? (static_cast<uint32_t>(k) * nxy + static_cast<uint32_t>(static_cast<int>(pl) + d)) * ES
+                                          : kOutside;
+    };
+    const T *kxp = nullptr, *kyp = nullptr, *kzp = nullptr;
+    if constexpr (FACES) {
+        if constexpr (sizeof(T) == 8)
+            kxp = reinterpret_cast<const T *>(S.kx), kyp = reinterpret_cast<const T *>(S.ky),
+            kzp = reinterpret_cast<const T *>(S.kz);
+        else
+            kxp = reinterpret_cast<const T *>(S.kx32), kyp = reinterpret_cast<const T *>(S.ky32),
+            kzp = reinterpret_cast<const T *>(S.kz32);
+    }
+    // faces: x-faces (nx + 1 per grid row), y-faces (ny + 1 rows of nx per
+    // plane), z-faces (nz + 1 planes)
+    const uint32_t xrow = static_cast<uint32_t>(nx + 1);
+    const __amdgpu_buffer_rsrc_t rfx = make_window(kxp, static_cast<uint32_t>(nz) * ny * xrow * ES);
+    const __amdgpu_buffer_rsrc_t rfy = make_window(kyp, static_cast<uint32_t>(nz) * (ny + 1) * nx * ES);
+    const __amdgpu_buffer_rsrc_t rfz = make_window(kzp, (static_cast<uint32_t>(nz) + 1) * nxy * ES);
+    const uint32_t fx_pl = static_cast<uint32_t>(ey) * xrow + static_cast<uint32_t>(i);
+    const uint32_t fy_pl = static_cast<uint32_t>(ey * nx + i);
+    auto fx_at = [&](int k, int d) -> uint32_t {
+        return in_dom && k >= 0 && k <= kv_hi ? (static_cast<uint32_t>(k) * ny * xrow + fx_pl + d) * ES : kOutside;
+    };
+    auto fy_at = [&](int k, int d) -> uint32_t {
+        return in_dom && k >= 0 && k <= kv_hi ? (static_cast<uint32_t>(k) * (ny + 1) * nx + fy_pl + d) * ES : kOutside;
+    };
+    auto fz_at = [&](int k) -> uint32_t {  // z-face below plane k (k = nz: the top face of the last plane)
+        return in_dom && k >= 0 && k <= kv_hi + 1 ? (static_cast<uint32_t>(k) * nxy + pl) * ES : kOutside;
+    };
+    const T theta = static_cast<T>(S.theta), sigma = static_cast<T>(S.sigma);
+    const T two_theta = T(2) * theta;
+    const T minv_c = precond ? T(1) / T(6) : T(1);
+    T pm = buf_load(T(), rj, at(k0 - 2, 0, in_dom, 0, kj_hi));  // p_j one plane below the current one
+    T p0 = buf_load(T(), rj, at(k0 - 1, 0, in_dom, 0, kj_hi));  // p_j on the current plane
+    T qb = T(0), qc = T(0);  // q two planes and one plane below the current one
+    T fb = T(0);             // bottom face of the current plane
+    if constexpr (FACES)
+        fb = buf_load(T(), rfz, fz_at(k0 - 1));
+    // coefficients of the plane below (the second step's plane)
+    T gw = T(0), ge = T(0), gs = T(0), gn = T(0), gb = T(0), gt = T(0), gd = T(0);
+    // slot u holds, for plane kq = k0 - 1 + u (mod D): p_j on plane kq + 1,
+    // p_{j-1}, the ring neighbour and the faces of plane kq
+    T pjs[D], pps[D], rgs[D];
+    // the faces of plane kq in slot kq - k0 + 1 (mod DF), DF dividing D
+    static_assert(D % DF == 0, "face slots must divide the step unroll");
+    T fws[FACES ? DF : 1], fes[FACES ? DF : 1], fss[FACES ? DF : 1], fns[FACES ? DF : 1], fts[FACES ? DF : 1];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        const int kq = k0 - 1 + u;
+        pjs[u] = buf_load(T(), rj, at(kq + 1, 0, in_dom, 0, kj_hi));
+        pps[u] = FIRST ? T(0) : buf_load(T(), rv, at(kq, 0, in_dom, 0, kv_hi));
+        rgs[u] = buf_load(T(), rj, at(kq, off_r, ring, 0, kv_hi));
+    }
+#pragma unroll
+    for (int u = 0; u < DF; ++u) {
+        const int kq = k0 - 1 + u;
+        if constexpr (FACES) {
+            fws[u] = buf_load(T(), rfx, fx_at(kq, 0));
+            fes[u] = buf_load(T(), rfx, fx_at(kq, 1));
+            fss[u] = buf_load(T(), rfy, fy_at(kq, 0));
+            fns[u] = buf_load(T(), rfy, fy_at(kq, nx));
+            fts[u] = buf_load(T(), rfz, fz_at(kq + 1));
+        }
+    }
+    // planes k0 - 1 .. k1, padded to a multiple of D: a padding step loads
+    // nothing (its offsets lie outside the windows) and stores nothing
+    const int nstep = (k1 - k0 + 2 + D - 1) / D * D;
+    for (int base = k0 - 1; base < k0 - 1 + nstep; base += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int kq = base + u;
+            const int buf = kq & 1;
+            const T pp = pjs[u], pv = pps[u], rg = rgs[u];
+            T fw = T(0), fe = T(0), fs = T(0), fn = T(0), ft = T(0), dinv = minv_c;
+            if constexpr (FACES) {
+                const int f = u % DF;
+                fw = fws[f], fe = fes[f], fs = fss[f], fn = fns[f], ft = fts[f];
+                dinv = precond ? T(1) / (((((fw + fe) + fs) + fn) + fb) + ft) : T(1);
+            }
+            ps[buf][tid] = p0;
+            lds_barrier();
+            T q = T(0);
+            if (in_dom && kq >= 0 && kq <= k1 && kq < nz) {
+                const T w = hw ? ps[buf][tid - 1] : T(0);
+                const T e = he ? ps[buf][tid + 1] : T(0);
+                const T s = hs ? ps[buf][tid - nx] : rg;
+                const T n = hn ? ps[buf][tid + nx] : rg;
+                T y;
+                if constexpr (FACES)
+                    y = fw * (p0 - w) + fe * (p0 - e) + fs * (p0 - s) + fn * (p0 - n) + fb * (p0 - pm) +
+                        ft * (p0 - pp);
+                else
+                    y = T(6) * p0 - (((((w + e) + s) + n) + pm) + pp);
+                if constexpr (FIRST)
+                    q = theta * (dinv * y - sigma * p0);
+                else
+                    q = two_theta * (dinv * y - sigma * p0) - pv;
+            }
+            buf_store_out(q, rq, at(kq, 0, interior, k0, k1 - 1));
+            qs[buf][tid] = q;
+            // the second step on the plane below: q there is in qs[buf ^ 1]
+            // (stored before this plane's barrier), q below it in qb, above in q
+            T p2 = T(0);
+            if (interior) {
+                const T *qp = qs[buf ^ 1];
+                const T w = hw ? qp[tid - 1] : T(0);
+                const T e = he ? qp[tid + 1] : T(0);
+                const T s = hs ? qp[tid - nx] : T(0);
+                const T n = hn ? qp[tid + nx] : T(0);
+                T y;
+                if constexpr (FACES)
+                    y = gw * (qc - w) + ge * (qc - e) + gs * (qc - s) + gn * (qc - n) + gb * (qc - qb) +
+                        gt * (qc - q);
+                else
+                    y = T(6) * qc - (((((w + e) + s) + n) + qb) + q);
+                p2 = two_theta * ((FACES ? gd : minv_c) * y - sigma * qc) - pm;
+            }
+            buf_store_out(p2, r2, at(kq - 1, 0, interior, k0, k1 - 1));
+            qb = qc;
+            qc = q;
+            pm = p0;
+            p0 = pp;
+            if constexpr (FACES) {
+                gw = fw, ge = fe, gs = fs, gn = fn, gb = fb, gt = ft, gd = dinv;
+                fb = ft;
+            }
+            // refill the slot for plane kq + D once its values are used
+            const int kn = kq + D;
+            pjs[u] = buf_load(T(), rj, at(kn + 1, 0, in_dom, 0, kj_hi));
+            if constexpr (!FIRST)
+                pps[u] = buf_load(T(), rv, at(kn, 0, in_dom, 0, kv_hi));
+            rgs[u] = buf_load(T(), rj, at(kn, off_r, ring, 0, kv_hi));
+            if constexpr (FACES) {
+                const int f = u % DF, kf = kq + DF;
+                fws[f] = buf_load(T(), rfx, fx_at(kf, 0));
+                fes[f] = buf_load(T(), rfx, fx_at(kf, 1));
+                fss[f] = buf_load(T(), rfy, fy_at(kf, 0));
+                fns[f] = buf_load(T(), rfy, fy_at(kf, nx));
+                fts[f] = buf_load(T(), rfz, fz_at(kf + 1));
+            }
+        }
+    }
+}
+
 // x += P alpha for every pair whose solve continues.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bupdate(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
@@ -311,6 +523,44 @@ hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st)
     if (a.fp32)
         return a.faces ? bbasis_t<float, true>(a, j, st) : bbasis_t<float, false>(a, j, st);
     return a.faces ? bbasis_t<double, true>(a, j, st) : bbasis_t<double, false>(a, j, st);
+}
+
+namespace {
+template <typename T, bool FACES, int D, int DF, int NT>
+hipError_t bbasis_pair_v(const BatchArgs &a, int j, hipStream_t st)
+{
+    const dim3 grid(a.f2per * kNumXcd);
+    const uint32_t nbl = static_cast<uint32_t>(a.nf2) * static_cast<uint32_t>(a.nrhs);
+    T *P = static_cast<T *>(a.P);
+    if (j == 0)
+        hipLaunchKernelGGL((k_bbasis_f2<T, FACES, true, D, DF, NT>), grid, dim3(NT), 0, st, a.gl, a.sys,
+                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P);
+    else
+        hipLaunchKernelGGL((k_bbasis_f2<T, FACES, false, D, DF, NT>), grid, dim3(NT), 0, st, a.gl, a.sys,
+                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P);
+    return hipGetLastError();
+}
+template <typename T, bool FACES>
+hipError_t bbasis_pair_t(const BatchArgs &a, int j, hipStream_t st)
+{
+    constexpr int D = sizeof(T) == 8 ? 2 : 4;
+    if (a.f2nt == 512)
+        return a.f2df == 1 ? bbasis_pair_v<T, FACES, D, 1, 512>(a, j, st) : bbasis_pair_v<T, FACES, D, D, 512>(a, j, st);
+    if (a.f2nt == 256)
+        return a.f2df == 1 ? bbasis_pair_v<T, FACES, D, 1, 256>(a, j, st) : bbasis_pair_v<T, FACES, D, D, 256>(a, j, st);
+    return a.f2df == 1 ? bbasis_pair_v<T, FACES, D, 1, 1024>(a, j, st) : bbasis_pair_v<T, FACES, D, D, 1024>(a, j, st);
+}
+}  // namespace
+
+// Steps j and j + 1 of every active pair's basis (recurrence Gram kind, the
+// band table built on the host).
+hipError_t launch_bbasis_pair(const BatchArgs &a, int j, hipStream_t st)
+{
+    if (!a.f2 || j < 0 || j + 2 > a.s)
+        return hipErrorInvalidValue;
+    if (a.fp32)
+        return a.faces ? bbasis_pair_t<float, true>(a, j, st) : bbasis_pair_t<float, false>(a, j, st);
+    return a.faces ? bbasis_pair_t<double, true>(a, j, st) : bbasis_pair_t<double, false>(a, j, st);
 }
 
 hipError_t launch_bupdate(const BatchArgs &a, hipStream_t st)

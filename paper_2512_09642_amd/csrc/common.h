@@ -87,9 +87,35 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Block sums of NV per-thread values in a fixed order (each wave by
+// butterfly, then the waves in order); value u goes to out[u * stride].
+// Every thread of the block must call it.
+template <int NV, int NT>
+__device__ __forceinline__ void block_partials(const double (&v)[NV], double *__restrict__ out, int64_t stride)
+{
+    constexpr int NW = NT / kWave;
+    __shared__ double part[NW][NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const double t = wave_sum(v[u]);
+        if (threadIdx.x % kWave == 0)
+            part[threadIdx.x / kWave][u] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double acc = 0.0;
+        for (int w = 0; w < NW; ++w)
+            acc += part[w][threadIdx.x];
+        out[threadIdx.x * stride] = acc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Operators.  apply() returns the centre value p_c, y = (A p)_c and the
-// Jacobi factor M^{-1}_cc (1 without preconditioning).
+// Jacobi factor M^{-1}_cc (1 without preconditioning); apply_w() also the
+// weight of the M inner product at c: the diagonal a_cc with Jacobi, 1
+// without, and 1 for the constant-coefficient stencils, whose constant
+// diagonal the caller applies afterwards.
 // ---------------------------------------------------------------------------
 
 // Constant-coefficient 7-point Poisson operator: diagonal 6, off-diagonal -1.
@@ -98,6 +124,11 @@ struct OpPoisson7 {
     Grid3 g;
     T minv;  // 1/6 with Jacobi, 1 without
 
+    __device__ __forceinline__ void apply_w(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv, T &wt) const
+    {
+        apply(p, c, pc, y, dinv);
+        wt = T(1);
+    }
     __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
     {
         const uint32_t q = fdiv(static_cast<uint32_t>(c), g.dx);  // j + ny*k
@@ -124,6 +155,11 @@ struct OpPoisson27 {
     Grid3 g;
     T minv;  // 1/26 with Jacobi, 1 without
 
+    __device__ __forceinline__ void apply_w(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv, T &wt) const
+    {
+        apply(p, c, pc, y, dinv);
+        wt = T(1);
+    }
     __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
     {
         const uint32_t q = fdiv(static_cast<uint32_t>(c), g.dx);
@@ -171,6 +207,11 @@ struct OpFaces7 {
 
     __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
     {
+        T wt;
+        apply_w(p, c, pc, y, dinv, wt);
+    }
+    __device__ __forceinline__ void apply_w(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv, T &wt) const
+    {
         const uint32_t q = fdiv(static_cast<uint32_t>(c), g.dx);
         const uint32_t i = static_cast<uint32_t>(c) - q * g.nx;
         const uint32_t k = fdiv(q, g.dy);
@@ -188,7 +229,9 @@ struct OpFaces7 {
         const T b = k > 0 ? p[c - g.nxy] : T(0);
         const T t = k + 1 < static_cast<uint32_t>(g.nz) ? p[c + g.nxy] : T(0);
         y = fw * (pc - w) + fe * (pc - e) + fs * (pc - s) + fn * (pc - n) + fb * (pc - b) + ft * (pc - t);
-        dinv = precond ? T(1) / (((((fw + fe) + fs) + fn) + fb) + ft) : T(1);
+        const T d = ((((fw + fe) + fs) + fn) + fb) + ft;
+        dinv = precond ? T(1) / d : T(1);
+        wt = precond ? d : T(1);
     }
 };
 
@@ -200,6 +243,11 @@ struct OpCsr {
     const T *__restrict__ val;
     const T *__restrict__ invd;  // M^{-1} diagonal (all ones without preconditioning)
 
+    __device__ __forceinline__ void apply_w(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv, T &wt) const
+    {
+        apply(p, c, pc, y, dinv);
+        wt = T(1) / dinv;
+    }
     __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
     {
         const int32_t k0 = rp[c], k1 = rp[c + 1];
@@ -235,6 +283,11 @@ struct OpEll {
 
     __device__ __forceinline__ void apply(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv) const
     {
+        T wt;
+        apply_w(p, c, pc, y, dinv, wt);
+    }
+    __device__ __forceinline__ void apply_w(const T *__restrict__ p, int64_t c, T &pc, T &y, T &dinv, T &wt) const
+    {
         const int64_t q = c / kEllSlice;
         const int64_t o0 = off[q];
         const int w = static_cast<int>((off[q + 1] - o0) / kEllSlice);
@@ -264,6 +317,7 @@ struct OpEll {
             dinv = precond ? T(1) / diag : T(1);
         else
             dinv = invd[c];
+        wt = precond ? diag : T(1);
     }
 };
 

@@ -17,6 +17,8 @@ template <int S>
 hipError_t fgs_launch_s(const IterArgs &a, hipStream_t st);
 template <int S>
 hipError_t fgs_rec_launch_s(const IterArgs &a, hipStream_t st);
+template <int S>
+hipError_t fgs_mom_launch_s(const IterArgs &a, hipStream_t st);
 template <typename T, int S>
 hipError_t gram_sym_launch_s(const IterArgs &a, hipStream_t st);
 template <typename T, int S>

@@ -194,23 +194,16 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs(DevState *__restrict__ st, 
 // diagonal (6, 26 or 1) when the kernel did not weight by M itself.  The
 // block writes G_raw (lower triangle) and c' for the s columns into LDS in
 // the layout of k_fgs, then wave 0 runs fgs_wave.
+// The block's part after h (LDS, the layout above) is filled and synchronised.
 template <int s>
-__global__ __launch_bounds__(kFgsThreads) void k_fgs_rec(DevState *__restrict__ st, const double *__restrict__ sums,
-                                                         int nu, double cscale, int fp32, double inv_sqrt_n,
-                                                         double *__restrict__ dbg, double *__restrict__ hist,
-                                                         int hist_cap, double theta, double sigma, double hscale,
-                                                         int monomial)
+__device__ __forceinline__ void fgs_rec_from_h(DevState *__restrict__ st, const double *h, int nu, double cscale,
+                                               int fp32, double inv_sqrt_n, double *__restrict__ dbg,
+                                               double *__restrict__ hist, int hist_cap, double theta, double sigma,
+                                               double hscale, int monomial)
 {
-    if (st->done)
-        return;
     constexpr int S1 = s + 1;
-    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
     constexpr int T0 = s * (s + 1) / 2;
-    __shared__ double h[E1];
     __shared__ double sg[T0 + s];
-    for (int t = threadIdx.x; t < E1; t += kFgsThreads)
-        h[t] = sums[t];
-    __syncthreads();
     auto H = [&](int a, int b) { return a >= b ? h[tri_index(a, b)] : h[tri_index(b, a)]; };
     for (int e = threadIdx.x; e < T0; e += kFgsThreads) {
         int i = 0;
@@ -235,6 +228,70 @@ __global__ __launch_bounds__(kFgsThreads) void k_fgs_rec(DevState *__restrict__ 
 }
 
 template <int s>
+__global__ __launch_bounds__(kFgsThreads) void k_fgs_rec(DevState *__restrict__ st, const double *__restrict__ sums,
+                                                         int nu, double cscale, int fp32, double inv_sqrt_n,
+                                                         double *__restrict__ dbg, double *__restrict__ hist,
+                                                         int hist_cap, double theta, double sigma, double hscale,
+                                                         int monomial)
+{
+    if (st->done)
+        return;
+    constexpr int S1 = s + 1;
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    __shared__ double h[E1];
+    for (int t = threadIdx.x; t < E1; t += kFgsThreads)
+        h[t] = sums[t];
+    __syncthreads();
+    fgs_rec_from_h<s>(st, h, nu, cscale, fp32, inv_sqrt_n, dbg, hist, hist_cap, theta, sigma, hscale, monomial);
+}
+
+// The Gram matrix of the Chebyshev basis from its moments.  With
+// X = theta (M^{-1} A - sigma I), p_i = T_i(X) p_0 (Sec. 2, Definition) and M X
+// symmetric, the product rule of Chebyshev polynomials, T_i T_j =
+// (T_{i+j} + T_{|i-j|}) / 2, gives
+//     H_ij = <p_i, M p_j> = (mu_{i+j} + mu_{|i-j|}) / 2,  mu_k = <p_0, M T_k(X) p_0>,
+// and taking (i, j) = (i, i) and (i, i-1):
+//     mu_0 = d_0, mu_1 = e_1, mu_2i = 2 d_i - mu_0, mu_{2i-1} = 2 e_i - mu_1,
+// so the 2s + 1 products d_i, e_i fix all of H (p_0 .. p_s), and the
+// right-hand side c'_i = <p_i, M p_0> = mu_i.  The block forms h in the
+// recurrence kind's layout and continues as k_fgs_rec.
+template <int s>
+__global__ __launch_bounds__(kFgsThreads) void k_fgs_mom(DevState *__restrict__ st, const double *__restrict__ sums,
+                                                         int nu, double cscale, int fp32, double inv_sqrt_n,
+                                                         double *__restrict__ dbg, double *__restrict__ hist,
+                                                         int hist_cap, double theta, double sigma, double hscale)
+{
+    if (st->done)
+        return;
+    constexpr int S1 = s + 1;
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    __shared__ double mu[2 * s + 1];
+    __shared__ double h[E1];
+    for (int k = threadIdx.x; k <= 2 * s; k += kFgsThreads) {
+        double m;
+        if (k <= 1)
+            m = sums[k];
+        else if (k % 2 == 0)
+            m = 2.0 * sums[k] - sums[0];
+        else
+            m = 2.0 * sums[k] - sums[1];
+        mu[k] = m;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < S1 * (S1 + 1) / 2; e += kFgsThreads) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= e)
+            ++i;
+        const int j = e - i * (i + 1) / 2;
+        h[e] = 0.5 * (mu[i + j] + mu[i - j]);
+    }
+    for (int i = threadIdx.x; i < S1; i += kFgsThreads)
+        h[S1 * (S1 + 1) / 2 + i] = mu[i];
+    __syncthreads();
+    fgs_rec_from_h<s>(st, h, nu, cscale, fp32, inv_sqrt_n, dbg, hist, hist_cap, theta, sigma, hscale, 0);
+}
+
+template <int s>
 hipError_t fgs_rec_launch_s(const IterArgs &a, hipStream_t st)
 {
     constexpr int S1 = s + 1;
@@ -242,6 +299,14 @@ hipError_t fgs_rec_launch_s(const IterArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_partial_sums<S1>, dim3(E1), dim3(kSumThreads), 0, st, a.st, a.gpart, a.nbg, a.gsum);
     hipLaunchKernelGGL(k_fgs_rec<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.gsum, a.nu, a.cscale, a.fp32,
                        a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap, a.theta, a.sigma, a.rec_hscale, a.monomial);
+    return hipGetLastError();
+}
+
+template <int s>
+hipError_t fgs_mom_launch_s(const IterArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fgs_mom<s>, dim3(1), dim3(kFgsThreads), 0, st, a.st, a.gsum, a.nu, a.cscale, a.fp32,
+                       a.inv_sqrt_n, a.dbg, a.hist, a.hist_cap, a.theta, a.sigma, a.rec_hscale);
     return hipGetLastError();
 }
 

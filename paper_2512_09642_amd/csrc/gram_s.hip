@@ -27,6 +27,7 @@ template hipError_t bfgs_launch_s<SSTEP_S>(const BatchArgs &, hipStream_t);
 template hipError_t gram_sym_launch_s<double, SSTEP_S>(const IterArgs &, hipStream_t);
 template hipError_t gram_sym_launch_s<float, SSTEP_S>(const IterArgs &, hipStream_t);
 template hipError_t fgs_rec_launch_s<SSTEP_S>(const IterArgs &, hipStream_t);
+template hipError_t fgs_mom_launch_s<SSTEP_S>(const IterArgs &, hipStream_t);
 template hipError_t bgram_sym_launch_s<double, SSTEP_S>(const BatchArgs &, hipStream_t);
 template hipError_t bgram_sym_launch_s<float, SSTEP_S>(const BatchArgs &, hipStream_t);
 template hipError_t bfgs_rec_launch_s<SSTEP_S>(const BatchArgs &, hipStream_t);

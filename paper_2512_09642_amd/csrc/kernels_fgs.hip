@@ -1,8 +1,50 @@
 // Dispatch of the Gram, FGS and batched launches to the instantiation for the
 // basis width s (one object per width, see dispatch.h).
 #include "dispatch.h"
+#include "stop.h"
 
 namespace sstep {
+
+namespace {
+// Moments kind: the basis kernels leave, per logical block, the M inner
+// products d_i = <p_i, M p_i> (slot 2i, i = 0..s) and e_i = <p_i, M p_{i-1}>
+// (slot 2i - 1, i = 1..s); slot k holds cnt[k] block partials at
+// part + k * stride.  One block per slot sums them in a fixed order (as
+// k_partial_sums does).
+__global__ __launch_bounds__(kSumThreads) void k_mom_sums(const DevState *__restrict__ st,
+                                                          const double *__restrict__ part,
+                                                          const int32_t *__restrict__ cnt, int64_t stride,
+                                                          double *__restrict__ sums)
+{
+    __shared__ double wpart[kSumThreads / kWave];
+    if (st->done)
+        return;
+    const int k = blockIdx.x;
+    const double *src = part + static_cast<int64_t>(k) * stride;
+    const int nb = cnt[k];
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kSumThreads)
+        acc += src[q];
+    acc = wave_sum(acc);
+    if (threadIdx.x % kWave == 0)
+        wpart[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int w = 0; w < kSumThreads / kWave; ++w)
+            v += wpart[w];
+        sums[k] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mom_sums(const IterArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mom_sums, dim3(2 * a.s + 1), dim3(kSumThreads), 0, st, a.st, a.mpart, a.mcnt, a.mstride,
+                       a.gsum);
+    return hipGetLastError();
+}
 
 #define SSTEP_CASES_1_16(F) \
     F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)
@@ -14,6 +56,8 @@ namespace sstep {
 
 hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 {
+    if (a.gram_mom)  // the basis kernels formed the products: only their sums remain
+        return launch_mom_sums(a, st);
     if (a.gram_rec) {
 #define SSTEP_GS(S)                                                                          \
     case S:                                                                                  \
@@ -37,6 +81,13 @@ hipError_t launch_gram(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_fgs(const IterArgs &a, hipStream_t st)
 {
+    if (a.gram_mom) {
+#define SSTEP_FM(S) \
+    case S:         \
+        return fgs_mom_launch_s<S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_FM) SSTEP_CASES_17_31(SSTEP_FM) default: return hipErrorInvalidValue; }
+#undef SSTEP_FM
+    }
     if (a.gram_rec) {
 #define SSTEP_FR(S) \
     case S:         \

@@ -185,6 +185,48 @@ __global__ __launch_bounds__(kBlock) void k_basis(const DevState *__restrict__ s
     }
 }
 
+// The same step for the moments Gram kind (no AP): besides p_{j+1}, block
+// partials of the M inner products that fix the Gram matrix (fgs_core.h,
+// k_fgs_mom): <p_{j+1}, M p_j> and <p_{j+1}, M p_{j+1}>, and <p_0, M p_0>
+// first when j = 0, written to consecutive slots of mpart (stride mstride),
+// one value per logical block.  The threads past n take part in the block
+// sums with weight 0.
+template <class Op, typename T, int STEP>
+__global__ __launch_bounds__(kBlock) void k_basis_mom(const DevState *__restrict__ st, Op op,
+                                                      const T *__restrict__ pj, const T *__restrict__ pprev,
+                                                      T *__restrict__ pnext, T theta, T sigma, int64_t n,
+                                                      uint32_t per, uint32_t nbl, double *__restrict__ mpart,
+                                                      int64_t mstride)
+{
+    static_assert(STEP == 0 || STEP == 1, "the moments kind forms every column");
+    if (st->done)
+        return;
+    const uint32_t lb = xcd_block(blockIdx.x, per);
+    if (lb >= nbl)
+        return;  // whole block
+    const int64_t c = static_cast<int64_t>(lb) * kBlock + threadIdx.x;
+    const bool valid = c < n;
+    const int64_t cc = valid ? c : n - 1;
+    T pc, y, dinv, wt;
+    op.apply_w(pj, cc, pc, y, dinv, wt);
+    T pn;
+    if constexpr (STEP == 0)
+        pn = theta * (dinv * y - sigma * pc);
+    else
+        pn = T(2) * theta * (dinv * y - sigma * pc) - __builtin_nontemporal_load(pprev + cc);
+    if (valid)
+        pnext[c] = pn;
+    const double w = valid ? static_cast<double>(wt) : 0.0;
+    const double a = static_cast<double>(pn), b = static_cast<double>(pc);
+    if constexpr (STEP == 0) {
+        const double v[3] = {w * b * b, w * a * b, w * a * a};
+        block_partials<3, kBlock>(v, mpart + lb, mstride);
+    } else {
+        const double v[2] = {w * a * b, w * a * a};
+        block_partials<2, kBlock>(v, mpart + lb, mstride);
+    }
+}
+
 // The same step for the constant Poisson operator in FP64 (nx even): a thread
 // owns two consecutive x-points and KZ = 8 consecutive z-planes, so the +-z
 // neighbours come from registers (one 16-byte load per plane instead of
@@ -554,6 +596,18 @@ hipError_t basis_for(const IterArgs &a, const Op &op, int j, int step, hipStream
     T *apj = AP ? AP + j * a.ld : nullptr;
     T *pnext = j + 1 < a.s || a.gram_rec ? P + (j + 1) * a.ld : nullptr;
     const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
+    if (a.gram_mom) {
+        if (step == 2)
+            return hipErrorInvalidValue;
+        double *mp = a.mpart + static_cast<int64_t>(mom_slot(j)) * a.mstride;
+        if (step == 0)
+            hipLaunchKernelGGL((k_basis_mom<Op, T, 0>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev,
+                               pnext, theta, sigma, a.op.n, l.per, l.nbl, mp, a.mstride);
+        else
+            hipLaunchKernelGGL((k_basis_mom<Op, T, 1>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev,
+                               pnext, theta, sigma, a.op.n, l.per, l.nbl, mp, a.mstride);
+        return hipGetLastError();
+    }
     if (step == 2)
         hipLaunchKernelGGL((k_basis<Op, T, 2>), dim3(l.grid), dim3(kBlock), 0, st, a.st, op, pj, pprev, apj, pnext,
                            theta, sigma, a.op.n, l.per, l.nbl);
@@ -623,7 +677,7 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
     switch (a.op.kind) {
     case kOpPoisson:
         if constexpr (sizeof(T) == 8)
-            if (a.op.g.nx % 2 == 0)
+            if (a.op.g.nx % 2 == 0 && !a.gram_mom)
                 return basis_poisson_pairs(a, j, step, st);
         return basis_for<OpPoisson7<T>, T>(a, make_poisson<T>(a.op), j, step, st);
     case kOpFaces:
@@ -640,18 +694,20 @@ hipError_t basis_t(const IterArgs &a, int j, int step, hipStream_t st)
 // Two basis steps per launch (basis_f2.h) for the constant 7-point operator,
 // shapes measured fastest on MI355X at 224^3: FP64 56-point tile rows
 // (64-byte aligned stores), 3 planes of loads in flight; FP32 62-point rows,
-// 6 planes.  Ranges of 28 planes give 2 blocks per CU in one wave there;
+// 6 planes.  With the moments Gram kind the products' FP64 accumulators take
+// registers, and DM planes in flight (2 and 3) are the most that keep the
+// kernel within 64 registers without spilling.  Ranges of 28 planes give 2 blocks per CU in one wave there;
 // smaller grids take thinner ranges to keep some 512 blocks.
 constexpr int kF2Rows = 16;
 template <typename T>
 struct F2Shape;
 template <>
 struct F2Shape<double> {
-    static constexpr int D = 3, TXI = 56;
+    static constexpr int D = 3, TXI = 56, DM = 2;
 };
 template <>
 struct F2Shape<float> {
-    static constexpr int D = 6, TXI = 62;
+    static constexpr int D = 6, TXI = 62, DM = 3;
 };
 
 template <typename T>
@@ -675,7 +731,7 @@ bool f2_fits(const IterArgs &a)
 // operator when AP is not stored (recurrence and operator-applying Gram kinds).
 bool basis_pairs_apply(const IterArgs &a)
 {
-    if (a.op.kind != kOpPoisson || a.AP || a.monomial)
+    if (a.op.kind != kOpPoisson || a.AP || a.monomial || a.one_step)
         return false;
     return a.fp32 ? f2_fits<float>(a) : f2_fits<double>(a);
 }
@@ -688,7 +744,7 @@ int basis_columns(const IterArgs &a) { return a.gram_op ? a.s - 1 : a.s; }
 template <typename T>
 hipError_t basis_pair(const IterArgs &a, int j, hipStream_t st)
 {
-    constexpr int D = F2Shape<T>::D, TXI = F2Shape<T>::TXI;
+    constexpr int D = F2Shape<T>::D, TXI = F2Shape<T>::TXI, DM = F2Shape<T>::DM;
     const F2Plan plan = f2_plan<T>(a.op.g);
     T *P = static_cast<T *>(a.P);
     const T *pprev = j > 0 ? P + (j - 1) * a.ld : nullptr;
@@ -697,12 +753,21 @@ hipError_t basis_pair(const IterArgs &a, int j, hipStream_t st)
     const T minv = a.op.precond ? T(1) / T(6) : T(1);
     const T theta = static_cast<T>(a.theta), sigma = static_cast<T>(a.sigma);
     const dim3 grid(plan.per * kNumXcd), block(kF2Lanes * kF2Rows);
-    if (j == 0)
-        hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, true, D, 8, TXI>), grid, block, 0, st, a.st, a.op.g, minv, pprev,
-                           pj, q, p2, theta, sigma, plan);
-    else
-        hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, false, D, 8, TXI>), grid, block, 0, st, a.st, a.op.g, minv,
-                           pprev, pj, q, p2, theta, sigma, plan);
+    double *mp = a.gram_mom ? a.mpart + static_cast<int64_t>(mom_slot(j)) * a.mstride : nullptr;
+    if (a.gram_mom) {
+        if (j == 0)
+            hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, true, DM, 8, TXI, true>), grid, block, 0, st, a.st, a.op.g,
+                               minv, pprev, pj, q, p2, theta, sigma, plan, mp, a.mstride);
+        else
+            hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, false, DM, 8, TXI, true>), grid, block, 0, st, a.st, a.op.g,
+                               minv, pprev, pj, q, p2, theta, sigma, plan, mp, a.mstride);
+    } else if (j == 0) {
+        hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, true, D, 8, TXI, false>), grid, block, 0, st, a.st, a.op.g, minv,
+                           pprev, pj, q, p2, theta, sigma, plan, mp, a.mstride);
+    } else {
+        hipLaunchKernelGGL((k_basis_f2<T, kF2Rows, false, D, 8, TXI, false>), grid, block, 0, st, a.st, a.op.g,
+                           minv, pprev, pj, q, p2, theta, sigma, plan, mp, a.mstride);
+    }
     return hipGetLastError();
 }
 
@@ -912,9 +977,33 @@ hipError_t launch_basis_all(const IterArgs &a, hipStream_t st)
     return e;
 }
 
+void mom_layout(const IterArgs &a, int32_t *cnt, int64_t *stride)
+{
+    const int m = basis_columns(a);
+    int64_t mx = 0;
+    auto put = [&](int j, int ncols, int64_t nbl) {
+        const int first = mom_slot(j);
+        const int nslot = (j == 0 ? 1 : 0) + 2 * ncols;
+        for (int k = first; k < first + nslot; ++k)
+            cnt[k] = static_cast<int32_t>(nbl);
+        mx = std::max(mx, nbl);
+    };
+    int j = 0;
+    if (basis_pairs_apply(a)) {
+        const int64_t nbl = a.fp32 ? f2_plan<float>(a.op.g).nbl : f2_plan<double>(a.op.g).nbl;
+        for (; j + 2 <= m; j += 2)
+            put(j, 2, nbl);
+    }
+    for (; j < m; ++j)
+        put(j, 1, plan_points(a.op.n).nbl);
+    *stride = mx;
+}
+
 hipError_t launch_product(const IterArgs &a, int j, hipStream_t st)
 {
-    return a.fp32 ? basis_t<float>(a, j, 2, st) : basis_t<double>(a, j, 2, st);
+    IterArgs p = a;  // A p_j alone: no products for the moments kind
+    p.gram_mom = 0;
+    return a.fp32 ? basis_t<float>(p, j, 2, st) : basis_t<double>(p, j, 2, st);
 }
 
 hipError_t launch_update(const IterArgs &a, hipStream_t st)

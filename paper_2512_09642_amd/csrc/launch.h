@@ -56,6 +56,7 @@ struct IterArgs {
     int fp32 = 0;     // 1 = FP32 basis / SpMV / Gram
     int p0_mode = 0;  // 0: p_0 = M^{-1} r, 1: p_0 = r
     int monomial = 0; // 1: monomial basis p_{j+1} = M^{-1} A p_j instead of Chebyshev
+    int one_step = 0; // 1: one basis step per launch even where two fit
     int s = 0, nu = 0;
     double theta = 0, sigma = 0;
     void *P = nullptr;   // n x s, column-major, leading dimension ld
@@ -91,6 +92,13 @@ struct IterArgs {
     int gram_rec = 0;
     int rec_wap = 0;          // the Gram kernel weights by the M diagonal array
     double rec_hscale = 1.0;  // constant M diagonal applied by the FGS kernel otherwise
+    // Moments kind (also gram_rec): no Gram kernel; the basis kernels write
+    // block partials of <p_i, M p_i> (slot 2i) and <p_i, M p_{i-1}> (slot
+    // 2i - 1), slot k at mpart + k * mstride with mcnt[k] of them
+    int gram_mom = 0;
+    double *mpart = nullptr;
+    int32_t *mcnt = nullptr;
+    int64_t mstride = 0;
 };
 
 // Debug block layout written by the FGS kernel.
@@ -130,6 +138,14 @@ struct PTile {  // kBlock points of one system (basis)
 struct GTile {  // chunk of one pair (Gram)
     int32_t q, chunk, r, pad;
 };
+// Two basis steps per launch (recurrence Gram kind): a band of whole grid
+// rows [y0, y1) of system q over the planes [k0, k1); the block also forms
+// the first step on the row below and the row above the band.
+struct BF2Tile {
+    int32_t q, y0, y1, k0, k1, pad;
+};
+constexpr int kBf2Threads = 1024;  // threads per block of the two-step batched basis
+constexpr int kBf2Planes = 16;     // planes per z-range it aims for
 struct BGlob {
     int32_t ndone, npairs;
 };
@@ -154,11 +170,17 @@ struct BatchArgs {
     // rec_hscale M = const), the FGS kernel maps H onto P^T A P
     int rec = 0, rec_wap = 0;
     double rec_hscale = 1.0;
+    // two basis steps per launch (f2 = 1): nf2 bands x nrhs logical blocks,
+    // f2per of them per XCD
+    int f2 = 0, nf2 = 0, f2nt = kBf2Threads, f2df = 2;
+    uint32_t f2per = 0;
+    const BF2Tile *f2tiles = nullptr;
 };
 
 hipError_t launch_bresidual(const BatchArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_bp0scale(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st);
+hipError_t launch_bbasis_pair(const BatchArgs &a, int j, hipStream_t st);
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bupdate(const BatchArgs &a, hipStream_t st);
@@ -219,6 +241,14 @@ hipError_t launch_ell_fill_val(const OpDev &op, const float *val, float *ev, hip
 // The whole basis p_1 .. p_m of one outer iteration: two steps per launch
 // for the constant 7-point operator without stored AP, else one per launch.
 hipError_t launch_basis_all(const IterArgs &a, hipStream_t st);
+// Moments kind: the basis launch that starts at column j writes its products
+// from slot 0 (j = 0: <p_0,Mp_0>, <p_1,Mp_0>, <p_1,Mp_1>, ...) or from slot
+// 2j + 1 (<p_{j+1},Mp_j>, <p_{j+1},Mp_{j+1}>, ...).  mom_layout gives the
+// block count each of the 2s + 1 slots receives from the launches
+// launch_basis_all makes, and the largest.
+inline int mom_slot(int j) { return j == 0 ? 0 : 2 * j + 1; }
+void mom_layout(const IterArgs &a, int32_t *cnt, int64_t *stride);
+hipError_t launch_mom_sums(const IterArgs &a, hipStream_t st);
 // Launches launch_basis_all makes, and (if pairs is not NULL) how many of
 // them form two columns.
 int basis_kernel_count(const IterArgs &a, int *pairs);

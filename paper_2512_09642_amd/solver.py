@@ -133,7 +133,7 @@ class Solver:
     def __init__(self, op: Operator, s: int, nu: int, lmin: float, lmax: float, *, precision: str = "fp64",
                  precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
                  record_history: bool = False, autotune: bool = True, gram: str = "auto", basis: str = "chebyshev",
-                 stream=None):
+                 basis_steps: int = 0, stream=None):
         self._lib = N.load()
         self.op = op
         self.s, self.nu, self.lmin, self.lmax = s, nu, lmin, lmax
@@ -149,6 +149,7 @@ class Solver:
         opt.autotune = 1 if autotune else 0
         opt.gram = N.GRAM_KINDS[gram]
         opt.basis = {"chebyshev": 0, "monomial": 1}[basis]
+        opt.basis_steps = basis_steps
         self._stream = stream
         opt.stream = self._stream_ptr()
         self.max_outer = max_outer
@@ -315,7 +316,7 @@ class BatchedSolver:
 
     def __init__(self, ops: list, nrhs: int, s: int, nu: int, lmin, lmax, *, precision: str = "fp64",
                  precond: bool = True, p0_mode: int = 0, max_outer: int = 10000, graph_chunk: int = 4,
-                 autotune: bool = True, gram: str = "auto", stream=None):
+                 autotune: bool = True, gram: str = "auto", basis_steps: int = 0, stream=None):
         self._lib = N.load()
         self.ops = list(ops)
         self.nsys = len(self.ops)
@@ -330,6 +331,7 @@ class BatchedSolver:
         opt.graph_chunk = graph_chunk
         opt.autotune = 1 if autotune else 0
         opt.gram = N.GRAM_KINDS[gram]
+        opt.basis_steps = basis_steps
         self._stream = stream
         opt.stream = stream.cuda_stream if stream is not None else (
             torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None)
@@ -351,6 +353,10 @@ class BatchedSolver:
         _check(self._lib.sstep_batched_tiles(ctx, C.byref(rows), C.byref(factor)), ctx)
         #: the tile schedule: rows per chunk tile and persistent blocks per compute unit
         self.tiles = {"rows_per_tile": int(rows.value), "grid_factor": int(factor.value)}
+        pairs = C.c_int32(0)
+        #: kernel launches per basis and how many of them form two columns
+        self.basis_launches = int(self._lib.sstep_basis_launches(ctx, C.byref(pairs)))
+        self.basis_pairs = int(pairs.value)
 
     def close(self):
         if getattr(self, "_ctx", None):

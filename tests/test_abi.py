@@ -122,9 +122,10 @@ def test_batched_entry_points_report_status(native):
 
 def test_setup_rejects_unavailable_gram_kinds(native):
     """The operator-applying Gram kernel needs a stencil operator, s <= 16 and
-    columns under 4 GiB, the recurrence kind s <= 31; asking for them
-    otherwise is unsupported, an unknown kind is an argument error.  Checked
-    before any device work."""
+    columns under 4 GiB, the recurrence kind s <= 31, the moments kind s <= 31
+    with the Chebyshev basis and p_0 = M^{-1} r (or no preconditioner); asking
+    for them otherwise is unsupported, an unknown kind or option value is an
+    argument error.  Checked before any device work."""
     lib = native.load()
 
     def setup(op, s, gram):
@@ -149,6 +150,27 @@ def test_setup_rejects_unavailable_gram_kinds(native):
     # 820^3 doubles per column exceed the kernel's 32-bit byte offsets
     st, ctx = setup(_poisson(native, 820, 820, 820), 4, apply_op)
     assert st == 7 and not ctx.value
+    # the moments kind: s <= 31, the Chebyshev basis, and c = P^T r in the M
+    # inner product (p_0 = M^{-1} r, or no preconditioner)
+    moments = native.GRAM_KINDS["moments"]
+    st, ctx = setup(_poisson(native), 32, moments)
+    assert st == 7 and not ctx.value
+
+    def setup_opts(**kw):
+        opt = native.Options()
+        lib.sstep_default_options(C.byref(opt))
+        opt.gram = moments
+        for k, v in kw.items():
+            setattr(opt, k, v)
+        ctx = C.c_void_p()
+        return lib.sstep_setup(C.byref(ctx), C.byref(_poisson(native)), 8, 5, 0.1, 1.9, C.byref(opt)), ctx
+
+    st, ctx = setup_opts(p0_mode=1)
+    assert st == 7 and not ctx.value
+    st, ctx = setup_opts(basis=1)
+    assert st == 7 and not ctx.value
+    st, ctx = setup_opts(basis_steps=2)
+    assert st == 1 and not ctx.value
 
 
 def test_missing_library_fails_loudly(native, monkeypatch, tmp_path):

@@ -20,6 +20,8 @@ def test_basis_vectors_single_steps():
     assert bench.basis_vectors(4, "apply") == 8
     # recurrence kind, s = 4: p1 (2), p2, p3, p4 (3 each) = 11 = 3s - 1
     assert bench.basis_vectors(4, "recurrence") == 11
+    # the moments kind forms the same columns
+    assert bench.basis_vectors(4, "moments") == 11
 
 
 def test_basis_vectors_pairs():
@@ -40,9 +42,21 @@ def test_basis_vectors_pairs():
     ("recurrence", 0, 32 + 8 * (1 + 47 + 17 + 16)),
     ("recurrence", 8, 32 + 8 * (1 + 31 + 17 + 16)),
     ("apply", 7, 32 + 8 * (1 + 30 + 16 + 16)),
+    # moments: no Gram pass over the columns
+    ("moments", 8, 32 + 8 * (1 + 31 + 0 + 16)),
 ])
 def test_stencil_bytes_per_outer(kind, pairs, expect):
     assert bench.stencil_bytes_per_outer(1, 16, 8, kind, pairs) == expect
+
+
+def test_moments_drop_the_diagonal_read():
+    # the CSR and face figures count the M diagonal for the Gram kernel's
+    # right-hand side; the moments kind takes the weights from the operator
+    n, nnz, s = 1000, 7000, 16
+    assert (bench.csr_bytes_per_outer(n, nnz, s, 8, "recurrence", 8)
+            - bench.csr_bytes_per_outer(n, nnz, s, 8, "moments", 8)) == n * 8 * (17 + 1)
+    assert (bench.faces_bytes_per_outer(n, s, 8, 1, "recurrence")
+            - bench.faces_bytes_per_outer(n, s, 8, 1, "moments")) == n * 8 * (17 + 1)
 
 
 def test_basis_bytes_per_launch():

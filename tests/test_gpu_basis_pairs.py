@@ -8,7 +8,8 @@ below the range and one above it.  The grids here are ragged against the tile
 shape in x and y.  They are small enough that the ranges are 4 planes thick,
 so most blocks have ranges above and below them.  The cases cover:
 - even and odd column counts (an odd count ends with a single step);
-- both Gram kinds that keep no AP;
+- the Gram kinds that keep no AP (moments, the default; recurrence;
+  operator-applying);
 - Jacobi on and off, and both p_0 readings;
 - widths from 2 to 31, and FP32.
 The bar for FP64 is the lockstep bar of the single-step path: every basis
@@ -47,6 +48,10 @@ CASES = {
     "rec_s8_p0_mode1": ((64, 14, 30), 8, 20, {"p0_mode": 1}),
     "rec_s31": ((24, 20, 18), 31, 30, {}),
     "rec_s12_thin_z": ((70, 45, 3), 12, 20, {}),
+    # the default Gram kind is the moments kind; these two take the
+    # recurrence kind, whose Gram kernel reads the columns back
+    "recurrence_kind_s16": ((61, 47, 23), 16, 25, {"gram": "recurrence"}),
+    "recurrence_kind_s7_odd": ((58, 31, 19), 7, 20, {"gram": "recurrence"}),
 }
 
 

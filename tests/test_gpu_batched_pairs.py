@@ -1,0 +1,144 @@
+"""Two basis steps per launch in batched solves (recurrence Gram kind), on the
+GPU.
+
+A block of the two-step kernel owns a band of whole grid rows of one system
+and a range of its planes; it also forms the first step on the row below and
+the row above the band.  The grids here span:
+- planes that fit one block (one band);
+- several bands, with heights that do not divide the grid;
+- rows of 341 points, the widest that still leave one band row per block;
+- several z-ranges, the last one shorter.
+Widths cover even s, odd s (the last column then takes a single step), s = 2
+(the first pair only) and s = 1 (no pair).
+
+Each case is checked two ways.  First, the iterates after 1 and 2 outer
+iterations equal those of the same context built with one step per launch,
+bit for bit: both kernels form every value with the same operations in the
+same order, and the rest of the iteration is the same code.  Second, they
+are checked against the FP64 oracle within the lockstep bar of 1e-10."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def t64(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_batch(seed, dims_list, nrhs, faces=True):
+    r = gen.rng(seed)
+    systems = []
+    for dims in dims_list:
+        if faces:
+            kx, ky, kz = gen.face_coefficients(r, *dims, 1.0)
+            lmin, lmax = gen.gershgorin_jacobi_bounds()
+        else:
+            kx = ky = kz = None
+            lmin, lmax = gen.jacobi_poisson_bounds(*dims)
+        n = int(np.prod(dims))
+        rhs = np.stack([gen.uniform(r, n) for _ in range(nrhs)])
+        systems.append(dict(dims=dims, kx=kx, ky=ky, kz=kz, lmin=lmin, lmax=lmax, rhs=rhs))
+    return systems
+
+
+def iterate(hip, systems, nrhs, s, nu, k, **kw):
+    """x after k outer iterations of every pair, and the context's basis
+    launch counts."""
+    ops = [hip.Operator.stencil(*sy["dims"], sy["kx"], sy["ky"], sy["kz"]) for sy in systems]
+    with hip.BatchedSolver(ops, nrhs, s, nu, [sy["lmin"] for sy in systems], [sy["lmax"] for sy in systems],
+                           max_outer=k, autotune=False, **kw) as bs:
+        b = [t64(sy["rhs"].ravel()) for sy in systems]
+        x, st = bs.solve(b, None, 1e-14, raise_on_error=False)
+        counts = (bs.basis_launches, bs.basis_pairs)
+    for p in st:
+        assert p.outer_iters == k and p.status == 5, (p.outer_iters, p.status)
+    return [host(xq).reshape(nrhs, -1) for xq in x], counts
+
+
+# name: (grids, nrhs, s, faces, precond)
+CASES = {
+    # 40 x 37 planes: bands of 19 rows (2 bands), 35 planes: ranges 12, 12, 11
+    "faces_bands_ranges_s16": ([(40, 37, 35), (9, 11, 7)], 3, 16, True, True),
+    # rows of 341 points: one band row per block, 7 bands
+    "faces_widest_rows_s6": ([(341, 7, 5), (20, 20, 20)], 2, 6, True, True),
+    # odd s: seven pairs and a single step; heights 63 / 2 bands of 32
+    "faces_odd_s15": ([(30, 63, 17), (17, 3, 40)], 2, 15, True, True),
+    "poisson_bands_s8": ([(64, 45, 33), (33, 31, 9)], 2, 8, False, True),
+    "faces_no_jacobi_s10": ([(50, 29, 18)], 3, 10, True, False),
+    "faces_s2_first_pair_only": ([(45, 40, 21)], 2, 2, True, True),
+    "faces_s3_pair_and_step": ([(26, 41, 19)], 2, 3, True, True),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pairs_equal_single_steps_and_oracle(hip, name):
+    dims, nrhs, s, faces, precond = CASES[name]
+    nu = 20
+    systems = make_batch(7, dims, nrhs, faces=faces)
+    for k in (1, 2):
+        x2, c2 = iterate(hip, systems, nrhs, s, nu, k, precond=precond)
+        x1, c1 = iterate(hip, systems, nrhs, s, nu, k, precond=precond, basis_steps=1)
+        assert c2 == (s - s // 2, s // 2), c2
+        assert c1 == (s, 0), c1
+        for q in range(len(systems)):
+            assert np.array_equal(x2[q], x1[q]), (k, q, float(np.max(np.abs(x2[q] - x1[q]))))
+    # lockstep against the oracle after 2 outer iterations
+    for q, sy in enumerate(systems):
+        A = oracle.assemble_stencil7(*sy["dims"], sy["kx"], sy["ky"], sy["kz"])
+        for r in range(nrhs):
+            xo = np.zeros(sy["rhs"].shape[1])
+            for _ in range(2):
+                o = oracle.step(A, sy["rhs"][r], xo, s, nu, sy["lmin"], sy["lmax"], precond=1 if precond else 0)
+                xo = o["x"]
+            assert rel(x2[q][r], xo) <= 1e-10, (q, r, rel(x2[q][r], xo))
+
+
+def test_pairs_fp32ir_solve(hip):
+    """FP32 basis by pairs (FP32 face coefficients): every pair reaches 1e-8
+    in the FP64 residual."""
+    dims = [(40, 37, 35), (33, 20, 18), (12, 12, 12)]
+    nrhs, s, nu = 2, 16, 25
+    systems = make_batch(8, dims, nrhs)
+    ops = [hip.Operator.stencil(*sy["dims"], sy["kx"], sy["ky"], sy["kz"]) for sy in systems]
+    with hip.BatchedSolver(ops, nrhs, s, nu, [0.0] * 3, [2.0] * 3, precision="fp32ir", autotune=False) as bs:
+        assert bs.basis_pairs == 8
+        x, st = bs.solve([t64(sy["rhs"].ravel()) for sy in systems], None, 1e-8)
+    for q, sy in enumerate(systems):
+        A = oracle.assemble_stencil7(*sy["dims"], sy["kx"], sy["ky"], sy["kz"])
+        xq = host(x[q]).reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert st[q * nrhs + r].status == 0
+            b = sy["rhs"][r]
+            assert np.linalg.norm(b - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_pairs_only_where_they_fit(hip):
+    """One step per launch with AP stored, and for a batch holding a system
+    whose rows are too wide for a band (342 points); s = 1 has no pair."""
+    small = make_batch(9, [(12, 10, 8)], 1)[0]
+    wide = make_batch(9, [(342, 3, 3)], 1)[0]
+
+    def counts(systems, s, **kw):
+        ops = [hip.Operator.stencil(*sy["dims"], sy["kx"], sy["ky"], sy["kz"]) for sy in systems]
+        with hip.BatchedSolver(ops, 1, s, 5, [0.0] * len(ops), [2.0] * len(ops), autotune=False, **kw) as bs:
+            return bs.basis_launches, bs.basis_pairs
+
+    assert counts([small], 8) == (4, 4)
+    assert counts([small], 8, gram="stored") == (8, 0)
+    assert counts([small, wide], 8) == (8, 0)
+    assert counts([small], 1) == (1, 0)
+    with pytest.raises(hip.SStepError) as ei:
+        counts([small], 8, basis_steps=2)
+    assert ei.value.name == "SSTEP_E_ARG"

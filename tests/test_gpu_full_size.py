@@ -59,7 +59,7 @@ def test_full_size_lockstep_matches_oracle(hip, c2):
     bt = t64(b)
     x = np.zeros(pr.n)
     with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax) as sv:
-        assert sv.gram_kind == "recurrence"
+        assert sv.gram_kind == "moments"
         for k in range(2):
             g = sv.step(bt, t64(x))
             o = oracle.step(A, b, x, S, NU, pr.lmin, pr.lmax)
@@ -80,7 +80,7 @@ def test_full_size_solve_follows_oracle(hip, c2):
         ref = json.load(f)
     assert ref["status"] == 0
     with hip.Solver(hip.Operator.stencil(N, N, N), S, NU, pr.lmin, pr.lmax, record_history=True) as sv:
-        assert sv.gram_kind == "recurrence"
+        assert sv.gram_kind == "moments"
         x, st = sv.solve(t64(b), None, 1e-8, history=True)
     assert st.status == 0
     assert abs(st.outer_iters - ref["iters"]) <= max(1, int(0.05 * ref["iters"])), (st.outer_iters, ref["iters"])

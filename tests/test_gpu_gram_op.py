@@ -34,12 +34,14 @@ PROBLEMS = {
 
 
 def test_gram_mode_selection(hip):
-    """The default is the recurrence kind for s <= 31 (every operator and
-    precision), the stored-AP kind at s = 32; the operator-applying kind on
-    request for 7-point stencils with s <= 16."""
+    """The default is the moments kind for s <= 31 in FP64 (every operator,
+    p_0 = M^{-1} r), the recurrence kind in FP32+IR, the stored-AP kind at
+    s = 32; the other kinds on request."""
     pr = ragged_poisson(0)
     op = make_operator(hip, pr, "stencil")
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax) as sv:
+        assert sv.gram_kind == "moments" and not sv.gram_applies_operator
+    with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, gram="recurrence") as sv:
         assert sv.gram_kind == "recurrence" and not sv.gram_applies_operator
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, gram="apply") as sv:
         assert sv.gram_kind == "apply" and sv.gram_applies_operator
@@ -50,11 +52,11 @@ def test_gram_mode_selection(hip):
     with hip.Solver(op, 16, 5, pr.lmin, pr.lmax, precision="fp32ir", gram="apply") as sv:
         assert sv.gram_kind == "apply"
     with hip.Solver(op, 17, 5, pr.lmin, pr.lmax) as sv:
-        assert sv.gram_kind == "recurrence"
+        assert sv.gram_kind == "moments"
     with hip.Solver(op, 32, 5, pr.lmin, pr.lmax) as sv:
         assert sv.gram_kind == "stored"
     with hip.Solver(make_operator(hip, pr, "csr"), 8, 5, pr.lmin, pr.lmax) as sv:
-        assert sv.gram_kind == "recurrence"
+        assert sv.gram_kind == "moments"
 
 
 @pytest.mark.parametrize("name", list(PROBLEMS))

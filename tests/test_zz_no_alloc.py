@@ -52,7 +52,9 @@ def noalloc(hip, op, s, nu, lmin, lmax, b, x, tol=1e-8, precision=0):
 
 
 def reference(hip, pr, form, s, nu, b):
-    with hip.Solver(make_operator(hip, pr, form), s, nu, pr.lmin, pr.lmax, autotune=False) as sv:
+    # the allocation-free entry point takes the recurrence Gram kind
+    with hip.Solver(make_operator(hip, pr, form), s, nu, pr.lmin, pr.lmax, autotune=False,
+                    gram="recurrence") as sv:
         return sv.solve(b, None, 1e-8)
 
 
