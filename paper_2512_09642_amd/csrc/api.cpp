@@ -370,8 +370,9 @@ sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, co
         *kind = SSTEP_GRAM_MOMENTS;
         return SSTEP_OK;
     }
-    // AUTO: the moments kind in FP64; in FP32+IR the recurrence kind, whose
-    // solves took fewer outer iterations (52 against 82 at 224^3, s = 16)
+    // AUTO: the moments kind in FP64; in FP32+IR the recurrence kind.  FP32+IR
+    // iteration counts to 1e-8 swing with rounding at s = 16 (recurrence /
+    // moments: 57 / 46 at 160^3, 52 / 82 at 224^3)
     if (o.gram == SSTEP_GRAM_AUTO && allow_moments && moments_fit(s, o) && o.precision == SSTEP_FP64) {
         *kind = SSTEP_GRAM_MOMENTS;
         return SSTEP_OK;
