@@ -90,6 +90,20 @@ def faces_bytes_per_outer(n: int, s: int, w: int, nrhs: int = 1, kind: str = "st
     return nrhs * (stencil_bytes_per_outer(n, s, w, kind) + dvec) + float(n) * 3 * (8 + s * w)
 
 
+def batched_system_bytes(n: int, s: int, w: int, kind: str, pairs: int) -> tuple:
+    """Bytes of one outer iteration of one batched face-coefficient system of
+    n unknowns: (per right-hand side, shared by its right-hand sides).  Per
+    right-hand side: the stencil figure with the basis launches used, and the
+    M diagonal read by the Gram kernel (not with the moments kind).  Shared:
+    the three face arrays read by the FP64 residual (8-byte) and once per
+    basis launch in width w, and with two steps per launch the array of
+    Jacobi weights too."""
+    launches = s - pairs
+    per_rhs = stencil_bytes_per_outer(n, s, w, kind, pairs) + (0.0 if kind == "moments" else float(n) * w)
+    shared = float(n) * (3 * 8 + launches * (3 + (1 if pairs else 0)) * w)
+    return per_rhs, shared
+
+
 def basis_bytes_per_launch(n: int, s: int, w: int, kind: str = "stored", pairs: int = 0,
                            launches: int = 0) -> float:
     """Average algorithmic bytes of one basis launch: basis_vectors over the
@@ -330,8 +344,7 @@ def build_legs(lib, torch, legs, N, s, nu, c4_nsys, gram="auto"):
         # per system: (bytes per right-hand side per outer iteration, face-array bytes shared by the rhs),
         # for the Gram kind the batched solver uses
         kind = leg.solver.gram_kind
-        leg.pair_bytes = [(stencil_bytes_per_outer(nq, 16, w, kind) + float(nq) * w, float(nq) * 3 * (8 + 16 * w))
-                          for nq in sizes]
+        leg.pair_bytes = [batched_system_bytes(nq, 16, w, kind, leg.solver.basis_pairs) for nq in sizes]
         leg.bytes_per_outer = None
         leg.n = sum(sizes)
         leg.nsys = len(probs)
@@ -422,7 +435,8 @@ def main():
                 tot_bytes += per_rhs * sum(its) + faces * max(its)
             per_sys = [max(leg.pair_iters[q * 8:(q + 1) * 8]) for q in range(leg.nsys)]
             g = tot_bytes / (t * 1e-3) / 1e9
-            r.update(frac_of_hbm_peak=g / HBM_PEAK_GBPS, tiles=leg.solver.tiles)
+            r.update(frac_of_hbm_peak=g / HBM_PEAK_GBPS, tiles=leg.solver.tiles,
+                     basis_launches=leg.solver.basis_launches, basis_pairs=leg.solver.basis_pairs)
             r.update(outer_iters_min=min(leg.pair_iters), outer_iters_max=max(leg.pair_iters),
                      pairs=len(leg.pair_iters), unknown_rhs=leg.n * 8,
                      max_rel_res=max(leg.pair_relres), gbps_effective=tot_bytes / (t * 1e-3) / 1e9,

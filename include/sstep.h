@@ -110,7 +110,8 @@ typedef struct {
  * + sigma p_j (j >= 1), M^{-1} A p_0 = p_1 / theta + sigma p_0 (monomial
  * basis: M^{-1} A p_j = p_{j+1}).  AP is neither written nor allocated and A
  * is not applied in the Gram kernel.  MOMENTS (Chebyshev basis, s <= 31,
- * p_0 = M^{-1} r or no preconditioner, contexts made by sstep_setup): as
+ * p_0 = M^{-1} r or no preconditioner; batched contexts in FP64 with an even
+ * s and two basis steps per launch): as
  * RECURRENCE, but no kernel reads the basis back.  While the basis kernels
  * form p_i, they sum d_i = <p_i, M p_i> and e_i = <p_i, M p_{i-1}>
  * (fixed-order block partials).  With X = theta (M^{-1} A - sigma I),
@@ -144,9 +145,9 @@ typedef struct {
                                (default) = SSTEP_GRAM_MOMENTS in FP64 where it applies, else
                                SSTEP_GRAM_RECURRENCE for s <= 31 (FP32+IR, p_0 = r with Jacobi,
                                the monomial basis, the allocation-free solve), SSTEP_GRAM_STORED_AP
-                               at s = 32.  Batched contexts take AUTO (= RECURRENCE for s <= 31),
-                               RECURRENCE or STORED_AP (SSTEP_E_UNSUPPORTED for APPLY_OP and
-                               MOMENTS) */
+                               at s = 32.  Batched contexts take AUTO (= MOMENTS where it applies,
+                               else RECURRENCE for s <= 31), MOMENTS, RECURRENCE or STORED_AP
+                               (SSTEP_E_UNSUPPORTED for APPLY_OP) */
     int32_t basis;          /* 0 = Chebyshev basis (default, Sec. 2); 1 = monomial basis
                                p_{j+1} = M^{-1} A p_j of the same Krylov space, the comparison of
                                Sec. 4 (a diagnostic: its Gram matrix is badly conditioned; the

@@ -999,7 +999,8 @@ int32_t sstep_gram_mode(const sstep_ctx *ctx)
     if (!ctx)
         return -1;
     if (ctx->batch)
-        return ctx->batch->ba.rec ? SSTEP_GRAM_RECURRENCE : SSTEP_GRAM_STORED_AP;
+        return ctx->batch->ba.mom ? SSTEP_GRAM_MOMENTS
+                                  : (ctx->batch->ba.rec ? SSTEP_GRAM_RECURRENCE : SSTEP_GRAM_STORED_AP);
     if (ctx->it.gram_mom)
         return SSTEP_GRAM_MOMENTS;
     return ctx->it.gram_rec ? SSTEP_GRAM_RECURRENCE : (ctx->it.gram_op ? SSTEP_GRAM_APPLY_OP : SSTEP_GRAM_STORED_AP);
@@ -1268,7 +1269,7 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
 // block of kBf2Threads threads; a grid whose planes fit in one block is one
 // band), its planes into ranges of about kBf2Planes.  Empty when some system
 // does not fit that shape (a row wider than a third of a block) or the
-// windows of its buffer accesses would pass 2 GiB: the batch then takes one
+// windows of its buffer accesses would reach 1 GiB: the batch then takes one
 // step per launch.
 static std::vector<BF2Tile> bf2_bands(const std::vector<BSys> &sys, size_t elem, bool faces, int nt, int kzt)
 {
@@ -1276,7 +1277,7 @@ static std::vector<BF2Tile> bf2_bands(const std::vector<BSys> &sys, size_t elem,
     for (size_t q = 0; q < sys.size(); ++q) {
         const Grid3 &g = sys[q].g;
         const int64_t nx = g.nx, ny = g.ny, nz = g.nz;
-        const int64_t lim = (int64_t(1) << 31) - 1;
+        const int64_t lim = (int64_t(1) << 30) - 1;  // below the kernel's out-of-window mark
         int64_t bytes = sys[q].n;
         if (faces)
             bytes = std::max({bytes, nz * ny * (nx + 1), nz * (ny + 1) * nx, (nz + 1) * g.nxy});
@@ -1443,8 +1444,16 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves use the Chebyshev basis");
     if (o.gram < SSTEP_GRAM_AUTO || o.gram > SSTEP_GRAM_MOMENTS)
         return fail(ctx, SSTEP_E_ARG, "unknown gram kind");
-    if (o.gram == SSTEP_GRAM_APPLY_OP || o.gram == SSTEP_GRAM_MOMENTS)
-        return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves take the recurrence or the stored-AP Gram kind");
+    if (o.gram == SSTEP_GRAM_APPLY_OP)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "batched solves take the moments, recurrence or stored-AP Gram kind");
+    // the moments kind in batched solves: FP64, two basis steps per launch
+    // with no single step left (even s), c = P^T r in the M inner product
+    const bool mom_fit = o.precision == SSTEP_FP64 && s % 2 == 0 && s <= kRecMaxS && o.basis_steps == 0 &&
+                         (o.p0_mode == 0 || o.precond == 0);
+    if (o.gram == SSTEP_GRAM_MOMENTS && !mom_fit)
+        return fail(ctx, SSTEP_E_UNSUPPORTED,
+                    "the batched moments Gram kind needs FP64, an even s <= 31, two basis steps per launch and "
+                    "p_0 = M^{-1} r or no preconditioner");
     if (o.gram == SSTEP_GRAM_RECURRENCE && s > kRecMaxS)
         return fail(ctx, SSTEP_E_UNSUPPORTED, "the recurrence Gram kind needs s <= 31");
     if (o.graph_chunk <= 0)
@@ -1497,7 +1506,8 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     a.cscale = (jac_p0 && !a.faces) ? 6.0 : 1.0;
     // recurrence kind by default for s <= 31: H = P^T M P with M the face
     // diagonals, or 6 I (constant Poisson with Jacobi), or I (no Jacobi)
-    a.rec = o.gram == SSTEP_GRAM_RECURRENCE || (o.gram == SSTEP_GRAM_AUTO && s <= kRecMaxS);
+    a.rec = o.gram == SSTEP_GRAM_RECURRENCE || o.gram == SSTEP_GRAM_MOMENTS ||
+            (o.gram == SSTEP_GRAM_AUTO && s <= kRecMaxS);
     a.rec_wap = a.rec && o.precond == 1 && a.faces;
     a.rec_hscale = (a.rec && o.precond == 1 && !a.faces) ? 6.0 : 1.0;
     OKCHK(dalloc(ctx, &ctx->bad_flag, 1));
@@ -1546,6 +1556,16 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
                 HIPCHK(ctx, launch_to_fp32(dv, dv32, S.n, ctx->stream));
                 S.kx32 = k32, S.ky32 = k32 + nfx, S.kz32 = k32 + nfx + nfy, S.dvec32 = dv32;
             }
+            if (a.rec && o.basis_steps == 0) {  // Jacobi weights for the two-step basis
+                double *di = nullptr;
+                float *di32 = nullptr;
+                OKCHK(dalloc(ctx, &di, size_t(S.ld)));
+                if (a.fp32)
+                    OKCHK(dalloc(ctx, &di32, size_t(S.ld)));
+                S.dinv = di;
+                S.dinv32 = di32;
+                HIPCHK(ctx, launch_bdinv(S, o.precond, a.fp32, di, di32, ctx->stream));
+            }
         }
         B.sys.push_back(S);
         B.n.push_back(S.n);
@@ -1592,7 +1612,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     a.ptiles = B.dpt;
     a.gtiles = B.dgt;
     if (a.rec && o.basis_steps == 0) {
-        const std::vector<BF2Tile> f2 = bf2_bands(B.sys, w, a.faces, a.f2nt, kBf2Planes);
+        const std::vector<BF2Tile> f2 = bf2_bands(B.sys, w, a.faces, kBf2Threads, kBf2Planes);
         if (!f2.empty()) {
             OKCHK(dalloc(ctx, &B.df2, f2.size()));
             HIPCHK(ctx, hipMemcpy(B.df2, f2.data(), f2.size() * sizeof(BF2Tile), hipMemcpyHostToDevice));
@@ -1601,7 +1621,27 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
             a.f2per = uint32_t((int64_t(a.nf2) * a.nrhs + kNumXcd - 1) / kNumXcd);
             a.f2tiles = B.df2;
         }
+        if (a.f2 && mom_fit && (o.gram == SSTEP_GRAM_MOMENTS || o.gram == SSTEP_GRAM_AUTO)) {
+            // band entries are ordered by system: each system's range of them,
+            // and its product slots (2s + 1 per right-hand side, one partial per band)
+            int64_t mofs = 0;
+            size_t e = 0;
+            for (int q = 0; q < a.nsys; ++q) {
+                BSys &S = B.sys[size_t(q)];
+                S.f2first = int32_t(e);
+                while (e < f2.size() && f2[e].q == q)
+                    ++e;
+                S.nf2q = int32_t(e - size_t(S.f2first));
+                S.mofs = mofs;
+                mofs += int64_t(a.nrhs) * (2 * s + 1) * S.nf2q;
+            }
+            OKCHK(dalloc(ctx, &a.mpart, size_t(mofs)));
+            a.mom = 1;
+        }
     }
+    if (o.gram == SSTEP_GRAM_MOMENTS && !a.mom)
+        return fail(ctx, SSTEP_E_UNSUPPORTED, "the batched moments Gram kind needs every system to fit the two-step "
+                                              "basis (rows of at most 341 points)");
     // a non-zero npairs with ndone = 0 keeps the kernels active while tuning
     BGlob g0{0, a.npairs};
     HIPCHK(ctx, hipMemcpy(a.gl, &g0, sizeof(BGlob), hipMemcpyHostToDevice));

@@ -68,6 +68,27 @@ __device__ __forceinline__ T block_sum(T v)
     return acc;
 }
 
+// Jacobi weights of one face-coefficient system, 1 / diag (1 without Jacobi),
+// formed by the expression the single-step kernel uses, in T from the faces
+// in T, for the two-step kernel to read.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bdinv(BSys S, int precond, T *__restrict__ out)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c >= S.n)
+        return;
+    const T *kx, *ky, *kz;
+    if constexpr (sizeof(T) == 8)
+        kx = reinterpret_cast<const T *>(S.kx), ky = reinterpret_cast<const T *>(S.ky),
+        kz = reinterpret_cast<const T *>(S.kz);
+    else
+        kx = reinterpret_cast<const T *>(S.kx32), ky = reinterpret_cast<const T *>(S.ky32),
+        kz = reinterpret_cast<const T *>(S.kz32);
+    PointStencil<T, true> op;
+    op.init(S, c, precond, kx, ky, kz);
+    out[c] = op.dinv;
+}
+
 // r = b - A x (FP64) per pair over a chunk, ||r||^2 partial per (pair, chunk),
 // p_0 = p0scale * (M^{-1} r or r) as column 0 of the pair's basis.  The
 // right-hand sides go in groups of kRhsGroup: a point's coefficients are
@@ -223,21 +244,37 @@ __global__ __launch_bounds__(kBlock) void k_bbasis(const BGlob *__restrict__ gl,
 // block; it marches the range in z with the current plane of p_j and of q in
 // LDS and the planes above and below in registers, as the single-system pair
 // kernel does.  Face coefficients are read once per point and plane (the
-// bottom face is the top face of the plane below); the diagonal is summed
-// from them in the order of the face operator.  Logical blocks take the
-// right-hand sides of one band fastest, so the blocks that read the same
-// coefficients run together on one XCD and share them through its L2.
-// Every memory access is a buffer access whose offset leaves the window when
-// the point, plane or row does not exist (see basis_f2.h).
-template <typename T, bool FACES, bool FIRST, int D, int DF, int NT>
+// bottom face is the top face of the plane below), the Jacobi weight from the
+// system's array of 1 / diag (formed at set-up by the same expression).
+// Logical blocks take the right-hand sides of one band fastest, so the blocks
+// that read the same coefficients run together on one XCD and share them
+// through its L2.
+//
+// The loop body has no branch: a neighbour that does not exist is read from
+// a zero slot past the end of each LDS plane (or, across the block's first
+// and last rows, taken from the register loaded from global memory), and
+// every value is formed and then selected.  Every memory access is a buffer
+// access at a per-lane base plus a block-uniform plane offset; either is
+// kMark when the point or the plane does not exist, and since every window
+// stays below 1 GiB = kMark, such a sum lies outside it (the load returns 0,
+// the store is dropped).
+//
+// MOM (moments Gram kind): the block also sums, over the points it stores,
+// <q, M p_j>, <q, M q>, <p_{j+2}, M q>, <p_{j+2}, M p_{j+2}> (and
+// <p_0, M p_0> first when FIRST), M the face diagonal with Jacobi (1 for the
+// constant operator, whose diagonal the FGS kernel applies), and writes them
+// to the pair's product slots from slot 2j + 1 (0 when FIRST), one partial
+// per band (BSys::mofs).
+constexpr uint32_t kMark = 0x40000000u;
+template <typename T, bool FACES, bool FIRST, int D, int NT, bool MOM>
 __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                   const BF2Tile *__restrict__ tiles, uint32_t nbl, uint32_t per,
                                                   const DevState *__restrict__ pairs, int nrhs, int precond, int j,
-                                                  T *__restrict__ P)
+                                                  T *__restrict__ P, double *__restrict__ mpart, int s)
 {
     constexpr uint32_t ES = sizeof(T);
-    __shared__ T ps[2][NT];
-    __shared__ T qs[2][NT];
+    __shared__ T ps[2][NT + 1];  // slot NT holds 0
+    __shared__ T qs[2][NT + 1];
     if (gl->ndone == gl->npairs)
         return;
     const uint32_t lb = xcd_block(blockIdx.x, per);
@@ -251,6 +288,10 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
     const int nx = S.g.nx, ny = S.g.ny, nz = S.g.nz;
     const uint32_t nxy = static_cast<uint32_t>(S.g.nxy);
     const int tid = threadIdx.x;
+    if (tid < 2) {
+        ps[tid][NT] = T(0);
+        qs[tid][NT] = T(0);
+    }
     // rows of the block: the band and the row on each side of it
     const int ye0 = tl.y0 > 0 ? tl.y0 - 1 : 0;
     const int ye1 = tl.y1 < ny ? tl.y1 + 1 : ny;
@@ -259,16 +300,28 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
     const int ey = ye0 + er;
     const bool in_dom = ey < ye1;
     const bool interior = in_dom && ey >= tl.y0 && ey < tl.y1;
-    const bool hw = i > 0, he = i + 1 < nx, hs = ey > ye0, hn = ey + 1 < ye1;
+    const bool hs = ey > ye0, hn = ey + 1 < ye1;
+    // LDS neighbours: the point's own slot index, or the zero slot
+    const int iw = in_dom && i > 0 ? tid - 1 : NT;
+    const int ie = in_dom && i + 1 < nx ? tid + 1 : NT;
+    const int is = in_dom && hs ? tid - nx : NT;
+    const int in = in_dom && hn ? tid + nx : NT;
     // A point of the first or last row of the block reads its one neighbour
     // outside the block from global memory (0 where the grid ends there).
     const bool ring_s = in_dom && !hs && ey > 0;
     const bool ring = ring_s || (in_dom && !hn && ey + 1 < ny);
-    const int off_r = ring_s ? -nx : nx;
     const uint32_t pl = in_dom ? static_cast<uint32_t>(ey * nx + i) : 0u;
+    const uint32_t b_pt = in_dom ? pl * ES : kMark;            // the point
+    const uint32_t b_in = interior ? pl * ES : kMark;          // the point, stored by this block
+    const uint32_t b_rg = ring ? (ring_s ? pl - nx : pl + nx) * ES : kMark;
     const int k0 = tl.k0, k1 = tl.k1;
     const int kj_hi = k1 + 1 < nz ? k1 + 1 : nz - 1;  // last plane of p_j the range reads
     const int kv_hi = k1 < nz ? k1 : nz - 1;          // last plane of q, p_{j-1}, ring values, faces
+    const uint32_t pbytes = nxy * ES;
+    // block-uniform plane offsets
+    auto po = [&](int k, int klo, int khi) -> uint32_t {
+        return k >= klo && k <= khi ? static_cast<uint32_t>(k) * pbytes : kMark;
+    };
     const int64_t step = static_cast<int64_t>(nrhs) * S.ld;
     T *const col = P + S.pofs + static_cast<int64_t>(r) * S.ld + static_cast<int64_t>(j) * step;
     const uint32_t cbytes = static_cast<uint32_t>(S.n) * ES;
@@ -276,72 +329,64 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
     const __amdgpu_buffer_rsrc_t rv = make_window(FIRST ? col : col - step, cbytes);
     const __amdgpu_buffer_rsrc_t rq = make_window(col + step, cbytes);
     const __amdgpu_buffer_rsrc_t r2 = make_window(col + 2 * step, cbytes);
-    // byte offset of the thread's point (+ d in-plane) on plane k, or
-    // kOutside when the point is outside the grid or k outside [0, khi]
-    auto at = [&](int k, int d, bool ok, int klo, int khi) -> uint32_t {
-        return ok && k >= klo && k <= khi ? (static_cast<uint32_t>(k) * nxy + static_cast<uint32_t>(static_cast<int>(pl) + d)) * ES
-                                          : kOutside;
-    };
-    const T *kxp = nullptr, *kyp = nullptr, *kzp = nullptr;
+    const T *kxp = nullptr, *kyp = nullptr, *kzp = nullptr, *dvp = nullptr;
     if constexpr (FACES) {
         if constexpr (sizeof(T) == 8)
             kxp = reinterpret_cast<const T *>(S.kx), kyp = reinterpret_cast<const T *>(S.ky),
-            kzp = reinterpret_cast<const T *>(S.kz);
+            kzp = reinterpret_cast<const T *>(S.kz), dvp = reinterpret_cast<const T *>(S.dinv);
         else
             kxp = reinterpret_cast<const T *>(S.kx32), kyp = reinterpret_cast<const T *>(S.ky32),
-            kzp = reinterpret_cast<const T *>(S.kz32);
+            kzp = reinterpret_cast<const T *>(S.kz32), dvp = reinterpret_cast<const T *>(S.dinv32);
     }
     // faces: x-faces (nx + 1 per grid row), y-faces (ny + 1 rows of nx per
     // plane), z-faces (nz + 1 planes)
     const uint32_t xrow = static_cast<uint32_t>(nx + 1);
-    const __amdgpu_buffer_rsrc_t rfx = make_window(kxp, static_cast<uint32_t>(nz) * ny * xrow * ES);
-    const __amdgpu_buffer_rsrc_t rfy = make_window(kyp, static_cast<uint32_t>(nz) * (ny + 1) * nx * ES);
-    const __amdgpu_buffer_rsrc_t rfz = make_window(kzp, (static_cast<uint32_t>(nz) + 1) * nxy * ES);
-    const uint32_t fx_pl = static_cast<uint32_t>(ey) * xrow + static_cast<uint32_t>(i);
-    const uint32_t fy_pl = static_cast<uint32_t>(ey * nx + i);
-    auto fx_at = [&](int k, int d) -> uint32_t {
-        return in_dom && k >= 0 && k <= kv_hi ? (static_cast<uint32_t>(k) * ny * xrow + fx_pl + d) * ES : kOutside;
-    };
-    auto fy_at = [&](int k, int d) -> uint32_t {
-        return in_dom && k >= 0 && k <= kv_hi ? (static_cast<uint32_t>(k) * (ny + 1) * nx + fy_pl + d) * ES : kOutside;
-    };
-    auto fz_at = [&](int k) -> uint32_t {  // z-face below plane k (k = nz: the top face of the last plane)
-        return in_dom && k >= 0 && k <= kv_hi + 1 ? (static_cast<uint32_t>(k) * nxy + pl) * ES : kOutside;
-    };
+    const uint32_t xplane = static_cast<uint32_t>(ny) * xrow * ES, yplane = static_cast<uint32_t>(ny + 1) * nx * ES;
+    const __amdgpu_buffer_rsrc_t rfx = make_window(kxp, static_cast<uint32_t>(nz) * xplane);
+    const __amdgpu_buffer_rsrc_t rfy = make_window(kyp, static_cast<uint32_t>(nz) * yplane);
+    const __amdgpu_buffer_rsrc_t rfz = make_window(kzp, (static_cast<uint32_t>(nz) + 1) * pbytes);
+    const __amdgpu_buffer_rsrc_t rdv = make_window(dvp, cbytes);
+    const uint32_t b_fx = in_dom ? (static_cast<uint32_t>(ey) * xrow + static_cast<uint32_t>(i)) * ES : kMark;
+    const uint32_t b_fy = b_pt;  // (ey * nx + i) within a plane of y-faces
+    auto fxo = [&](int k) -> uint32_t { return k >= 0 && k <= kv_hi ? static_cast<uint32_t>(k) * xplane : kMark; };
+    auto fyo = [&](int k) -> uint32_t { return k >= 0 && k <= kv_hi ? static_cast<uint32_t>(k) * yplane : kMark; };
     const T theta = static_cast<T>(S.theta), sigma = static_cast<T>(S.sigma);
     const T two_theta = T(2) * theta;
     const T minv_c = precond ? T(1) / T(6) : T(1);
-    T pm = buf_load(T(), rj, at(k0 - 2, 0, in_dom, 0, kj_hi));  // p_j one plane below the current one
-    T p0 = buf_load(T(), rj, at(k0 - 1, 0, in_dom, 0, kj_hi));  // p_j on the current plane
+    T pm = buf_load(T(), rj, b_pt + po(k0 - 2, 0, kj_hi));  // p_j one plane below the current one
+    T p0 = buf_load(T(), rj, b_pt + po(k0 - 1, 0, kj_hi));  // p_j on the current plane
     T qb = T(0), qc = T(0);  // q two planes and one plane below the current one
     T fb = T(0);             // bottom face of the current plane
     if constexpr (FACES)
-        fb = buf_load(T(), rfz, fz_at(k0 - 1));
+        fb = buf_load(T(), rfz, b_pt + po(k0 - 1, 0, kv_hi + 1));
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;  // products (MOM)
     // coefficients of the plane below (the second step's plane)
     T gw = T(0), ge = T(0), gs = T(0), gn = T(0), gb = T(0), gt = T(0), gd = T(0);
     // slot u holds, for plane kq = k0 - 1 + u (mod D): p_j on plane kq + 1,
-    // p_{j-1}, the ring neighbour and the faces of plane kq
+    // p_{j-1}, the ring neighbour, the faces and the Jacobi weight of plane kq
     T pjs[D], pps[D], rgs[D];
-    // the faces of plane kq in slot kq - k0 + 1 (mod DF), DF dividing D
-    static_assert(D % DF == 0, "face slots must divide the step unroll");
-    T fws[FACES ? DF : 1], fes[FACES ? DF : 1], fss[FACES ? DF : 1], fns[FACES ? DF : 1], fts[FACES ? DF : 1];
+    T fws[FACES ? D : 1], fes[FACES ? D : 1], fss[FACES ? D : 1], fns[FACES ? D : 1], fts[FACES ? D : 1],
+        fds[FACES ? D : 1];
+    auto fill = [&](int u, int kq) {
+        pjs[u] = buf_load(T(), rj, b_pt + po(kq + 1, 0, kj_hi));
+        if constexpr (!FIRST)
+            pps[u] = buf_load(T(), rv, b_pt + po(kq, 0, kv_hi));
+        rgs[u] = buf_load(T(), rj, b_rg + po(kq, 0, kv_hi));
+        if constexpr (FACES) {
+            const uint32_t ox = b_fx + fxo(kq), oy = b_fy + fyo(kq);
+            fws[u] = buf_load(T(), rfx, ox);
+            fes[u] = buf_load(T(), rfx, ox + ES);
+            fss[u] = buf_load(T(), rfy, oy);
+            fns[u] = buf_load(T(), rfy, oy + static_cast<uint32_t>(nx) * ES);
+            fts[u] = buf_load(T(), rfz, b_pt + po(kq + 1, 0, kv_hi + 1));
+            fds[u] = buf_load(T(), rdv, b_pt + po(kq, 0, kv_hi));
+        }
+    };
 #pragma unroll
     for (int u = 0; u < D; ++u) {
-        const int kq = k0 - 1 + u;
-        pjs[u] = buf_load(T(), rj, at(kq + 1, 0, in_dom, 0, kj_hi));
-        pps[u] = FIRST ? T(0) : buf_load(T(), rv, at(kq, 0, in_dom, 0, kv_hi));
-        rgs[u] = buf_load(T(), rj, at(kq, off_r, ring, 0, kv_hi));
-    }
-#pragma unroll
-    for (int u = 0; u < DF; ++u) {
-        const int kq = k0 - 1 + u;
-        if constexpr (FACES) {
-            fws[u] = buf_load(T(), rfx, fx_at(kq, 0));
-            fes[u] = buf_load(T(), rfx, fx_at(kq, 1));
-            fss[u] = buf_load(T(), rfy, fy_at(kq, 0));
-            fns[u] = buf_load(T(), rfy, fy_at(kq, nx));
-            fts[u] = buf_load(T(), rfz, fz_at(kq + 1));
-        }
+        if constexpr (FIRST)
+            pps[u] = T(0);
+        fill(u, k0 - 1 + u);
     }
     // planes k0 - 1 .. k1, padded to a multiple of D: a padding step loads
     // nothing (its offsets lie outside the windows) and stores nothing
@@ -353,50 +398,62 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
             const int buf = kq & 1;
             const T pp = pjs[u], pv = pps[u], rg = rgs[u];
             T fw = T(0), fe = T(0), fs = T(0), fn = T(0), ft = T(0), dinv = minv_c;
-            if constexpr (FACES) {
-                const int f = u % DF;
-                fw = fws[f], fe = fes[f], fs = fss[f], fn = fns[f], ft = fts[f];
-                dinv = precond ? T(1) / (((((fw + fe) + fs) + fn) + fb) + ft) : T(1);
-            }
+            if constexpr (FACES)
+                fw = fws[u], fe = fes[u], fs = fss[u], fn = fns[u], ft = fts[u], dinv = fds[u];
             ps[buf][tid] = p0;
             lds_barrier();
-            T q = T(0);
-            if (in_dom && kq >= 0 && kq <= k1 && kq < nz) {
-                const T w = hw ? ps[buf][tid - 1] : T(0);
-                const T e = he ? ps[buf][tid + 1] : T(0);
-                const T s = hs ? ps[buf][tid - nx] : rg;
-                const T n = hn ? ps[buf][tid + nx] : rg;
+            T q;
+            {
+                const T w = ps[buf][iw], e = ps[buf][ie];
+                const T sl = ps[buf][is], nl = ps[buf][in];
+                const T s = hs ? sl : rg;
+                const T n = hn ? nl : rg;
                 T y;
                 if constexpr (FACES)
                     y = fw * (p0 - w) + fe * (p0 - e) + fs * (p0 - s) + fn * (p0 - n) + fb * (p0 - pm) +
                         ft * (p0 - pp);
                 else
                     y = T(6) * p0 - (((((w + e) + s) + n) + pm) + pp);
+                T qv;
                 if constexpr (FIRST)
-                    q = theta * (dinv * y - sigma * p0);
+                    qv = theta * (dinv * y - sigma * p0);
                 else
-                    q = two_theta * (dinv * y - sigma * p0) - pv;
+                    qv = two_theta * (dinv * y - sigma * p0) - pv;
+                const bool act = kq >= 0 && kq <= k1 && kq < nz;  // block-uniform
+                q = in_dom && act ? qv : T(0);
             }
-            buf_store_out(q, rq, at(kq, 0, interior, k0, k1 - 1));
+            buf_store_out(q, rq, b_in + po(kq, k0, k1 - 1));
             qs[buf][tid] = q;
             // the second step on the plane below: q there is in qs[buf ^ 1]
             // (stored before this plane's barrier), q below it in qb, above in q
-            T p2 = T(0);
-            if (interior) {
+            {
                 const T *qp = qs[buf ^ 1];
-                const T w = hw ? qp[tid - 1] : T(0);
-                const T e = he ? qp[tid + 1] : T(0);
-                const T s = hs ? qp[tid - nx] : T(0);
-                const T n = hn ? qp[tid + nx] : T(0);
+                const T w = qp[iw], e = qp[ie], s = qp[is], n = qp[in];
                 T y;
                 if constexpr (FACES)
                     y = gw * (qc - w) + ge * (qc - e) + gs * (qc - s) + gn * (qc - n) + gb * (qc - qb) +
                         gt * (qc - q);
                 else
                     y = T(6) * qc - (((((w + e) + s) + n) + qb) + q);
-                p2 = two_theta * ((FACES ? gd : minv_c) * y - sigma * qc) - pm;
+                const T p2 = two_theta * ((FACES ? gd : minv_c) * y - sigma * qc) - pm;
+                buf_store_out(p2, r2, b_in + po(kq - 1, k0, k1 - 1));
+                if constexpr (MOM) {
+                    // the plane just stored: p_j, q and p_{j+2} of plane kq - 1
+                    const bool own = interior && kq - 1 >= k0 && kq - 1 < k1;
+                    double w = 1.0;
+                    if constexpr (FACES)
+                        w = precond ? static_cast<double>(((((gw + ge) + gs) + gn) + gb) + gt) : 1.0;
+                    w = own ? w : 0.0;
+                    const double a = static_cast<double>(pm), b = static_cast<double>(qc);
+                    const double c2 = static_cast<double>(p2);
+                    if constexpr (FIRST)
+                        m0 += w * a * a;
+                    m1 += w * b * a;
+                    m2 += w * b * b;
+                    m3 += w * c2 * b;
+                    m4 += w * c2 * c2;
+                }
             }
-            buf_store_out(p2, r2, at(kq - 1, 0, interior, k0, k1 - 1));
             qb = qc;
             qc = q;
             pm = p0;
@@ -406,19 +463,19 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
                 fb = ft;
             }
             // refill the slot for plane kq + D once its values are used
-            const int kn = kq + D;
-            pjs[u] = buf_load(T(), rj, at(kn + 1, 0, in_dom, 0, kj_hi));
-            if constexpr (!FIRST)
-                pps[u] = buf_load(T(), rv, at(kn, 0, in_dom, 0, kv_hi));
-            rgs[u] = buf_load(T(), rj, at(kn, off_r, ring, 0, kv_hi));
-            if constexpr (FACES) {
-                const int f = u % DF, kf = kq + DF;
-                fws[f] = buf_load(T(), rfx, fx_at(kf, 0));
-                fes[f] = buf_load(T(), rfx, fx_at(kf, 1));
-                fss[f] = buf_load(T(), rfy, fy_at(kf, 0));
-                fns[f] = buf_load(T(), rfy, fy_at(kf, nx));
-                fts[f] = buf_load(T(), rfz, fz_at(kf + 1));
-            }
+            fill(u, kq + D);
+        }
+    }
+    if constexpr (MOM) {
+        const int ns = 2 * s + 1;
+        double *out = mpart + S.mofs + (static_cast<int64_t>(r) * ns + (FIRST ? 0 : 2 * j + 1)) * S.nf2q +
+                      (static_cast<int32_t>(lb / static_cast<uint32_t>(nrhs)) - S.f2first);
+        if constexpr (FIRST) {
+            const double v[5] = {m0, m1, m2, m3, m4};
+            block_partials<5, NT>(v, out, S.nf2q);
+        } else {
+            const double v[4] = {m1, m2, m3, m4};
+            block_partials<4, NT>(v, out, S.nf2q);
         }
     }
 }
@@ -526,31 +583,40 @@ hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st)
 }
 
 namespace {
-template <typename T, bool FACES, int D, int DF, int NT>
+template <typename T, bool FACES, int D, int NT, bool MOM>
 hipError_t bbasis_pair_v(const BatchArgs &a, int j, hipStream_t st)
 {
     const dim3 grid(a.f2per * kNumXcd);
     const uint32_t nbl = static_cast<uint32_t>(a.nf2) * static_cast<uint32_t>(a.nrhs);
     T *P = static_cast<T *>(a.P);
     if (j == 0)
-        hipLaunchKernelGGL((k_bbasis_f2<T, FACES, true, D, DF, NT>), grid, dim3(NT), 0, st, a.gl, a.sys,
-                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P);
+        hipLaunchKernelGGL((k_bbasis_f2<T, FACES, true, D, NT, MOM>), grid, dim3(NT), 0, st, a.gl, a.sys,
+                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P, a.mpart, a.s);
     else
-        hipLaunchKernelGGL((k_bbasis_f2<T, FACES, false, D, DF, NT>), grid, dim3(NT), 0, st, a.gl, a.sys,
-                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P);
+        hipLaunchKernelGGL((k_bbasis_f2<T, FACES, false, D, NT, MOM>), grid, dim3(NT), 0, st, a.gl, a.sys,
+                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P, a.mpart, a.s);
     return hipGetLastError();
 }
+// Planes of loads in flight: 2 in FP64, 3 in FP32 (fastest on MI355X for the
+// batched workload among 2..4 with 512- and 1024-thread blocks).
 template <typename T, bool FACES>
 hipError_t bbasis_pair_t(const BatchArgs &a, int j, hipStream_t st)
 {
-    constexpr int D = sizeof(T) == 8 ? 2 : 4;
-    if (a.f2nt == 512)
-        return a.f2df == 1 ? bbasis_pair_v<T, FACES, D, 1, 512>(a, j, st) : bbasis_pair_v<T, FACES, D, D, 512>(a, j, st);
-    if (a.f2nt == 256)
-        return a.f2df == 1 ? bbasis_pair_v<T, FACES, D, 1, 256>(a, j, st) : bbasis_pair_v<T, FACES, D, D, 256>(a, j, st);
-    return a.f2df == 1 ? bbasis_pair_v<T, FACES, D, 1, 1024>(a, j, st) : bbasis_pair_v<T, FACES, D, D, 1024>(a, j, st);
+    constexpr int D = sizeof(T) == 8 ? 2 : 3;
+    if (a.mom)
+        return bbasis_pair_v<T, FACES, D, kBf2Threads, true>(a, j, st);
+    return bbasis_pair_v<T, FACES, D, kBf2Threads, false>(a, j, st);
 }
 }  // namespace
+
+hipError_t launch_bdinv(const BSys &S, int precond, int fp32, double *dinv, float *dinv32, hipStream_t st)
+{
+    const dim3 grid(static_cast<uint32_t>((S.n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_bdinv<double>, grid, dim3(kBlock), 0, st, S, precond, dinv);
+    if (fp32)
+        hipLaunchKernelGGL(k_bdinv<float>, grid, dim3(kBlock), 0, st, S, precond, dinv32);
+    return hipGetLastError();
+}
 
 // Steps j and j + 1 of every active pair's basis (recurrence Gram kind, the
 // band table built on the host).

@@ -165,6 +165,37 @@ hipError_t bfgs_launch_s(const BatchArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// H (LDS, the recurrence kind's layout) mapped onto G_raw = P^T A P with the
+// system's theta, sigma (as k_fgs_rec does), then the FGS wave.
+template <int S>
+__device__ __forceinline__ void bfgs_map_sweep(BGlob *__restrict__ gl, DevState *__restrict__ ps, const BSys &Q,
+                                               const double *h, double *sg, int nu, double cscale, int fp32,
+                                               double hscale, double *__restrict__ pdbg)
+{
+    constexpr int S1 = S + 1;
+    constexpr int T0 = S * (S + 1) / 2;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const double theta = Q.theta, sigma = Q.sigma;
+    auto H = [&](int a, int b) { return a >= b ? h[tri_index(a, b)] : h[tri_index(b, a)]; };
+    for (int e = threadIdx.x; e < T0; e += kBFgsThreads) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= e)
+            ++i;
+        const int j = e - i * (i + 1) / 2;
+        const double g = j == 0 ? H(i, 1) / theta + sigma * H(i, 0)
+                                : (H(i, j + 1) + H(i, j - 1)) / (2.0 * theta) + sigma * H(i, j);
+        sg[e] = hscale * g;
+    }
+    for (int i = threadIdx.x; i < S; i += kBFgsThreads)
+        sg[T0 + i] = h[S1 * (S1 + 1) / 2 + i];
+    __syncthreads();
+    if (wave != 0)
+        return;
+    const int now = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, pdbg, nullptr, 0);
+    if (now && lane == 0)
+        atomicAdd(&gl->ndone, 1);
+}
+
 // Recurrence Gram kind: the pair's sums of H and c', the stopping test, then
 // H mapped onto G_raw = P^T A P with the system's theta, sigma (as k_fgs_rec
 // does) and the FGS wave.
@@ -214,25 +245,7 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_rec(BGlob *__restrict__ g
             atomicAdd(&gl->ndone, 1);
         return;
     }
-    const double theta = Q.theta, sigma = Q.sigma;
-    auto H = [&](int a, int b) { return a >= b ? h[tri_index(a, b)] : h[tri_index(b, a)]; };
-    for (int e = threadIdx.x; e < T0; e += kBFgsThreads) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= e)
-            ++i;
-        const int j = e - i * (i + 1) / 2;
-        const double g = j == 0 ? H(i, 1) / theta + sigma * H(i, 0)
-                                : (H(i, j + 1) + H(i, j - 1)) / (2.0 * theta) + sigma * H(i, j);
-        sg[e] = hscale * g;
-    }
-    for (int i = threadIdx.x; i < S; i += kBFgsThreads)
-        sg[T0 + i] = h[S1 * (S1 + 1) / 2 + i];
-    __syncthreads();
-    if (wave != 0)
-        return;
-    const int now = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, pdbg, nullptr, 0);
-    if (now && lane == 0)
-        atomicAdd(&gl->ndone, 1);
+    bfgs_map_sweep<S>(gl, ps, Q, h, sg, nu, cscale, fp32, hscale, pdbg);
 }
 
 template <int S>
@@ -240,6 +253,84 @@ hipError_t bfgs_rec_launch_s(const BatchArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfgs_rec<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs,
                        a.rpart, a.gpart, a.nu, a.cscale, a.fp32, a.rec_hscale, a.dbg);
+    return hipGetLastError();
+}
+
+// Moments kind: per pair, the sums of its 2S + 1 product slots (one partial
+// per band of its system, written by the two-step basis) and of its residual
+// partials, the stopping test, then the moments, H (as k_fgs_mom forms them)
+// and the recurrence mapping with the FGS wave.
+template <int S>
+__global__ __launch_bounds__(kBFgsThreads) void k_bfgs_mom(BGlob *__restrict__ gl, const BSys *__restrict__ sys,
+                                                           DevState *__restrict__ pairs, int nrhs,
+                                                           const double *__restrict__ rpart,
+                                                           const double *__restrict__ mpart, int nu, double cscale,
+                                                           int fp32, double hscale, double *__restrict__ dbg)
+{
+    constexpr int S1 = S + 1;
+    constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
+    constexpr int T0 = S * (S + 1) / 2;
+    constexpr int NS = 2 * S + 1;
+    const int p = blockIdx.x;
+    DevState *ps = pairs + p;
+    if (ps->done)
+        return;
+    const BSys &Q = sys[p / nrhs];
+    const int r = p % nrhs;
+    __shared__ double m[NS + 1];
+    __shared__ double mu[NS];
+    __shared__ double h[E1];
+    __shared__ double sg[T0 + S];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const double *mp = mpart + Q.mofs + static_cast<int64_t>(r) * NS * Q.nf2q;
+    const double *rp = rpart + Q.rofs + static_cast<int64_t>(r) * Q.nch;
+    for (int t = wave; t <= NS; t += kBFgsThreads / kWave) {
+        const double *src = t < NS ? mp + static_cast<int64_t>(t) * Q.nf2q : rp;
+        const int cnt = t < NS ? Q.nf2q : Q.nch;
+        double a0 = 0.0, a1 = 0.0;
+        int q = lane;
+        for (; q + kWave < cnt; q += 2 * kWave) {
+            a0 += src[q];
+            a1 += src[q + kWave];
+        }
+        for (; q < cnt; q += kWave)
+            a0 += src[q];
+        const double acc = wave_sum(a0 + a1);
+        if (lane == 0)
+            m[t] = acc;
+    }
+    __shared__ int stopped;
+    __syncthreads();
+    double *pdbg = dbg + static_cast<int64_t>(p) * dbg_size(S);
+    if (threadIdx.x == 0)
+        stopped = stop_test(ps, m[NS], pdbg + dbg_rho(S), nullptr, 0);
+    __syncthreads();
+    if (stopped) {
+        if (threadIdx.x == 0)
+            atomicAdd(&gl->ndone, 1);
+        return;
+    }
+    for (int k = threadIdx.x; k < NS; k += kBFgsThreads)
+        mu[k] = k <= 1 ? m[k] : 2.0 * m[k] - m[k % 2];
+    __syncthreads();
+    for (int e = threadIdx.x; e < S1 * (S1 + 1) / 2; e += kBFgsThreads) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= e)
+            ++i;
+        const int j = e - i * (i + 1) / 2;
+        h[e] = 0.5 * (mu[i + j] + mu[i - j]);
+    }
+    for (int i = threadIdx.x; i < S1; i += kBFgsThreads)
+        h[S1 * (S1 + 1) / 2 + i] = mu[i];
+    __syncthreads();
+    bfgs_map_sweep<S>(gl, ps, Q, h, sg, nu, cscale, fp32, hscale, pdbg);
+}
+
+template <int S>
+hipError_t bfgs_mom_launch_s(const BatchArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bfgs_mom<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs,
+                       a.rpart, a.mpart, a.nu, a.cscale, a.fp32, a.rec_hscale, a.dbg);
     return hipGetLastError();
 }
 

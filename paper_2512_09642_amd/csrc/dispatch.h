@@ -29,5 +29,7 @@ template <typename T, int S>
 hipError_t bgram_sym_launch_s(const BatchArgs &a, hipStream_t st);
 template <int S>
 hipError_t bfgs_rec_launch_s(const BatchArgs &a, hipStream_t st);
+template <int S>
+hipError_t bfgs_mom_launch_s(const BatchArgs &a, hipStream_t st);
 
 }  // namespace sstep

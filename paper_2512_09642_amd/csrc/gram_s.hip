@@ -31,6 +31,7 @@ template hipError_t fgs_mom_launch_s<SSTEP_S>(const IterArgs &, hipStream_t);
 template hipError_t bgram_sym_launch_s<double, SSTEP_S>(const BatchArgs &, hipStream_t);
 template hipError_t bgram_sym_launch_s<float, SSTEP_S>(const BatchArgs &, hipStream_t);
 template hipError_t bfgs_rec_launch_s<SSTEP_S>(const BatchArgs &, hipStream_t);
+template hipError_t bfgs_mom_launch_s<SSTEP_S>(const BatchArgs &, hipStream_t);
 #endif
 #if SSTEP_S <= 16
 static_assert(SSTEP_S <= kGoMaxS, "operator-applying Gram width");

@@ -104,6 +104,8 @@ hipError_t launch_fgs(const IterArgs &a, hipStream_t st)
 
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st)
 {
+    if (a.mom)  // the two-step basis formed the products
+        return hipSuccess;
     if (a.rec) {
 #define SSTEP_BGS(S)                                                                         \
     case S:                                                                                  \
@@ -120,6 +122,13 @@ hipError_t launch_bgram(const BatchArgs &a, hipStream_t st)
 
 hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st)
 {
+    if (a.mom) {
+#define SSTEP_BFM(S) \
+    case S:          \
+        return bfgs_mom_launch_s<S>(a, st);
+        switch (a.s) { SSTEP_CASES_1_16(SSTEP_BFM) SSTEP_CASES_17_31(SSTEP_BFM) default: return hipErrorInvalidValue; }
+#undef SSTEP_BFM
+    }
     if (a.rec) {
 #define SSTEP_BFR(S) \
     case S:          \

@@ -123,11 +123,18 @@ struct BSys {
     const float *kx32, *ky32, *kz32;
     const double *dvec;              // M diagonal, zero-padded to ld
     const float *dvec32;
+    const double *dinv;              // Jacobi weights 1 / diag (1 without Jacobi), faces only
+    const float *dinv32;             // the same from the FP32 faces (FP32+IR)
     double theta, sigma, inv_sqrt_n;
     int64_t gchunk;                  // rows per chunk tile (multiple of kPad)
     int64_t gofs;                    // Gram partials of pair (q, r): gofs + r*E*nch
     int64_t rofs;                    // residual partials of pair (q, r): rofs + r*nch
     int32_t pair0, nch;
+    // moments kind: the two-step basis's bands of this system are entries
+    // f2first .. f2first + nf2q - 1 of the band table; product slot k of pair
+    // (q, r) holds one partial per band at mofs + (r (2s + 1) + k) nf2q
+    int64_t mofs;
+    int32_t f2first, nf2q;
 };
 struct BTile {  // chunk of one system, all right-hand sides
     int32_t q, chunk;
@@ -172,15 +179,20 @@ struct BatchArgs {
     double rec_hscale = 1.0;
     // two basis steps per launch (f2 = 1): nf2 bands x nrhs logical blocks,
     // f2per of them per XCD
-    int f2 = 0, nf2 = 0, f2nt = kBf2Threads, f2df = 2;
+    int f2 = 0, nf2 = 0;
     uint32_t f2per = 0;
     const BF2Tile *f2tiles = nullptr;
+    // moments Gram kind (also rec): the two-step basis writes the products,
+    // k_bfgs_mom sums them; no Gram kernel
+    int mom = 0;
+    double *mpart = nullptr;
 };
 
 hipError_t launch_bresidual(const BatchArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_bp0scale(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st);
 hipError_t launch_bbasis_pair(const BatchArgs &a, int j, hipStream_t st);
+hipError_t launch_bdinv(const BSys &S, int precond, int fp32, double *dinv, float *dinv32, hipStream_t st);
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bfgs(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bupdate(const BatchArgs &a, hipStream_t st);

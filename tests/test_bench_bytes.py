@@ -59,6 +59,20 @@ def test_moments_drop_the_diagonal_read():
             - bench.faces_bytes_per_outer(n, s, 8, 1, "moments")) == n * 8 * (17 + 1)
 
 
+def test_batched_system_bytes():
+    n, s = 1000, 16
+    # single steps, recurrence kind: 47 basis vectors, 17 Gram columns, the M
+    # diagonal; faces read by the residual (3 x 8) and 16 launches (3 arrays)
+    per, shared = bench.batched_system_bytes(n, s, 8, "recurrence", 0)
+    assert per == n * (32 + 8 * (1 + 47 + 17 + 16)) + n * 8
+    assert shared == n * (24 + 16 * 3 * 8)
+    # two steps per launch, moments kind: 31 basis vectors, no Gram pass, no
+    # diagonal; 8 launches reading the faces and the Jacobi weights
+    per, shared = bench.batched_system_bytes(n, s, 8, "moments", 8)
+    assert per == n * (32 + 8 * (1 + 31 + 0 + 16))
+    assert shared == n * (24 + 8 * 4 * 8)
+
+
 def test_basis_bytes_per_launch():
     n = 224 ** 3
     # the headline basis: 8 pair launches moving 31 vectors of n doubles

@@ -160,11 +160,15 @@ def test_batched_gram_kind_selection(hip):
     pr = gen.small_faces3d(6, 5, 4)
     ops = [hip.Operator.stencil(6, 5, 4, pr.kx, pr.ky, pr.kz)]
     with hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0]) as bs:
+        assert bs.gram_kind == "moments"
+    with hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0], gram="recurrence") as bs:
         assert bs.gram_kind == "recurrence"
     with hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0], gram="stored") as bs:
         assert bs.gram_kind == "stored"
     with hip.BatchedSolver(ops, 2, 32, 5, [0.0], [2.0]) as bs:
         assert bs.gram_kind == "stored"
+    with hip.BatchedSolver(ops, 2, 7, 5, [0.0], [2.0]) as bs:
+        assert bs.gram_kind == "recurrence"
     with pytest.raises(hip.SStepError) as ei:
         hip.BatchedSolver(ops, 2, 8, 5, [0.0], [2.0], gram="apply")
     assert ei.value.name == "SSTEP_E_UNSUPPORTED"

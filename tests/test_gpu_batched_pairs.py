@@ -1,5 +1,6 @@
-"""Two basis steps per launch in batched solves (recurrence Gram kind), on the
-GPU.
+"""Two basis steps per launch in batched solves, on the GPU, with the
+recurrence Gram kind and with the moments kind (the FP64 default for even s,
+whose products the two-step kernel sums per band).
 
 A block of the two-step kernel owns a band of whole grid rows of one system
 and a range of its planes; it also forms the first step on the row below and
@@ -11,11 +12,13 @@ the row above the band.  The grids here span:
 Widths cover even s, odd s (the last column then takes a single step), s = 2
 (the first pair only) and s = 1 (no pair).
 
-Each case is checked two ways.  First, the iterates after 1 and 2 outer
-iterations equal those of the same context built with one step per launch,
-bit for bit: both kernels form every value with the same operations in the
-same order, and the rest of the iteration is the same code.  Second, they
-are checked against the FP64 oracle within the lockstep bar of 1e-10."""
+Each case is checked two ways with the recurrence kind.  First, the iterates
+after 1 and 2 outer iterations equal those of the same context built with one
+step per launch, bit for bit: both kernels form every value with the same
+operations in the same order, and the rest of the iteration is the same
+code.  Second, they are checked against the FP64 oracle within the lockstep
+bar of 1e-10.  The even-s cases are checked against the oracle with the
+moments kind too."""
 import numpy as np
 import pytest
 import torch
@@ -88,8 +91,9 @@ def test_pairs_equal_single_steps_and_oracle(hip, name):
     nu = 20
     systems = make_batch(7, dims, nrhs, faces=faces)
     for k in (1, 2):
-        x2, c2 = iterate(hip, systems, nrhs, s, nu, k, precond=precond)
-        x1, c1 = iterate(hip, systems, nrhs, s, nu, k, precond=precond, basis_steps=1)
+        # the same Gram kind on both sides (one step per launch has no moments kind)
+        x2, c2 = iterate(hip, systems, nrhs, s, nu, k, precond=precond, gram="recurrence")
+        x1, c1 = iterate(hip, systems, nrhs, s, nu, k, precond=precond, basis_steps=1, gram="recurrence")
         assert c2 == (s - s // 2, s // 2), c2
         assert c1 == (s, 0), c1
         for q in range(len(systems)):
@@ -103,6 +107,57 @@ def test_pairs_equal_single_steps_and_oracle(hip, name):
                 o = oracle.step(A, sy["rhs"][r], xo, s, nu, sy["lmin"], sy["lmax"], precond=1 if precond else 0)
                 xo = o["x"]
             assert rel(x2[q][r], xo) <= 1e-10, (q, r, rel(x2[q][r], xo))
+
+
+@pytest.mark.parametrize("name", [k for k, v in CASES.items() if v[2] % 2 == 0])
+def test_moments_kind_lockstep(hip, name):
+    """The moments kind (FP64 default for even s): the two-step basis sums
+    each pair's products per band, the FGS kernel forms the Gram matrix from
+    the Chebyshev moments.  x after 1 and 2 outer iterations within 1e-10 of
+    the oracle's, pair by pair."""
+    dims, nrhs, s, faces, precond = CASES[name]
+    nu = 20
+    systems = make_batch(7, dims, nrhs, faces=faces)
+    ops = [hip.Operator.stencil(*sy["dims"], sy["kx"], sy["ky"], sy["kz"]) for sy in systems]
+    with hip.BatchedSolver(ops, nrhs, s, nu, [sy["lmin"] for sy in systems], [sy["lmax"] for sy in systems],
+                           autotune=False, precond=precond) as bs:
+        assert bs.gram_kind == "moments"
+    for k in (1, 2):
+        x, _ = iterate(hip, systems, nrhs, s, nu, k, precond=precond)
+        for q, sy in enumerate(systems):
+            A = oracle.assemble_stencil7(*sy["dims"], sy["kx"], sy["ky"], sy["kz"])
+            for r in range(nrhs):
+                xo = np.zeros(sy["rhs"].shape[1])
+                for _ in range(k):
+                    xo = oracle.step(A, sy["rhs"][r], xo, s, nu, sy["lmin"], sy["lmax"],
+                                     precond=1 if precond else 0)["x"]
+                assert rel(x[q][r], xo) <= 1e-10, (k, q, r, rel(x[q][r], xo))
+
+
+def test_moments_kind_solve_and_selection(hip):
+    """A batched moments solve reaches 1e-8 on every pair; AUTO takes the
+    recurrence kind for odd s, FP32+IR and single steps, and the moments
+    kind is refused there."""
+    systems = make_batch(11, [(40, 37, 35), (21, 19, 17), (12, 12, 12)], 2)
+    ops = [hip.Operator.stencil(*sy["dims"], sy["kx"], sy["ky"], sy["kz"]) for sy in systems]
+    lo, hi = [sy["lmin"] for sy in systems], [sy["lmax"] for sy in systems]
+    with hip.BatchedSolver(ops, 2, 16, 25, lo, hi, autotune=False) as bs:
+        assert bs.gram_kind == "moments"
+        x, st = bs.solve([t64(sy["rhs"].ravel()) for sy in systems], None, 1e-8)
+    for q, sy in enumerate(systems):
+        A = oracle.assemble_stencil7(*sy["dims"], sy["kx"], sy["ky"], sy["kz"])
+        xq = host(x[q]).reshape(2, -1)
+        for r in range(2):
+            b = sy["rhs"][r]
+            assert st[q * 2 + r].status == 0
+            assert np.linalg.norm(b - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(b)
+    for kw in ({"s": 15}, {"precision": "fp32ir"}, {"basis_steps": 1}):
+        s = kw.pop("s", 16)
+        with hip.BatchedSolver(ops, 2, s, 25, lo, hi, autotune=False, **kw) as bs:
+            assert bs.gram_kind == "recurrence", kw
+        with pytest.raises(hip.SStepError) as e:
+            hip.BatchedSolver(ops, 2, s, 25, lo, hi, autotune=False, gram="moments", **kw)
+        assert e.value.name == "SSTEP_E_UNSUPPORTED"
 
 
 def test_pairs_fp32ir_solve(hip):
