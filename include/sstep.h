@@ -109,8 +109,8 @@ typedef struct {
  * G_raw = P^T A P exactly: M^{-1} A p_j = (p_{j+1} + p_{j-1}) / (2 theta)
  * + sigma p_j (j >= 1), M^{-1} A p_0 = p_1 / theta + sigma p_0 (monomial
  * basis: M^{-1} A p_j = p_{j+1}).  AP is neither written nor allocated and A
- * is not applied in the Gram kernel.  MOMENTS (Chebyshev basis, s <= 31,
- * p_0 = M^{-1} r or no preconditioner; batched contexts in FP64 with an even
+ * is not applied in the Gram kernel.  MOMENTS (FP64, Chebyshev basis,
+ * s <= 31, p_0 = M^{-1} r or no preconditioner; batched contexts with an even
  * s and two basis steps per launch): as
  * RECURRENCE, but no kernel reads the basis back.  While the basis kernels
  * form p_i, they sum d_i = <p_i, M p_i> and e_i = <p_i, M p_{i-1}>
@@ -142,7 +142,7 @@ typedef struct {
                                $SSTEP_TUNE_CACHE or ~/.cache/sstep/tune.json; systems under 2^20
                                unknowns use the defaults; 0 = defaults */
     int32_t gram;           /* sstep_gram_kind: how G = P^T A P (Sec. 2) is formed.  SSTEP_GRAM_AUTO
-                               (default) = SSTEP_GRAM_MOMENTS in FP64 where it applies, else
+                               (default) = SSTEP_GRAM_MOMENTS where it applies (FP64), else
                                SSTEP_GRAM_RECURRENCE for s <= 31 (FP32+IR, p_0 = r with Jacobi,
                                the monomial basis, the allocation-free solve), SSTEP_GRAM_STORED_AP
                                at s = 32.  Batched contexts take AUTO (= MOMENTS where it applies,

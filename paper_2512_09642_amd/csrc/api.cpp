@@ -353,10 +353,13 @@ sstep_status load_coefficients(sstep_ctx *ctx, const sstep_operator *A, bool fir
 // columns under 4 GiB (32-bit byte offsets); by default for FP64 only (in
 // FP32+IR the stored-AP kernel is as fast).
 // The moments kind needs the Chebyshev basis and c = P^T r expressible in the
-// same M inner product as H: r = M p_0 (p_0 = M^{-1} r) or M = I.
+// same M inner product as H: r = M p_0 (p_0 = M^{-1} r) or M = I; and FP64:
+// an FP32 basis departs from the polynomial identities by about 1e-8, which
+// under loose bounds can exceed the small diagonal entries p_i^T A p_i formed
+// from H (a batched FP32+IR solve broke down so).
 bool moments_fit(int s, const sstep_options &o)
 {
-    return s <= kRecMaxS && o.basis == 0 && (o.p0_mode == 0 || o.precond == 0);
+    return s <= kRecMaxS && o.basis == 0 && (o.p0_mode == 0 || o.precond == 0) && o.precision == SSTEP_FP64;
 }
 
 sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, const sstep_options &o, int *kind,
@@ -365,15 +368,13 @@ sstep_status choose_gram_kind(sstep_ctx *ctx, const sstep_operator *A, int s, co
     if (o.gram == SSTEP_GRAM_MOMENTS) {
         if (!allow_moments || !moments_fit(s, o))
             return fail(ctx, SSTEP_E_UNSUPPORTED,
-                        "the moments Gram kind needs the Chebyshev basis, s <= 31, p_0 = M^{-1} r or no "
+                        "the moments Gram kind needs FP64, the Chebyshev basis, s <= 31, p_0 = M^{-1} r or no "
                         "preconditioner, and a context that may allocate");
         *kind = SSTEP_GRAM_MOMENTS;
         return SSTEP_OK;
     }
-    // AUTO: the moments kind in FP64; in FP32+IR the recurrence kind.  FP32+IR
-    // iteration counts to 1e-8 swing with rounding at s = 16 (recurrence /
-    // moments: 57 / 46 at 160^3, 52 / 82 at 224^3)
-    if (o.gram == SSTEP_GRAM_AUTO && allow_moments && moments_fit(s, o) && o.precision == SSTEP_FP64) {
+    // AUTO: the moments kind where it applies (FP64)
+    if (o.gram == SSTEP_GRAM_AUTO && allow_moments && moments_fit(s, o)) {
         *kind = SSTEP_GRAM_MOMENTS;
         return SSTEP_OK;
     }

@@ -169,6 +169,8 @@ def test_setup_rejects_unavailable_gram_kinds(native):
     assert st == 7 and not ctx.value
     st, ctx = setup_opts(basis=1)
     assert st == 7 and not ctx.value
+    st, ctx = setup_opts(precision=native.FP32_IR)
+    assert st == 7 and not ctx.value
     st, ctx = setup_opts(basis_steps=2)
     assert st == 1 and not ctx.value
 
