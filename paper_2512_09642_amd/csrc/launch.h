@@ -151,8 +151,10 @@ struct GTile {  // chunk of one pair (Gram)
 struct BF2Tile {
     int32_t q, y0, y1, k0, k1, pad;
 };
-constexpr int kBf2Threads = 1024;  // threads per block of the two-step batched basis
-constexpr int kBf2Planes = 16;     // planes per z-range it aims for
+constexpr int kBf2Threads = 1024;    // threads per block of the two-step batched basis
+constexpr int kBf2MaxPlanes = 128;   // longest z-range of one block
+constexpr int kBf2MinPlanes = 16;    // shortest z-range (small batches)
+constexpr int kBf2BlocksPerCu = 4;   // blocks per CU the longest ranges must still give
 struct BGlob {
     int32_t ndone, npairs;
 };

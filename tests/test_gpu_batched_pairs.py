@@ -160,6 +160,35 @@ def test_moments_kind_solve_and_selection(hip):
         assert e.value.name == "SSTEP_E_UNSUPPORTED"
 
 
+def test_whole_system_ranges(hip):
+    """A batch big enough for 4 blocks per CU: 64 systems of side 36..48
+    with 8 right-hand sides, so each system is one z-range of up to 48
+    planes (the smaller batches above take ranges of about 16).  The first
+    iterate of four pairs against the oracle's to 1e-10, and every pair's
+    solve to 1e-8."""
+    probs = gen.config4(seed=3, nsys=64, nrhs=8, nmin=36, nmax=48)
+    nrhs, s, nu = 8, 16, 25
+    ops = [hip.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz) for pr in probs]
+    lo, hi = [pr.lmin for pr in probs], [pr.lmax for pr in probs]
+    b = [t64(np.concatenate(pr.rhs)) for pr in probs]
+    with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi, autotune=False, max_outer=1) as bs:
+        assert bs.basis_pairs == 8 and bs.gram_kind == "moments"
+        x1, _ = bs.solve(b, None, 1e-14, raise_on_error=False)
+    for q, r in ((0, 0), (17, 3), (40, 7), (63, 5)):
+        pr = probs[q]
+        A = oracle.problem_csr(pr)
+        xo = oracle.step(A, pr.rhs[r], np.zeros(pr.n), s, nu, pr.lmin, pr.lmax)["x"]
+        assert rel(host(x1[q]).reshape(nrhs, -1)[r], xo) <= 1e-10, (q, r)
+    with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi, autotune=False) as bs:
+        x, st = bs.solve(b, None, 1e-8)
+    for q, pr in enumerate(probs):
+        A = oracle.problem_csr(pr)
+        xq = host(x[q]).reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert st[q * nrhs + r].status == 0
+            assert np.linalg.norm(pr.rhs[r] - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(pr.rhs[r]), (q, r)
+
+
 def test_pairs_fp32ir_solve(hip):
     """FP32 basis by pairs (FP32 face coefficients): every pair reaches 1e-8
     in the FP64 residual."""
