@@ -317,6 +317,19 @@ sstep_status sstep_setup_batched(sstep_ctx **out, int32_t nsys, const sstep_oper
  * each may be NULL).  SSTEP_E_ARG for a NULL or non-batched context. */
 sstep_status sstep_batched_tiles(const sstep_ctx *ctx, int64_t *rows_per_tile, int32_t *grid_factor);
 
+/* The bands a batched context's two-step basis launches run over (host
+ * outputs, each may be NULL): *bands, the blocks per right-hand side of the
+ * band table chosen for the whole batch (z-ranges as long as still give four
+ * blocks per compute unit; 0 when every basis launch forms one column);
+ * *tail_bands, those of a second table with ranges of 16 planes, which a
+ * solve switches to once the pairs still running would start fewer than four
+ * blocks per compute unit from the first table (0 when the two tables are the
+ * same); *tail_replays, the graph replays of the last sstep_solve_batched that
+ * ran on the second table.  The basis columns do not depend on the table; the
+ * moments Gram kind sums its per-band partials in a different order.
+ * SSTEP_E_ARG for a NULL or non-batched context. */
+sstep_status sstep_batched_bands(const sstep_ctx *ctx, int32_t *bands, int32_t *tail_bands, int32_t *tail_replays);
+
 /* b[q], x[q] (host arrays of nsys device pointers): n_q x nrhs FP64,
  * column-major (right-hand side r at offset r*n_q).  st: host array of
  * nsys*nrhs entries (pair (q, r) at q*nrhs + r), may be NULL.  Returns the

@@ -20,7 +20,7 @@ KT_NAMES = ("residual", "basis", "gram", "fgs", "update")
 EXPORTS = (
     "sstep_default_options", "sstep_setup", "sstep_update_coefficients", "sstep_apply", "sstep_solve",
     "sstep_solve_adjoint", "sstep_grad_operator", "sstep_grad_size", "sstep_n", "sstep_step",
-    "sstep_lanczos", "sstep_set_bounds", "sstep_lanczos_bounds", "sstep_last_iteration", "sstep_kernel_times", "sstep_gram_mode", "sstep_basis_launches", "sstep_batched_tiles", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
+    "sstep_lanczos", "sstep_set_bounds", "sstep_lanczos_bounds", "sstep_last_iteration", "sstep_kernel_times", "sstep_gram_mode", "sstep_basis_launches", "sstep_batched_tiles", "sstep_batched_bands", "sstep_setup_batched", "sstep_solve_batched", "sstep_last_error",
     "sstep_status_string", "sstep_destroy", "sstep_solve_noalloc", "sstep_coarse_setup", "sstep_coarse_fgs",
     "sstep_coarse_info",
 )
@@ -107,6 +107,8 @@ def load():
     lib.sstep_basis_launches.restype = C.c_int32
     lib.sstep_batched_tiles.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     lib.sstep_batched_tiles.restype = st
+    lib.sstep_batched_bands.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.sstep_batched_bands.restype = st
     lib.sstep_setup_batched.argtypes = [C.POINTER(P), C.c_int32, C.POINTER(Operator), C.c_int32, C.c_int32,
                                         C.c_int32, P, P, C.POINTER(Options)]
     lib.sstep_setup_batched.restype = st

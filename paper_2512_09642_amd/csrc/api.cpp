@@ -66,6 +66,23 @@ struct Batched {
     PTile *dpt = nullptr;
     GTile *dgt = nullptr;
     BF2Tile *df2 = nullptr;
+    // the two-step basis over ranges of kBf2MinPlanes planes, for the end of
+    // a solve when too few pairs are left to fill the chip with the longer
+    // ranges of df2: its band table, its systems (their moment partials laid
+    // out for it) and a second graph
+    BF2Tile *df2_tail = nullptr;
+    BSys *dsys_tail = nullptr;
+    int nf2_tail = 0;
+    uint32_t *dmap = nullptr, *dmap_tail = nullptr;  // dispatch orders of the two tables
+    uint32_t grid_tail = 0;
+    struct TailBands {
+        int64_t mofs;
+        int32_t f2first, nf2q;
+    };
+    std::vector<TailBands> tail_bands;
+    hipGraph_t graph_tail = nullptr;
+    hipGraphExec_t gexec_tail = nullptr;
+    int32_t tail_replays = 0;        // replays of the last solve on the short ranges
     int64_t gchunk = 8192;
     int grid_factor = 4;
     int cus = 256;
@@ -778,6 +795,10 @@ void sstep_destroy(sstep_ctx *ctx)
         (void)hipStreamDestroy(ctx->stream);
     delete ctx->coarse;
     if (ctx->batch) {
+        if (ctx->batch->gexec_tail)
+            (void)hipGraphExecDestroy(ctx->batch->gexec_tail);
+        if (ctx->batch->graph_tail)
+            (void)hipGraphDestroy(ctx->batch->graph_tail);
         if (ctx->batch->pairs_host)
             (void)hipHostFree(ctx->batch->pairs_host);
         if (ctx->batch->gl_host)
@@ -1015,6 +1036,20 @@ sstep_status sstep_batched_tiles(const sstep_ctx *ctx, int64_t *rows_per_tile, i
         *rows_per_tile = ctx->batch->gchunk;
     if (grid_factor)
         *grid_factor = ctx->batch->grid_factor;
+    return SSTEP_OK;
+}
+
+sstep_status sstep_batched_bands(const sstep_ctx *ctx, int32_t *bands, int32_t *tail_bands, int32_t *tail_replays)
+{
+    if (!ctx || !ctx->batch)
+        return SSTEP_E_ARG;
+    const Batched &B = *ctx->batch;
+    if (bands)
+        *bands = B.ba.f2 ? B.ba.nf2 : 0;
+    if (tail_bands)
+        *tail_bands = B.nf2_tail;
+    if (tail_replays)
+        *tail_replays = B.tail_replays;
     return SSTEP_OK;
 }
 
@@ -1300,6 +1335,57 @@ static std::vector<BF2Tile> bf2_bands_kz(const std::vector<BSys> &sys, size_t el
                                int32_t(std::min(k0 + kz, nz)), 0});
     }
     return out;
+}
+
+// The order the two-step basis's logical blocks (band e, right-hand side r:
+// e * nrhs + r) run in.  Hardware block b runs on XCD b % 8, as the (b / 8)-th
+// block that XCD starts, so map[b] lists each XCD's queue interleaved.  Units
+// (whole systems, or single bands) go, largest first, to the XCD with the
+// least work so far; a unit's blocks stay together in table order, so the
+// right-hand sides of a band (and, for whole systems, neighbouring bands)
+// share one L2.  A band's work: its points with the ring rows and planes.
+// Entries past an XCD's queue are 0xFFFFFFFF (no block).
+static std::vector<uint32_t> bf2_dispatch(const std::vector<BF2Tile> &tab, const std::vector<BSys> &sys, int nrhs,
+                                          bool whole_systems)
+{
+    struct Unit {
+        double w;
+        size_t e0, e1;
+    };
+    std::vector<Unit> units;
+    for (size_t e = 0; e < tab.size();) {
+        size_t f = e + 1;
+        if (whole_systems)
+            while (f < tab.size() && tab[f].q == tab[e].q)
+                ++f;
+        double w = 0.0;
+        for (size_t k = e; k < f; ++k)
+            w += double(tab[k].y1 - tab[k].y0 + 2) * double(sys[size_t(tab[k].q)].g.nx) *
+                 double(tab[k].k1 - tab[k].k0 + 2);
+        units.push_back({w, e, f});
+        e = f;
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit &u, const Unit &v) { return u.w > v.w; });
+    std::vector<std::vector<uint32_t>> queue(kNumXcd);
+    double load[kNumXcd] = {};
+    for (const Unit &u : units) {
+        int x = 0;
+        for (int k = 1; k < kNumXcd; ++k)
+            if (load[k] < load[x])
+                x = k;
+        load[x] += u.w;
+        for (size_t e = u.e0; e < u.e1; ++e)
+            for (int r = 0; r < nrhs; ++r)
+                queue[size_t(x)].push_back(uint32_t(e * size_t(nrhs) + size_t(r)));
+    }
+    size_t len = 0;
+    for (const auto &v : queue)
+        len = std::max(len, v.size());
+    std::vector<uint32_t> map(len * kNumXcd, 0xFFFFFFFFu);
+    for (int x = 0; x < kNumXcd; ++x)
+        for (size_t k = 0; k < queue[size_t(x)].size(); ++k)
+            map[k * kNumXcd + size_t(x)] = queue[size_t(x)][k];
+    return map;
 }
 
 // The longest z-ranges (at most kBf2MaxPlanes planes) that still give every
@@ -1631,28 +1717,60 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     a.gtiles = B.dgt;
     if (a.rec && o.basis_steps == 0) {
         const std::vector<BF2Tile> f2 = bf2_bands(B.sys, w, a.faces, kBf2Threads, a.nrhs, B.cus);
+        std::vector<BF2Tile> f2s;
         if (!f2.empty()) {
             OKCHK(dalloc(ctx, &B.df2, f2.size()));
             HIPCHK(ctx, hipMemcpy(B.df2, f2.data(), f2.size() * sizeof(BF2Tile), hipMemcpyHostToDevice));
             a.f2 = 1;
             a.nf2 = int(f2.size());
-            a.f2per = uint32_t((int64_t(a.nf2) * a.nrhs + kNumXcd - 1) / kNumXcd);
             a.f2tiles = B.df2;
+            for (const BF2Tile &t : f2)
+                ++B.sys[size_t(t.q)].nbl;
+            const std::vector<uint32_t> map = bf2_dispatch(f2, B.sys, a.nrhs, true);
+            OKCHK(dalloc(ctx, &B.dmap, map.size()));
+            HIPCHK(ctx, hipMemcpy(B.dmap, map.data(), map.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+            a.f2map = B.dmap;
+            a.f2grid = uint32_t(map.size());
+            f2s = bf2_bands_kz(B.sys, w, a.faces, kBf2Threads, kBf2MinPlanes);
+            if (f2s.size() > f2.size()) {
+                OKCHK(dalloc(ctx, &B.df2_tail, f2s.size()));
+                HIPCHK(ctx, hipMemcpy(B.df2_tail, f2s.data(), f2s.size() * sizeof(BF2Tile), hipMemcpyHostToDevice));
+                B.nf2_tail = int(f2s.size());
+                const std::vector<uint32_t> mt = bf2_dispatch(f2s, B.sys, a.nrhs, false);
+                OKCHK(dalloc(ctx, &B.dmap_tail, mt.size()));
+                HIPCHK(ctx, hipMemcpy(B.dmap_tail, mt.data(), mt.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+                B.grid_tail = uint32_t(mt.size());
+            } else {
+                f2s.clear();
+            }
         }
         if (a.f2 && mom_fit && (o.gram == SSTEP_GRAM_MOMENTS || o.gram == SSTEP_GRAM_AUTO)) {
             // band entries are ordered by system: each system's range of them,
-            // and its product slots (2s + 1 per right-hand side, one partial per band)
-            int64_t mofs = 0;
-            size_t e = 0;
+            // and its product slots (2s + 1 per right-hand side, one partial
+            // per band); both band tables share one partial buffer
+            auto layout = [&](const std::vector<BF2Tile> &tab, std::vector<Batched::TailBands> &out) {
+                int64_t mofs = 0;
+                size_t e = 0;
+                for (int q = 0; q < a.nsys; ++q) {
+                    Batched::TailBands tb{mofs, int32_t(e), 0};
+                    while (e < tab.size() && tab[e].q == q)
+                        ++e;
+                    tb.nf2q = int32_t(e - size_t(tb.f2first));
+                    mofs += int64_t(a.nrhs) * (2 * s + 1) * tb.nf2q;
+                    out.push_back(tb);
+                }
+                return mofs;
+            };
+            std::vector<Batched::TailBands> whole;
+            int64_t mofs = layout(f2, whole);
             for (int q = 0; q < a.nsys; ++q) {
                 BSys &S = B.sys[size_t(q)];
-                S.f2first = int32_t(e);
-                while (e < f2.size() && f2[e].q == q)
-                    ++e;
-                S.nf2q = int32_t(e - size_t(S.f2first));
-                S.mofs = mofs;
-                mofs += int64_t(a.nrhs) * (2 * s + 1) * S.nf2q;
+                S.mofs = whole[size_t(q)].mofs;
+                S.f2first = whole[size_t(q)].f2first;
+                S.nf2q = whole[size_t(q)].nf2q;
             }
+            if (!f2s.empty())
+                mofs = std::max(mofs, layout(f2s, B.tail_bands));
             OKCHK(dalloc(ctx, &a.mpart, size_t(mofs)));
             a.mom = 1;
         }
@@ -1680,6 +1798,36 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         return hip_fail(ctx, "hipStreamEndCapture", e2);
     ctx->graph = gph;
     HIPCHK(ctx, hipGraphInstantiate(&ctx->gexec, gph, nullptr, nullptr, 0));
+    if (B.nf2_tail > 0) {
+        // the same iteration over the short-range band table; every other
+        // field of its systems (the tile schedule just chosen) is the same
+        std::vector<BSys> st = B.sys;
+        if (a.mom)
+            for (int q = 0; q < a.nsys; ++q) {
+                st[size_t(q)].mofs = B.tail_bands[size_t(q)].mofs;
+                st[size_t(q)].f2first = B.tail_bands[size_t(q)].f2first;
+                st[size_t(q)].nf2q = B.tail_bands[size_t(q)].nf2q;
+            }
+        OKCHK(dalloc(ctx, &B.dsys_tail, st.size()));
+        HIPCHK(ctx, hipMemcpy(B.dsys_tail, st.data(), st.size() * sizeof(BSys), hipMemcpyHostToDevice));
+        BatchArgs at = a;
+        at.sys = B.dsys_tail;
+        at.f2tiles = B.df2_tail;
+        at.nf2 = B.nf2_tail;
+        at.f2map = B.dmap_tail;
+        at.f2grid = B.grid_tail;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < ctx->chunk && e == hipSuccess; ++c)
+            e = enqueue_batched_iteration(at, ctx->stream);
+        hipGraph_t gt = nullptr;
+        e2 = hipStreamEndCapture(ctx->stream, &gt);
+        if (e != hipSuccess)
+            return hip_fail(ctx, "kernel launch during graph capture", e);
+        if (e2 != hipSuccess)
+            return hip_fail(ctx, "hipStreamEndCapture", e2);
+        B.graph_tail = gt;
+        HIPCHK(ctx, hipGraphInstantiate(&B.gexec_tail, gt, nullptr, nullptr, 0));
+    }
     return SSTEP_OK;
 }
 
@@ -1741,8 +1889,20 @@ sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double 
     }
     const int max_replays = (ctx->opt.max_outer + 1 + ctx->chunk - 1) / ctx->chunk + 1;
     int launched = 0, checked = 0;
+    // the short-range graph once the blocks the whole batch's band table
+    // would still start (as of the last replay read back) fall below
+    // kBf2BlocksPerCu per CU; the choice depends only on device results, so
+    // a solve replays the same graphs every time
+    const int64_t tail_below = int64_t(kBf2BlocksPerCu) * B.cus;
+    int64_t blocks_left = int64_t(a.nf2) * a.nrhs;
+    B.tail_replays = 0;
     auto enqueue = [&]() -> hipError_t {
-        hipError_t e = hipGraphLaunch(ctx->gexec, ctx->stream);
+        hipGraphExec_t gx = ctx->gexec;
+        if (B.gexec_tail && blocks_left < tail_below) {
+            gx = B.gexec_tail;
+            ++B.tail_replays;
+        }
+        hipError_t e = hipGraphLaunch(gx, ctx->stream);
         if (e != hipSuccess)
             return e;
         int32_t *slot = ctx->poll_host + 4 * (launched % 2);
@@ -1759,6 +1919,7 @@ sstep_status sstep_solve_batched(sstep_ctx *ctx, const double *const *b, double 
             HIPCHK(ctx, enqueue());
         HIPCHK(ctx, hipEventSynchronize(ctx->ev_poll[checked % 2]));
         const int32_t ndone = ctx->poll_host[4 * (checked % 2)];
+        blocks_left = int64_t(a.nf2) * a.nrhs - ctx->poll_host[4 * (checked % 2) + 2];
         ++checked;
         if (ndone >= a.npairs)
             break;

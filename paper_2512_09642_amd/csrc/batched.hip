@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_bbasis(const BGlob *__restrict__ gl,
 constexpr uint32_t kMark = 0x40000000u;
 template <typename T, bool FACES, bool FIRST, int D, int NT, bool MOM>
 __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
-                                                  const BF2Tile *__restrict__ tiles, uint32_t nbl, uint32_t per,
+                                                  const BF2Tile *__restrict__ tiles, uint32_t nbl,
+                                                  const uint32_t *__restrict__ map,
                                                   const DevState *__restrict__ pairs, int nrhs, int precond, int j,
                                                   T *__restrict__ P, double *__restrict__ mpart, int s)
 {
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
     __shared__ T qs[2][NT + 1];
     if (gl->ndone == gl->npairs)
         return;
-    const uint32_t lb = xcd_block(blockIdx.x, per);
+    const uint32_t lb = map[blockIdx.x];
     if (lb >= nbl)
         return;  // whole block: no barrier is skipped by part of it
     const BF2Tile tl = tiles[lb / static_cast<uint32_t>(nrhs)];
@@ -586,15 +587,15 @@ namespace {
 template <typename T, bool FACES, int D, int NT, bool MOM>
 hipError_t bbasis_pair_v(const BatchArgs &a, int j, hipStream_t st)
 {
-    const dim3 grid(a.f2per * kNumXcd);
+    const dim3 grid(a.f2grid);
     const uint32_t nbl = static_cast<uint32_t>(a.nf2) * static_cast<uint32_t>(a.nrhs);
     T *P = static_cast<T *>(a.P);
     if (j == 0)
         hipLaunchKernelGGL((k_bbasis_f2<T, FACES, true, D, NT, MOM>), grid, dim3(NT), 0, st, a.gl, a.sys,
-                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P, a.mpart, a.s);
+                           a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, j, P, a.mpart, a.s);
     else
         hipLaunchKernelGGL((k_bbasis_f2<T, FACES, false, D, NT, MOM>), grid, dim3(NT), 0, st, a.gl, a.sys,
-                           a.f2tiles, nbl, a.f2per, a.pairs, a.nrhs, a.precond, j, P, a.mpart, a.s);
+                           a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, j, P, a.mpart, a.s);
     return hipGetLastError();
 }
 // Planes of loads in flight: 2 in FP64, 3 in FP32 (fastest on MI355X for the

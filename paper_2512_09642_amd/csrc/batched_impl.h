@@ -7,6 +7,13 @@
 
 namespace sstep {
 
+// A pair has stopped: counted once, by one thread.
+__device__ __forceinline__ void pair_stopped(BGlob *gl, const BSys &Q)
+{
+    atomicAdd(&gl->ndone, 1);
+    atomicAdd(&gl->bdone, Q.nbl);
+}
+
 // Gram partials of every active pair: tile (q, chunk, r) reduces rows
 // [chunk*gchunk, (chunk+1)*gchunk) of pair (q, r)'s basis (column stride
 // nrhs*ld, zero padding past n) into gpart[gofs + r*E*nch + e*nch + chunk].
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs(BGlob *__restrict__ gl, c
     if (!now)
         now = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, pdbg, nullptr, 0);
     if (now && lane == 0)
-        atomicAdd(&gl->ndone, 1);
+        pair_stopped(gl, Q);
 }
 
 template <int S>
@@ -193,7 +200,7 @@ __device__ __forceinline__ void bfgs_map_sweep(BGlob *__restrict__ gl, DevState 
         return;
     const int now = fgs_wave<S>(ps, sg, nu, cscale, fp32, Q.inv_sqrt_n, pdbg, nullptr, 0);
     if (now && lane == 0)
-        atomicAdd(&gl->ndone, 1);
+        pair_stopped(gl, Q);
 }
 
 // Recurrence Gram kind: the pair's sums of H and c', the stopping test, then
@@ -242,7 +249,7 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_rec(BGlob *__restrict__ g
     __syncthreads();
     if (stopped) {
         if (threadIdx.x == 0)
-            atomicAdd(&gl->ndone, 1);
+            pair_stopped(gl, Q);
         return;
     }
     bfgs_map_sweep<S>(gl, ps, Q, h, sg, nu, cscale, fp32, hscale, pdbg);
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_mom(BGlob *__restrict__ g
     __syncthreads();
     if (stopped) {
         if (threadIdx.x == 0)
-            atomicAdd(&gl->ndone, 1);
+            pair_stopped(gl, Q);
         return;
     }
     for (int k = threadIdx.x; k < NS; k += kBFgsThreads)

@@ -135,6 +135,9 @@ struct BSys {
     // (q, r) holds one partial per band at mofs + (r (2s + 1) + k) nf2q
     int64_t mofs;
     int32_t f2first, nf2q;
+    // bands of this system in the band table of the whole batch: what a pair
+    // of it adds to BGlob::bdone when it stops
+    int32_t nbl, pad;
 };
 struct BTile {  // chunk of one system, all right-hand sides
     int32_t q, chunk;
@@ -155,8 +158,11 @@ constexpr int kBf2Threads = 1024;    // threads per block of the two-step batche
 constexpr int kBf2MaxPlanes = 128;   // longest z-range of one block
 constexpr int kBf2MinPlanes = 16;    // shortest z-range (small batches)
 constexpr int kBf2BlocksPerCu = 4;   // blocks per CU the longest ranges must still give
+// ndone: pairs that have stopped; bdone: the band-table blocks of the whole
+// batch's two-step basis those pairs no longer start (the host reads both
+// after each graph replay)
 struct BGlob {
-    int32_t ndone, npairs;
+    int32_t ndone, npairs, bdone, pad;
 };
 
 struct BatchArgs {
@@ -179,10 +185,12 @@ struct BatchArgs {
     // rec_hscale M = const), the FGS kernel maps H onto P^T A P
     int rec = 0, rec_wap = 0;
     double rec_hscale = 1.0;
-    // two basis steps per launch (f2 = 1): nf2 bands x nrhs logical blocks,
-    // f2per of them per XCD
+    // two basis steps per launch (f2 = 1): nf2 bands x nrhs logical blocks
+    // (band e, right-hand side r: e * nrhs + r); hardware block b of the
+    // f2grid runs logical block f2map[b] (none if it is nf2 * nrhs or more)
     int f2 = 0, nf2 = 0;
-    uint32_t f2per = 0;
+    uint32_t f2grid = 0;
+    const uint32_t *f2map = nullptr;
     const BF2Tile *f2tiles = nullptr;
     // moments Gram kind (also rec): the two-step basis writes the products,
     // k_bfgs_mom sums them; no Gram kernel

@@ -358,6 +358,15 @@ class BatchedSolver:
         self.basis_launches = int(self._lib.sstep_basis_launches(ctx, C.byref(pairs)))
         self.basis_pairs = int(pairs.value)
 
+    def bands(self):
+        """(bands, tail_bands, tail_replays): blocks per right-hand side of the
+        two-step basis's band table for the whole batch, of its short-range
+        table for the end of a solve (0 when there is none), and the graph
+        replays of the last solve that ran on the short ranges."""
+        b, t, r = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(self._lib.sstep_batched_bands(self._ctx, C.byref(b), C.byref(t), C.byref(r)), self._ctx)
+        return int(b.value), int(t.value), int(r.value)
+
     def close(self):
         if getattr(self, "_ctx", None):
             self._lib.sstep_destroy(self._ctx)

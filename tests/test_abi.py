@@ -39,6 +39,7 @@ def test_default_options_and_status_strings(native):
     assert (opt.precision, opt.precond, opt.p0_mode, opt.max_outer, opt.graph_chunk, opt.record_history,
             opt.autotune, opt.gram) == (0, 1, 0, 10000, 4, 0, 1, 0)
     assert lib.sstep_gram_mode(None) == -1
+    assert lib.sstep_batched_bands(None, None, None, None) == 1  # SSTEP_E_ARG
     for code, name in native.STATUS_NAMES.items():
         assert lib.sstep_status_string(code).decode() == name
 

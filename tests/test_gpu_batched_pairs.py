@@ -165,7 +165,10 @@ def test_whole_system_ranges(hip):
     with 8 right-hand sides, so each system is one z-range of up to 48
     planes (the smaller batches above take ranges of about 16).  The first
     iterate of four pairs against the oracle's to 1e-10, and every pair's
-    solve to 1e-8."""
+    solve to 1e-8.  Once pairs stop, fewer than 4 blocks per CU are left and
+    the solve moves to ranges of 16 planes: with the recurrence Gram kind
+    (whose sums do not depend on the bands) that solve equals one basis step
+    per launch bit for bit."""
     probs = gen.config4(seed=3, nsys=64, nrhs=8, nmin=36, nmax=48)
     nrhs, s, nu = 8, 16, 25
     ops = [hip.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz) for pr in probs]
@@ -181,12 +184,23 @@ def test_whole_system_ranges(hip):
         assert rel(host(x1[q]).reshape(nrhs, -1)[r], xo) <= 1e-10, (q, r)
     with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi, autotune=False) as bs:
         x, st = bs.solve(b, None, 1e-8)
+        bands, tail, replays = bs.bands()
+    assert tail > bands >= 64 and replays > 0, (bands, tail, replays)
     for q, pr in enumerate(probs):
         A = oracle.problem_csr(pr)
         xq = host(x[q]).reshape(nrhs, -1)
         for r in range(nrhs):
             assert st[q * nrhs + r].status == 0
             assert np.linalg.norm(pr.rhs[r] - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(pr.rhs[r]), (q, r)
+    runs = []
+    for steps in (0, 1):
+        with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi, autotune=False, gram="recurrence", basis_steps=steps) as bs:
+            xr, sr = bs.solve(b, None, 1e-8)
+            runs.append(([host(v) for v in xr], [t.outer_iters for t in sr], bs.bands()))
+    assert runs[0][2][2] > 0 and runs[1][2] == (0, 0, 0), (runs[0][2], runs[1][2])
+    assert runs[0][1] == runs[1][1]
+    for q in range(len(probs)):
+        assert np.array_equal(runs[0][0][q], runs[1][0][q]), q
 
 
 def test_pairs_fp32ir_solve(hip):
