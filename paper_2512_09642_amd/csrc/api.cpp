@@ -1300,111 +1300,6 @@ sstep_status sstep_kernel_times(sstep_ctx *ctx, const double *b, double *x, int3
     return SSTEP_OK;
 }
 
-// Bands of the two-step batched basis: each system's rows split into bands
-// of equal height (a band and its two neighbouring rows fill at most one
-// block of nt threads; a grid whose planes fit in one block is one band),
-// its planes into ranges of at most kzt.  Empty when some system does not
-// fit that shape (a row wider than a third of a block) or the windows of its
-// buffer accesses would reach 1 GiB: the batch then takes one step per
-// launch.
-static std::vector<BF2Tile> bf2_bands_kz(const std::vector<BSys> &sys, size_t elem, bool faces, int nt, int kzt)
-{
-    std::vector<BF2Tile> out;
-    for (size_t q = 0; q < sys.size(); ++q) {
-        const Grid3 &g = sys[q].g;
-        const int64_t nx = g.nx, ny = g.ny, nz = g.nz;
-        const int64_t lim = (int64_t(1) << 30) - 1;  // below the kernel's out-of-window mark
-        int64_t bytes = sys[q].n;
-        if (faces)
-            bytes = std::max({bytes, nz * ny * (nx + 1), nz * (ny + 1) * nx, (nz + 1) * g.nxy});
-        if (bytes * int64_t(elem) > lim)
-            return {};
-        int64_t bands = 1;
-        if (g.nxy > nt) {
-            const int64_t inner = nt / nx - 2;  // band rows a block can hold
-            if (inner < 1)
-                return {};
-            bands = (ny + inner - 1) / inner;
-        }
-        const int64_t h = (ny + bands - 1) / bands;
-        const int64_t ranges = (nz + kzt - 1) / kzt;
-        const int64_t kz = (nz + ranges - 1) / ranges;
-        for (int64_t y0 = 0; y0 < ny; y0 += h)
-            for (int64_t k0 = 0; k0 < nz; k0 += kz)
-                out.push_back({int32_t(q), int32_t(y0), int32_t(std::min(y0 + h, ny)), int32_t(k0),
-                               int32_t(std::min(k0 + kz, nz)), 0});
-    }
-    return out;
-}
-
-// The order the two-step basis's logical blocks (band e, right-hand side r:
-// e * nrhs + r) run in.  Hardware block b runs on XCD b % 8, as the (b / 8)-th
-// block that XCD starts, so map[b] lists each XCD's queue interleaved.  Units
-// (whole systems, or single bands) go, largest first, to the XCD with the
-// least work so far; a unit's blocks stay together in table order, so the
-// right-hand sides of a band (and, for whole systems, neighbouring bands)
-// share one L2.  A band's work: its points with the ring rows and planes.
-// Entries past an XCD's queue are 0xFFFFFFFF (no block).
-static std::vector<uint32_t> bf2_dispatch(const std::vector<BF2Tile> &tab, const std::vector<BSys> &sys, int nrhs,
-                                          bool whole_systems)
-{
-    struct Unit {
-        double w;
-        size_t e0, e1;
-    };
-    std::vector<Unit> units;
-    for (size_t e = 0; e < tab.size();) {
-        size_t f = e + 1;
-        if (whole_systems)
-            while (f < tab.size() && tab[f].q == tab[e].q)
-                ++f;
-        double w = 0.0;
-        for (size_t k = e; k < f; ++k)
-            w += double(tab[k].y1 - tab[k].y0 + 2) * double(sys[size_t(tab[k].q)].g.nx) *
-                 double(tab[k].k1 - tab[k].k0 + 2);
-        units.push_back({w, e, f});
-        e = f;
-    }
-    std::stable_sort(units.begin(), units.end(), [](const Unit &u, const Unit &v) { return u.w > v.w; });
-    std::vector<std::vector<uint32_t>> queue(kNumXcd);
-    double load[kNumXcd] = {};
-    for (const Unit &u : units) {
-        int x = 0;
-        for (int k = 1; k < kNumXcd; ++k)
-            if (load[k] < load[x])
-                x = k;
-        load[x] += u.w;
-        for (size_t e = u.e0; e < u.e1; ++e)
-            for (int r = 0; r < nrhs; ++r)
-                queue[size_t(x)].push_back(uint32_t(e * size_t(nrhs) + size_t(r)));
-    }
-    size_t len = 0;
-    for (const auto &v : queue)
-        len = std::max(len, v.size());
-    std::vector<uint32_t> map(len * kNumXcd, 0xFFFFFFFFu);
-    for (int x = 0; x < kNumXcd; ++x)
-        for (size_t k = 0; k < queue[size_t(x)].size(); ++k)
-            map[k * kNumXcd + size_t(x)] = queue[size_t(x)][k];
-    return map;
-}
-
-// The longest z-ranges (at most kBf2MaxPlanes planes) that still give every
-// CU kBf2BlocksPerCu blocks, else ranges of kBf2MinPlanes: a long range
-// re-reads fewer halo planes and starts fewer blocks (the batched workload:
-// 2.10 s with whole-system ranges of up to 96 planes against 2.30 s with
-// 16), a short one keeps small batches spread over the chip.
-static std::vector<BF2Tile> bf2_bands(const std::vector<BSys> &sys, size_t elem, bool faces, int nt, int nrhs,
-                                      int cus)
-{
-    std::vector<BF2Tile> out;
-    for (int kzt : {kBf2MaxPlanes, 96, 64, 48, 32, 24, kBf2MinPlanes}) {
-        out = bf2_bands_kz(sys, elem, faces, nt, kzt);
-        if (out.empty() || int64_t(out.size()) * nrhs >= int64_t(kBf2BlocksPerCu) * cus)
-            break;
-    }
-    return out;
-}
-
 static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bool upload)
 {
     if (gchunk < kMinBatchChunk || gchunk % kPad != 0 || factor < 1)
@@ -1716,7 +1611,10 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     a.ptiles = B.dpt;
     a.gtiles = B.dgt;
     if (a.rec && o.basis_steps == 0) {
-        const std::vector<BF2Tile> f2 = bf2_bands(B.sys, w, a.faces, kBf2Threads, a.nrhs, B.cus);
+        std::vector<BandGrid> grids;
+        for (const BSys &S : B.sys)
+            grids.push_back({S.g.nx, S.g.ny, S.g.nz});
+        const std::vector<BF2Tile> f2 = bf2_bands(grids, w, a.faces, kBf2Threads, a.nrhs, B.cus);
         std::vector<BF2Tile> f2s;
         if (!f2.empty()) {
             OKCHK(dalloc(ctx, &B.df2, f2.size()));
@@ -1726,17 +1624,17 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
             a.f2tiles = B.df2;
             for (const BF2Tile &t : f2)
                 ++B.sys[size_t(t.q)].nbl;
-            const std::vector<uint32_t> map = bf2_dispatch(f2, B.sys, a.nrhs, true);
+            const std::vector<uint32_t> map = bf2_dispatch(f2, grids, a.nrhs, true, int(kNumXcd));
             OKCHK(dalloc(ctx, &B.dmap, map.size()));
             HIPCHK(ctx, hipMemcpy(B.dmap, map.data(), map.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
             a.f2map = B.dmap;
             a.f2grid = uint32_t(map.size());
-            f2s = bf2_bands_kz(B.sys, w, a.faces, kBf2Threads, kBf2MinPlanes);
+            f2s = bf2_bands_kz(grids, w, a.faces, kBf2Threads, kBf2MinPlanes);
             if (f2s.size() > f2.size()) {
                 OKCHK(dalloc(ctx, &B.df2_tail, f2s.size()));
                 HIPCHK(ctx, hipMemcpy(B.df2_tail, f2s.data(), f2s.size() * sizeof(BF2Tile), hipMemcpyHostToDevice));
                 B.nf2_tail = int(f2s.size());
-                const std::vector<uint32_t> mt = bf2_dispatch(f2s, B.sys, a.nrhs, false);
+                const std::vector<uint32_t> mt = bf2_dispatch(f2s, grids, a.nrhs, false, int(kNumXcd));
                 OKCHK(dalloc(ctx, &B.dmap_tail, mt.size()));
                 HIPCHK(ctx, hipMemcpy(B.dmap_tail, mt.data(), mt.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
                 B.grid_tail = uint32_t(mt.size());

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "bands.h"
 #include "common.h"
 
 namespace sstep {
@@ -148,16 +149,6 @@ struct PTile {  // kBlock points of one system (basis)
 struct GTile {  // chunk of one pair (Gram)
     int32_t q, chunk, r, pad;
 };
-// Two basis steps per launch (recurrence Gram kind): a band of whole grid
-// rows [y0, y1) of system q over the planes [k0, k1); the block also forms
-// the first step on the row below and the row above the band.
-struct BF2Tile {
-    int32_t q, y0, y1, k0, k1, pad;
-};
-constexpr int kBf2Threads = 1024;    // threads per block of the two-step batched basis
-constexpr int kBf2MaxPlanes = 128;   // longest z-range of one block
-constexpr int kBf2MinPlanes = 16;    // shortest z-range (small batches)
-constexpr int kBf2BlocksPerCu = 4;   // blocks per CU the longest ranges must still give
 // ndone: pairs that have stopped; bdone: the band-table blocks of the whole
 // batch's two-step basis those pairs no longer start (the host reads both
 // after each graph replay)
