@@ -1364,9 +1364,12 @@ static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
     return launch_bupdate(a, s);
 }
 
-// Times the basis step and the Gram reduction (they touch only library
-// buffers) for each tile size and persistent-grid factor; keeps the fastest
-// pair, cached like the single-system Gram schedule.
+// Times the launches of an outer iteration that the tile schedule sets (the
+// residual, the single-step basis when it runs, the Gram reduction when it
+// runs, the update) for each tile size and persistent-grid factor; keeps the
+// fastest pair, cached like the single-system Gram schedule.  The residual
+// and the update run on zeroed scratch right-hand sides and iterates with
+// zero step lengths (x stays zero), freed before returning.
 static sstep_status tune_batched(sstep_ctx *ctx)
 {
     Batched &B = *ctx->batch;
@@ -1376,7 +1379,8 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     for (int64_t v : B.n)
         h = (h ^ uint64_t(v)) * 1099511628211ull;
     key << kTuneSchema << " gfx950 batched s=" << a.s << " prec=" << (a.fp32 ? "fp32" : "fp64") << " nrhs=" << a.nrhs
-        << " nsys=" << a.nsys << " faces=" << a.faces << " rec=" << a.rec << " sizes=" << std::hex << h;
+        << " nsys=" << a.nsys << " faces=" << a.faces << " rec=" << a.rec << " mom=" << a.mom << " f2=" << a.f2
+        << " timed=iteration sizes=" << std::hex << h;
     const std::string path = tune_cache_path();
     std::map<std::string, GramSchedule> cache;
     if (!path.empty()) {
@@ -1385,19 +1389,53 @@ static sstep_status tune_batched(sstep_ctx *ctx)
         if (f != cache.end() && batched_entry_ok(f->second, kPad, kMinBatchChunk))
             return batched_tiles(ctx, f->second.slab, f->second.nbg, true);
     }
+    struct Scratch {
+        double *p = nullptr;
+        ~Scratch()
+        {
+            if (p)
+                (void)hipFree(p);
+        }
+    } xb;
+    const size_t nb = size_t(B.total_n) * size_t(a.nrhs);
+    HIPCHK(ctx, hipMalloc(&xb.p, 2 * nb * sizeof(double)));
+    HIPCHK(ctx, hipMemsetAsync(xb.p, 0, 2 * nb * sizeof(double), ctx->stream));
+    {
+        std::vector<DevState> ps(size_t(a.npairs));
+        size_t off = 0;
+        for (int q = 0; q < a.nsys; ++q)
+            for (int r = 0; r < a.nrhs; ++r) {
+                DevState &d = ps[size_t(q * a.nrhs + r)];
+                std::memset(&d, 0, sizeof(DevState));
+                d.x = xb.p + off;
+                d.b = xb.p + nb + off;
+                d.p0scale = 1.0;
+                off += size_t(B.n[size_t(q)]);
+            }
+        HIPCHK(ctx, hipMemcpyAsync(a.pairs, ps.data(), sizeof(DevState) * ps.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    auto iteration = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = launch_bresidual(a, ctx->stream, true)) != hipSuccess)
+            return e;
+        if (!a.f2 && (e = launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream)) != hipSuccess)
+            return e;
+        if ((e = launch_bgram(a, ctx->stream)) != hipSuccess)
+            return e;
+        return launch_bupdate(a, ctx->stream);
+    };
     int64_t best_chunk = B.gchunk;
     int best_factor = B.grid_factor;
     double best = 1e30;
     for (int64_t gchunk : {int64_t(2048), int64_t(8192), int64_t(32768)}) {
         for (int factor : {2, 4, 8}) {
             OKCHK(batched_tiles(ctx, gchunk, factor, true));
-            HIPCHK(ctx, launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream));
-            HIPCHK(ctx, launch_bgram(a, ctx->stream));
+            HIPCHK(ctx, iteration());
             HIPCHK(ctx, hipEventRecord(ctx->ev_t0, ctx->stream));
-            for (int r = 0; r < 2; ++r) {
-                HIPCHK(ctx, launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream));
-                HIPCHK(ctx, launch_bgram(a, ctx->stream));
-            }
+            for (int r = 0; r < 2; ++r)
+                HIPCHK(ctx, iteration());
             HIPCHK(ctx, hipEventRecord(ctx->ev_t1, ctx->stream));
             HIPCHK(ctx, hipEventSynchronize(ctx->ev_t1));
             float ms = 0.f;
@@ -1409,6 +1447,8 @@ static sstep_status tune_batched(sstep_ctx *ctx)
             }
         }
     }
+    HIPCHK(ctx, hipMemsetAsync(a.pairs, 0, sizeof(DevState) * size_t(a.npairs), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     OKCHK(batched_tiles(ctx, best_chunk, best_factor, true));
     if (!path.empty()) {
         cache[key.str()] = GramSchedule{best_factor, best_chunk, 1e3 * best / 2};

@@ -240,3 +240,32 @@ def test_pairs_only_where_they_fit(hip):
     with pytest.raises(hip.SStepError) as ei:
         counts([small], 8, basis_steps=2)
     assert ei.value.name == "SSTEP_E_ARG"
+
+
+def test_autotuned_tile_schedule(hip, tmp_path, monkeypatch):
+    """A batch of 1.1M unknowns is autotuned at set-up: the tuner times the
+    residual and the update on scratch iterates, then gives the pairs back.
+    The schedule is one of its candidates, the cache holds it under the
+    iteration-timed key, and every pair still reaches 1e-8 (checked against
+    the oracle's operator); a second set-up reads the same schedule back."""
+    monkeypatch.setenv("SSTEP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs = gen.config4(seed=5, nsys=8, nrhs=2, nmin=50, nmax=54)
+    assert sum(pr.n for pr in probs) >= 1 << 20
+    nrhs, s, nu = 2, 16, 25
+    ops = [hip.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz) for pr in probs]
+    lo, hi = [pr.lmin for pr in probs], [pr.lmax for pr in probs]
+    b = [t64(np.concatenate(pr.rhs[:nrhs])) for pr in probs]
+    with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi) as bs:
+        tiles = dict(bs.tiles)
+        x, st = bs.solve(b, None, 1e-8)
+    assert tiles["rows_per_tile"] in (2048, 8192, 32768) and tiles["grid_factor"] in (2, 4, 8), tiles
+    text = (tmp_path / "tune.json").read_text()
+    assert "timed=iteration" in text and "batched" in text
+    for q, pr in enumerate(probs):
+        A = oracle.problem_csr(pr)
+        xq = host(x[q]).reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert st[q * nrhs + r].status == 0
+            assert np.linalg.norm(pr.rhs[r] - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(pr.rhs[r]), (q, r)
+    with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi) as bs:
+        assert dict(bs.tiles) == tiles
