@@ -52,7 +52,7 @@ typedef enum {
     SSTEP_E_BREAKDOWN = 4,   /* a basis column has p^T A p <= 0 or non-finite: scaling undefined */
     SSTEP_E_NOCONV = 5,      /* max_outer outer iterations without reaching tol */
     SSTEP_E_NONFINITE = 6,   /* the residual norm became NaN or Inf */
-    SSTEP_E_UNSUPPORTED = 7  /* valid request this build does not provide */
+    SSTEP_E_UNSUPPORTED = 7  /* valid request the library does not provide */
 } sstep_status;
 
 typedef enum {
