@@ -168,7 +168,8 @@ def test_whole_system_ranges(hip):
     solve to 1e-8.  Once pairs stop, fewer than 4 blocks per CU are left and
     the solve moves to ranges of 16 planes: with the recurrence Gram kind
     (whose sums do not depend on the bands) that solve equals one basis step
-    per launch bit for bit."""
+    per launch bit for bit, and an FP32+IR solve that moves too reaches 1e-8
+    in every pair."""
     probs = gen.config4(seed=3, nsys=64, nrhs=8, nmin=36, nmax=48)
     nrhs, s, nu = 8, 16, 25
     ops = [hip.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz) for pr in probs]
@@ -201,6 +202,17 @@ def test_whole_system_ranges(hip):
     assert runs[0][1] == runs[1][1]
     for q in range(len(probs)):
         assert np.array_equal(runs[0][0][q], runs[1][0][q]), q
+    # FP32 basis (recurrence kind) on both tables: every pair to 1e-8 in the FP64 residual
+    ops32 = [hip.Operator.stencil(*pr.dims, pr.kx, pr.ky, pr.kz) for pr in probs]
+    with hip.BatchedSolver(ops32, nrhs, s, nu, lo, hi, autotune=False, precision="fp32ir") as bs:
+        x, st = bs.solve(b, None, 1e-8)
+        assert bs.gram_kind == "recurrence" and bs.bands()[2] > 0, bs.bands()
+    for q, pr in enumerate(probs):
+        A = oracle.problem_csr(pr)
+        xq = host(x[q]).reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert st[q * nrhs + r].status == 0
+            assert np.linalg.norm(pr.rhs[r] - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(pr.rhs[r]), (q, r)
 
 
 def test_pairs_fp32ir_solve(hip):
