@@ -75,15 +75,15 @@ struct Batched {
     int nf2_tail = 0;
     uint32_t *dmap = nullptr, *dmap_tail = nullptr;  // dispatch orders of the two tables
     uint32_t grid_tail = 0;
-    struct TailBands {
+    struct BandLayout {
         int64_t mofs;
         int32_t f2first, nf2q;
     };
-    std::vector<TailBands> tail_bands;
+    std::vector<BandLayout> tail_bands;
     hipGraph_t graph_tail = nullptr;
     hipGraphExec_t gexec_tail = nullptr;
     int32_t tail_replays = 0;        // replays of the last solve on the short ranges
-    int64_t gchunk = 8192;
+    int64_t gchunk = kMinBatchChunk;
     int grid_factor = 4;
     int cus = 256;
     DevState *pairs_host = nullptr;  // pinned
@@ -1369,7 +1369,8 @@ static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
 // runs, the update) for each tile size and persistent-grid factor; keeps the
 // fastest pair, cached like the single-system Gram schedule.  The residual
 // and the update run on zeroed scratch right-hand sides and iterates with
-// zero step lengths (x stays zero), freed before returning.
+// zero step lengths (x stays zero), freed before returning; without device
+// memory for them the default schedule stays.
 static sstep_status tune_batched(sstep_ctx *ctx)
 {
     Batched &B = *ctx->batch;
@@ -1398,7 +1399,11 @@ static sstep_status tune_batched(sstep_ctx *ctx)
         }
     } xb;
     const size_t nb = size_t(B.total_n) * size_t(a.nrhs);
-    HIPCHK(ctx, hipMalloc(&xb.p, 2 * nb * sizeof(double)));
+    if (hipMalloc(&xb.p, 2 * nb * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();  // no room for the scratch: keep the default schedule
+        xb.p = nullptr;
+        return SSTEP_OK;
+    }
     HIPCHK(ctx, hipMemsetAsync(xb.p, 0, 2 * nb * sizeof(double), ctx->stream));
     {
         std::vector<DevState> ps(size_t(a.npairs));
@@ -1686,11 +1691,11 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
             // band entries are ordered by system: each system's range of them,
             // and its product slots (2s + 1 per right-hand side, one partial
             // per band); both band tables share one partial buffer
-            auto layout = [&](const std::vector<BF2Tile> &tab, std::vector<Batched::TailBands> &out) {
+            auto layout = [&](const std::vector<BF2Tile> &tab, std::vector<Batched::BandLayout> &out) {
                 int64_t mofs = 0;
                 size_t e = 0;
                 for (int q = 0; q < a.nsys; ++q) {
-                    Batched::TailBands tb{mofs, int32_t(e), 0};
+                    Batched::BandLayout tb{mofs, int32_t(e), 0};
                     while (e < tab.size() && tab[e].q == q)
                         ++e;
                     tb.nf2q = int32_t(e - size_t(tb.f2first));
@@ -1699,7 +1704,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
                 }
                 return mofs;
             };
-            std::vector<Batched::TailBands> whole;
+            std::vector<Batched::BandLayout> whole;
             int64_t mofs = layout(f2, whole);
             for (int q = 0; q < a.nsys; ++q) {
                 BSys &S = B.sys[size_t(q)];
@@ -1719,7 +1724,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
     // a non-zero npairs with ndone = 0 keeps the kernels active while tuning
     BGlob g0{0, a.npairs};
     HIPCHK(ctx, hipMemcpy(a.gl, &g0, sizeof(BGlob), hipMemcpyHostToDevice));
-    OKCHK(batched_tiles(ctx, 8192, 4, true));
+    OKCHK(batched_tiles(ctx, kMinBatchChunk, 4, true));  // the tuner's usual pick on large batches
     if (o.autotune && B.total_n >= (int64_t(1) << 20))
         OKCHK(tune_batched(ctx));
     // graph of graph_chunk outer iterations over all pairs
