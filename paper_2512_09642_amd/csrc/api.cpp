@@ -1347,7 +1347,9 @@ static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bo
 static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
 {
     hipError_t e;
-    if ((e = launch_bresidual(a, s, true)) != hipSuccess)
+    // the moments kind takes the residual over the band table, its ||r||^2
+    // beside the basis products
+    if ((e = a.mom ? launch_bres_f2(a, s) : launch_bresidual(a, s, true)) != hipSuccess)
         return e;
     int j = 0;
     if (a.f2)  // two steps per launch, an odd last step alone
@@ -1365,8 +1367,8 @@ static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
 }
 
 // Times the launches of an outer iteration that the tile schedule sets (the
-// residual, the single-step basis when it runs, the Gram reduction when it
-// runs, the update) for each tile size and persistent-grid factor; keeps the
+// residual outside the moments kind, the single-step basis and the Gram
+// reduction when they run, the update) for each tile size and persistent-grid factor; keeps the
 // fastest pair, cached like the single-system Gram schedule.  The residual
 // and the update run on zeroed scratch right-hand sides and iterates with
 // zero step lengths (x stays zero), freed before returning; without device
@@ -1423,7 +1425,7 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     }
     auto iteration = [&]() -> hipError_t {
         hipError_t e;
-        if ((e = launch_bresidual(a, ctx->stream, true)) != hipSuccess)
+        if (!a.mom && (e = launch_bresidual(a, ctx->stream, true)) != hipSuccess)
             return e;
         if (!a.f2 && (e = launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream)) != hipSuccess)
             return e;
@@ -1699,7 +1701,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
                     while (e < tab.size() && tab[e].q == q)
                         ++e;
                     tb.nf2q = int32_t(e - size_t(tb.f2first));
-                    mofs += int64_t(a.nrhs) * (2 * s + 1) * tb.nf2q;
+                    mofs += int64_t(a.nrhs) * bmom_slots(s) * tb.nf2q;
                     out.push_back(tb);
                 }
                 return mofs;

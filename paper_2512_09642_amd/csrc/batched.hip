@@ -468,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
         }
     }
     if constexpr (MOM) {
-        const int ns = 2 * s + 1;
+        const int ns = bmom_slots(s);
         double *out = mpart + S.mofs + (static_cast<int64_t>(r) * ns + (FIRST ? 0 : 2 * j + 1)) * S.nf2q +
                       (static_cast<int32_t>(lb / static_cast<uint32_t>(nrhs)) - S.f2first);
         if constexpr (FIRST) {
@@ -482,6 +482,96 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
 }
 
 // x += P alpha for every pair whose solve continues.
+// Residual of the moments kind over the two-step basis's band table (FP64):
+// on the band's rows of one right-hand side, r = b - A x, p_0 = p0scale M^{-1}
+// r (p0scale r with p0_mode 1), and the band's partial of ||r||^2 in slot
+// 2s + 1 of the pair's band partials.  The block marches its range of planes:
+// x of the current plane (the band's rows and the row on each side) sits in
+// LDS, double-buffered with one barrier per plane, and the planes below and
+// above in registers, so each range reads x once (plus one plane on each
+// side).  The operator expression is PointStencil's and the Jacobi weights
+// are the stored ones, as in k_bresidual.
+template <bool FACES, int NT>
+__global__ __launch_bounds__(NT) void k_bres_f2(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
+                                               const BF2Tile *__restrict__ tiles, uint32_t nbl,
+                                               const uint32_t *__restrict__ map, const DevState *__restrict__ pairs,
+                                               int nrhs, int precond, int p0_mode, double *__restrict__ P,
+                                               double *__restrict__ mpart, int s)
+{
+    __shared__ double xs[2][NT];
+    if (gl->ndone == gl->npairs)
+        return;
+    const uint32_t lb = map[blockIdx.x];
+    if (lb >= nbl)
+        return;  // whole block: no barrier is skipped by part of it
+    const BF2Tile tl = tiles[lb / static_cast<uint32_t>(nrhs)];
+    const int r = static_cast<int>(lb % static_cast<uint32_t>(nrhs));
+    const BSys &S = sys[tl.q];
+    const DevState &ps = pairs[S.pair0 + r];
+    if (ps.done)
+        return;
+    const int nx = S.g.nx, ny = S.g.ny, nz = S.g.nz;
+    const int64_t nxy = S.g.nxy;
+    const int tid = threadIdx.x;
+    const int ye0 = tl.y0 > 0 ? tl.y0 - 1 : 0;
+    const int ye1 = tl.y1 < ny ? tl.y1 + 1 : ny;
+    const int er = tid / nx;
+    const int i = tid - er * nx;
+    const int ey = ye0 + er;
+    const bool in_dom = ey < ye1;
+    const bool interior = in_dom && ey >= tl.y0 && ey < tl.y1;
+    const int64_t pl = in_dom ? static_cast<int64_t>(ey) * nx + i : 0;
+    const double *__restrict__ x = ps.x;
+    const double *__restrict__ b = ps.b;
+    const double scale = ps.p0scale;
+    double *__restrict__ p0 = P + S.pofs + static_cast<int64_t>(r) * S.ld;
+    const double dconst = precond ? 1.0 / 6.0 : 1.0;
+    const int k0 = tl.k0, k1 = tl.k1;
+    double xb = in_dom && k0 > 0 ? x[pl + (k0 - 1) * nxy] : 0.0;
+    double xc = in_dom ? x[pl + k0 * nxy] : 0.0;
+    double acc = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const int64_t c = pl + static_cast<int64_t>(k) * nxy;
+        const double xt = in_dom && k + 1 < nz ? x[c + nxy] : 0.0;
+        double bc = 0.0, fw = 0.0, fe = 0.0, fs = 0.0, fn = 0.0, fb = 0.0, ft = 0.0, dv = dconst;
+        if (interior) {
+            bc = b[c];
+            if constexpr (FACES) {
+                const int64_t fx = c + static_cast<int64_t>(k) * ny + ey;  // x-faces: nx + 1 per grid row
+                const int64_t fy = c + static_cast<int64_t>(k) * nx;       // y-faces: ny + 1 rows per plane
+                fw = S.kx[fx], fe = S.kx[fx + 1], fs = S.ky[fy], fn = S.ky[fy + nx], fb = S.kz[c],
+                ft = S.kz[c + nxy];
+                dv = S.dinv[c];
+            }
+        }
+        double *buf = xs[k & 1];
+        buf[tid] = xc;
+        __syncthreads();
+        if (interior) {
+            const double w = i > 0 ? buf[tid - 1] : 0.0;
+            const double e = i + 1 < nx ? buf[tid + 1] : 0.0;
+            const double so = ey > 0 ? buf[tid - nx] : 0.0;
+            const double no = ey + 1 < ny ? buf[tid + nx] : 0.0;
+            double ax;
+            if constexpr (FACES)
+                ax = fw * (xc - w) + fe * (xc - e) + fs * (xc - so) + fn * (xc - no) + fb * (xc - xb) +
+                     ft * (xc - xt);
+            else
+                ax = 6.0 * xc - (((((w + e) + so) + no) + xb) + xt);
+            const double rr = bc - ax;
+            acc += rr * rr;
+            p0[c] = scale * (p0_mode ? rr : dv * rr);
+        }
+        xb = xc;
+        xc = xt;
+    }
+    const double v[1] = {acc};
+    block_partials<1, NT>(v,
+                          mpart + S.mofs + (static_cast<int64_t>(r) * bmom_slots(s) + 2 * s + 1) * S.nf2q +
+                              (static_cast<int32_t>(lb / static_cast<uint32_t>(nrhs)) - S.f2first),
+                          S.nf2q);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bupdate(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                     const BTile *__restrict__ tiles, int ntiles,
@@ -609,6 +699,21 @@ hipError_t bbasis_pair_t(const BatchArgs &a, int j, hipStream_t st)
     return bbasis_pair_v<T, FACES, D, kBf2Threads, false>(a, j, st);
 }
 }  // namespace
+
+hipError_t launch_bres_f2(const BatchArgs &a, hipStream_t st)
+{
+    if (a.fp32 || !a.f2 || !a.mom)
+        return hipErrorInvalidValue;  // FP64 moments kind over the band table only
+    const uint32_t nbl = static_cast<uint32_t>(a.nf2) * static_cast<uint32_t>(a.nrhs);
+    double *P = static_cast<double *>(a.P);
+    if (a.faces)
+        hipLaunchKernelGGL((k_bres_f2<true, kBf2Threads>), dim3(a.f2grid), dim3(kBf2Threads), 0, st, a.gl, a.sys,
+                           a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, a.p0_mode, P, a.mpart, a.s);
+    else
+        hipLaunchKernelGGL((k_bres_f2<false, kBf2Threads>), dim3(a.f2grid), dim3(kBf2Threads), 0, st, a.gl,
+                           a.sys, a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, a.p0_mode, P, a.mpart, a.s);
+    return hipGetLastError();
+}
 
 hipError_t launch_bdinv(const BSys &S, int precond, int fp32, double *dinv, float *dinv32, hipStream_t st)
 {

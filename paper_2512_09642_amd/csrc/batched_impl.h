@@ -270,7 +270,6 @@ hipError_t bfgs_rec_launch_s(const BatchArgs &a, hipStream_t st)
 template <int S>
 __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_mom(BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                            DevState *__restrict__ pairs, int nrhs,
-                                                           const double *__restrict__ rpart,
                                                            const double *__restrict__ mpart, int nu, double cscale,
                                                            int fp32, double hscale, double *__restrict__ dbg)
 {
@@ -289,11 +288,11 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_mom(BGlob *__restrict__ g
     __shared__ double h[E1];
     __shared__ double sg[T0 + S];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const double *mp = mpart + Q.mofs + static_cast<int64_t>(r) * NS * Q.nf2q;
-    const double *rp = rpart + Q.rofs + static_cast<int64_t>(r) * Q.nch;
+    // slots 0 .. NS - 1: the products; slot NS: ||r||^2 (k_bres_f2)
+    const double *mp = mpart + Q.mofs + static_cast<int64_t>(r) * bmom_slots(S) * Q.nf2q;
     for (int t = wave; t <= NS; t += kBFgsThreads / kWave) {
-        const double *src = t < NS ? mp + static_cast<int64_t>(t) * Q.nf2q : rp;
-        const int cnt = t < NS ? Q.nf2q : Q.nch;
+        const double *src = mp + static_cast<int64_t>(t) * Q.nf2q;
+        const int cnt = Q.nf2q;
         double a0 = 0.0, a1 = 0.0;
         int q = lane;
         for (; q + kWave < cnt; q += 2 * kWave) {
@@ -337,7 +336,7 @@ template <int S>
 hipError_t bfgs_mom_launch_s(const BatchArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfgs_mom<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs,
-                       a.rpart, a.mpart, a.nu, a.cscale, a.fp32, a.rec_hscale, a.dbg);
+                       a.mpart, a.nu, a.cscale, a.fp32, a.rec_hscale, a.dbg);
     return hipGetLastError();
 }
 

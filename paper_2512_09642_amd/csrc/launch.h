@@ -117,6 +117,10 @@ __host__ __device__ inline int gram_entries(int s) { return s * (s + 1) / 2 + s;
 // System q's basis block is laid out [s][nrhs][ld_q] at element offset pofs:
 // column j of pair (q, r) starts at pofs + (j*nrhs + r)*ld_q.
 // ---------------------------------------------------------------------------
+// Per-band partial slots of a batched pair in the moments kind: the 2s + 1
+// basis products (slots 0 .. 2s) and ||r||^2 (slot 2s + 1).
+__host__ __device__ inline int bmom_slots(int s) { return 2 * s + 2; }
+
 struct BSys {
     Grid3 g;
     int64_t n, ld, pofs;
@@ -132,8 +136,8 @@ struct BSys {
     int64_t rofs;                    // residual partials of pair (q, r): rofs + r*nch
     int32_t pair0, nch;
     // moments kind: the two-step basis's bands of this system are entries
-    // f2first .. f2first + nf2q - 1 of the band table; product slot k of pair
-    // (q, r) holds one partial per band at mofs + (r (2s + 1) + k) nf2q
+    // f2first .. f2first + nf2q - 1 of the band table; slot k of pair (q, r)
+    // holds one partial per band at mofs + (r bmom_slots(s) + k) nf2q
     int64_t mofs;
     int32_t f2first, nf2q;
     // bands of this system in the band table of the whole batch: what a pair
@@ -192,6 +196,7 @@ struct BatchArgs {
 hipError_t launch_bresidual(const BatchArgs &a, hipStream_t st, bool write_p0);
 hipError_t launch_bp0scale(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bbasis(const BatchArgs &a, int j, hipStream_t st);
+hipError_t launch_bres_f2(const BatchArgs &a, hipStream_t st);
 hipError_t launch_bbasis_pair(const BatchArgs &a, int j, hipStream_t st);
 hipError_t launch_bdinv(const BSys &S, int precond, int fp32, double *dinv, float *dinv32, hipStream_t st);
 hipError_t launch_bgram(const BatchArgs &a, hipStream_t st);
