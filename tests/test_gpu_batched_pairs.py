@@ -281,3 +281,35 @@ def test_autotuned_tile_schedule(hip, tmp_path, monkeypatch):
             assert np.linalg.norm(pr.rhs[r] - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(pr.rhs[r]), (q, r)
     with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi) as bs:
         assert dict(bs.tiles) == tiles
+
+
+def test_constant_poisson_batch_moments(hip):
+    """Constant-coefficient 7-point systems (no face arrays) on the default
+    kind: the moments kind with two steps per launch and the band-table
+    residual.  One band (a 12 x 10 plane), several bands (40 x 30) and a
+    narrow grid (36 x 7).  The first iterate of every pair against the
+    oracle's to 1e-10, and every pair's solve to 1e-8."""
+    dims = [(12, 10, 9), (40, 30, 20), (36, 7, 33)]
+    nrhs, s, nu = 2, 16, 25
+    probs = [gen.small_poisson3d(*d, seed=7 + q) for q, d in enumerate(dims)]
+    ops = [hip.Operator.stencil(*d) for d in dims]
+    lo, hi = [pr.lmin for pr in probs], [pr.lmax for pr in probs]
+    rng = np.random.default_rng(11)
+    rhs = [[rng.uniform(-1.0, 1.0, pr.n) for _ in range(nrhs)] for pr in probs]
+    b = [t64(np.concatenate(rq)) for rq in rhs]
+    with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi, autotune=False, max_outer=1) as bs:
+        assert bs.gram_kind == "moments" and bs.basis_pairs == s // 2
+        x1, _ = bs.solve(b, None, 1e-14, raise_on_error=False)
+    for q, pr in enumerate(probs):
+        A = oracle.problem_csr(pr)
+        for r in range(nrhs):
+            xo = oracle.step(A, rhs[q][r], np.zeros(pr.n), s, nu, pr.lmin, pr.lmax)["x"]
+            assert rel(host(x1[q]).reshape(nrhs, -1)[r], xo) <= 1e-10, (q, r)
+    with hip.BatchedSolver(ops, nrhs, s, nu, lo, hi, autotune=False) as bs:
+        x, st = bs.solve(b, None, 1e-8)
+    for q, pr in enumerate(probs):
+        A = oracle.problem_csr(pr)
+        xq = host(x[q]).reshape(nrhs, -1)
+        for r in range(nrhs):
+            assert st[q * nrhs + r].status == 0
+            assert np.linalg.norm(rhs[q][r] - oracle.spmv(A, xq[r])) <= 1e-8 * np.linalg.norm(rhs[q][r]), (q, r)
