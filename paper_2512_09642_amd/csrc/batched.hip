@@ -489,8 +489,9 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
 // x of the current plane (the band's rows and the row on each side) sits in
 // LDS, double-buffered with one barrier per plane, and the planes below and
 // above in registers, so each range reads x once (plus one plane on each
-// side).  The operator expression is PointStencil's and the Jacobi weights
-// are the stored ones, as in k_bresidual.
+// side).  The operator expression is PointStencil's, as in k_bresidual; the
+// Jacobi weights are the stored ones, which k_bdinv forms with PointStencil's
+// expression.
 template <bool FACES, int NT>
 __global__ __launch_bounds__(NT) void k_bres_f2(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                const BF2Tile *__restrict__ tiles, uint32_t nbl,
