@@ -1691,8 +1691,9 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         }
         if (a.f2 && mom_fit && (o.gram == SSTEP_GRAM_MOMENTS || o.gram == SSTEP_GRAM_AUTO)) {
             // band entries are ordered by system: each system's range of them,
-            // and its product slots (2s + 1 per right-hand side, one partial
-            // per band); both band tables share one partial buffer
+            // and its partial slots (bmom_slots(s) per right-hand side: the
+            // 2s + 1 products and ||r||^2, one partial per band); both band
+            // tables share one partial buffer
             auto layout = [&](const std::vector<BF2Tile> &tab, std::vector<Batched::BandLayout> &out) {
                 int64_t mofs = 0;
                 size_t e = 0;
