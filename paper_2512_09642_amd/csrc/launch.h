@@ -187,8 +187,8 @@ struct BatchArgs {
     uint32_t f2grid = 0;
     const uint32_t *f2map = nullptr;
     const BF2Tile *f2tiles = nullptr;
-    // moments Gram kind (also rec): the two-step basis writes the products,
-    // k_bfgs_mom sums them; no Gram kernel
+    // moments Gram kind (also rec): the two-step basis writes the products
+    // and k_bres_f2 ||r||^2, per band; k_bfgs_mom sums them; no Gram kernel
     int mom = 0;
     double *mpart = nullptr;
 };
