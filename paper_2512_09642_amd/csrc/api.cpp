@@ -1347,9 +1347,9 @@ static sstep_status batched_tiles(sstep_ctx *ctx, int64_t gchunk, int factor, bo
 static hipError_t enqueue_batched_iteration(const BatchArgs &a, hipStream_t s)
 {
     hipError_t e;
-    // the moments kind takes the residual over the band table, its ||r||^2
-    // beside the basis products
-    if ((e = a.mom ? launch_bres_f2(a, s) : launch_bresidual(a, s, true)) != hipSuccess)
+    // with two basis steps per launch the residual runs over the band table,
+    // its ||r||^2 per band (beside the basis products in the moments kind)
+    if ((e = a.bres ? launch_bres_f2(a, s) : launch_bresidual(a, s, true)) != hipSuccess)
         return e;
     int j = 0;
     if (a.f2)  // two steps per launch, an odd last step alone
@@ -1425,7 +1425,7 @@ static sstep_status tune_batched(sstep_ctx *ctx)
     }
     auto iteration = [&]() -> hipError_t {
         hipError_t e;
-        if (!a.mom && (e = launch_bresidual(a, ctx->stream, true)) != hipSuccess)
+        if (!a.bres && (e = launch_bresidual(a, ctx->stream, true)) != hipSuccess)
             return e;
         if (!a.f2 && (e = launch_bbasis(a, 1 < a.s ? 1 : 0, ctx->stream)) != hipSuccess)
             return e;
@@ -1689,11 +1689,15 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
                 f2s.clear();
             }
         }
-        if (a.f2 && mom_fit && (o.gram == SSTEP_GRAM_MOMENTS || o.gram == SSTEP_GRAM_AUTO)) {
+        if (a.f2) {
+            a.mom = mom_fit && (o.gram == SSTEP_GRAM_MOMENTS || o.gram == SSTEP_GRAM_AUTO);
             // band entries are ordered by system: each system's range of them,
-            // and its partial slots (bmom_slots(s) per right-hand side: the
-            // 2s + 1 products and ||r||^2, one partial per band); both band
-            // tables share one partial buffer
+            // and its partial slots per right-hand side, one partial per band
+            // (the moments kind: the 2s + 1 products and ||r||^2; the
+            // recurrence kind: ||r||^2); both band tables share one buffer
+            a.bres = 1;
+            a.bres_slots = a.mom ? bmom_slots(s) : 1;
+            a.bres_slot = a.mom ? 2 * s + 1 : 0;
             auto layout = [&](const std::vector<BF2Tile> &tab, std::vector<Batched::BandLayout> &out) {
                 int64_t mofs = 0;
                 size_t e = 0;
@@ -1702,7 +1706,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
                     while (e < tab.size() && tab[e].q == q)
                         ++e;
                     tb.nf2q = int32_t(e - size_t(tb.f2first));
-                    mofs += int64_t(a.nrhs) * bmom_slots(s) * tb.nf2q;
+                    mofs += int64_t(a.nrhs) * a.bres_slots * tb.nf2q;
                     out.push_back(tb);
                 }
                 return mofs;
@@ -1718,7 +1722,6 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
             if (!f2s.empty())
                 mofs = std::max(mofs, layout(f2s, B.tail_bands));
             OKCHK(dalloc(ctx, &a.mpart, size_t(mofs)));
-            a.mom = 1;
         }
     }
     if (o.gram == SSTEP_GRAM_MOMENTS && !a.mom)
@@ -1748,7 +1751,7 @@ static sstep_status setup_batched_impl(sstep_ctx *ctx, int32_t nsys, const sstep
         // the same iteration over the short-range band table; every other
         // field of its systems (the tile schedule just chosen) is the same
         std::vector<BSys> st = B.sys;
-        if (a.mom)
+        if (a.bres)
             for (int q = 0; q < a.nsys; ++q) {
                 st[size_t(q)].mofs = B.tail_bands[size_t(q)].mofs;
                 st[size_t(q)].f2first = B.tail_bands[size_t(q)].f2first;

@@ -482,22 +482,22 @@ __global__ __launch_bounds__(NT) void k_bbasis_f2(const BGlob *__restrict__ gl, 
 }
 
 // x += P alpha for every pair whose solve continues.
-// Residual of the moments kind over the two-step basis's band table (FP64):
-// on the band's rows of one right-hand side, r = b - A x, p_0 = p0scale M^{-1}
-// r (p0scale r with p0_mode 1), and the band's partial of ||r||^2 in slot
-// 2s + 1 of the pair's band partials.  The block marches its range of planes:
+// Residual over the two-step basis's band table (FP64 arithmetic; p_0 stored
+// in TP): on the band's rows of one right-hand side, r = b - A x, p_0 =
+// p0scale M^{-1} r (p0scale r with p0_mode 1), and the band's partial of
+// ||r||^2 in slot `slot` of the pair's `slots` band partials.  The block marches its range of planes:
 // x of the current plane (the band's rows and the row on each side) sits in
 // LDS, double-buffered with one barrier per plane, and the planes below and
 // above in registers, so each range reads x once (plus one plane on each
 // side).  The operator expression is PointStencil's, as in k_bresidual; the
 // Jacobi weights are the stored ones, which k_bdinv forms with PointStencil's
 // expression.
-template <bool FACES, int NT>
+template <typename TP, bool FACES, int NT>
 __global__ __launch_bounds__(NT) void k_bres_f2(const BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                const BF2Tile *__restrict__ tiles, uint32_t nbl,
                                                const uint32_t *__restrict__ map, const DevState *__restrict__ pairs,
-                                               int nrhs, int precond, int p0_mode, double *__restrict__ P,
-                                               double *__restrict__ mpart, int s)
+                                               int nrhs, int precond, int p0_mode, TP *__restrict__ P,
+                                               double *__restrict__ mpart, int slots, int slot)
 {
     __shared__ double xs[2][NT];
     if (gl->ndone == gl->npairs)
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(NT) void k_bres_f2(const BGlob *__restrict__ gl, co
     const double *__restrict__ x = ps.x;
     const double *__restrict__ b = ps.b;
     const double scale = ps.p0scale;
-    double *__restrict__ p0 = P + S.pofs + static_cast<int64_t>(r) * S.ld;
+    TP *__restrict__ p0 = P + S.pofs + static_cast<int64_t>(r) * S.ld;
     const double dconst = precond ? 1.0 / 6.0 : 1.0;
     const int k0 = tl.k0, k1 = tl.k1;
     double xb = in_dom && k0 > 0 ? x[pl + (k0 - 1) * nxy] : 0.0;
@@ -561,14 +561,14 @@ __global__ __launch_bounds__(NT) void k_bres_f2(const BGlob *__restrict__ gl, co
                 ax = 6.0 * xc - (((((w + e) + so) + no) + xb) + xt);
             const double rr = bc - ax;
             acc += rr * rr;
-            p0[c] = scale * (p0_mode ? rr : dv * rr);
+            p0[c] = static_cast<TP>(scale * (p0_mode ? rr : dv * rr));
         }
         xb = xc;
         xc = xt;
     }
     const double v[1] = {acc};
     block_partials<1, NT>(v,
-                          mpart + S.mofs + (static_cast<int64_t>(r) * bmom_slots(s) + 2 * s + 1) * S.nf2q +
+                          mpart + S.mofs + (static_cast<int64_t>(r) * slots + slot) * S.nf2q +
                               (static_cast<int32_t>(lb / static_cast<uint32_t>(nrhs)) - S.f2first),
                           S.nf2q);
 }
@@ -701,19 +701,25 @@ hipError_t bbasis_pair_t(const BatchArgs &a, int j, hipStream_t st)
 }
 }  // namespace
 
+namespace {
+template <typename TP, bool FACES>
+hipError_t bres_f2_t(const BatchArgs &a, hipStream_t st)
+{
+    const uint32_t nbl = static_cast<uint32_t>(a.nf2) * static_cast<uint32_t>(a.nrhs);
+    hipLaunchKernelGGL((k_bres_f2<TP, FACES, kBf2Threads>), dim3(a.f2grid), dim3(kBf2Threads), 0, st, a.gl, a.sys,
+                       a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, a.p0_mode, static_cast<TP *>(a.P),
+                       a.mpart, a.bres_slots, a.bres_slot);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_bres_f2(const BatchArgs &a, hipStream_t st)
 {
-    if (a.fp32 || !a.f2 || !a.mom)
-        return hipErrorInvalidValue;  // FP64 moments kind over the band table only
-    const uint32_t nbl = static_cast<uint32_t>(a.nf2) * static_cast<uint32_t>(a.nrhs);
-    double *P = static_cast<double *>(a.P);
-    if (a.faces)
-        hipLaunchKernelGGL((k_bres_f2<true, kBf2Threads>), dim3(a.f2grid), dim3(kBf2Threads), 0, st, a.gl, a.sys,
-                           a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, a.p0_mode, P, a.mpart, a.s);
-    else
-        hipLaunchKernelGGL((k_bres_f2<false, kBf2Threads>), dim3(a.f2grid), dim3(kBf2Threads), 0, st, a.gl,
-                           a.sys, a.f2tiles, nbl, a.f2map, a.pairs, a.nrhs, a.precond, a.p0_mode, P, a.mpart, a.s);
-    return hipGetLastError();
+    if (!a.f2 || !a.bres)
+        return hipErrorInvalidValue;  // only over a band table with its partial slots
+    if (a.fp32)
+        return a.faces ? bres_f2_t<float, true>(a, st) : bres_f2_t<float, false>(a, st);
+    return a.faces ? bres_f2_t<double, true>(a, st) : bres_f2_t<double, false>(a, st);
 }
 
 hipError_t launch_bdinv(const BSys &S, int precond, int fp32, double *dinv, float *dinv32, hipStream_t st)

@@ -210,12 +210,15 @@ template <int S>
 __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_rec(BGlob *__restrict__ gl, const BSys *__restrict__ sys,
                                                            DevState *__restrict__ pairs, int nrhs,
                                                            const double *__restrict__ rpart,
+                                                           const double *__restrict__ bpart,
                                                            const double *__restrict__ gpart, int nu, double cscale,
                                                            int fp32, double hscale, double *__restrict__ dbg)
 {
     constexpr int S1 = S + 1;
     constexpr int E1 = S1 * (S1 + 1) / 2 + S1;
     constexpr int T0 = S * (S + 1) / 2;
+    // ||r||^2: one partial per band (bpart, k_bres_f2, one slot per
+    // right-hand side) or per chunk tile (rpart, k_bresidual)
     const int p = blockIdx.x;
     DevState *ps = pairs + p;
     if (ps->done)
@@ -226,16 +229,18 @@ __global__ __launch_bounds__(kBFgsThreads) void k_bfgs_rec(BGlob *__restrict__ g
     __shared__ double sg[T0 + S];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const double *gp = gpart + Q.gofs + static_cast<int64_t>(r) * E1 * Q.nch;
-    const double *rp = rpart + Q.rofs + static_cast<int64_t>(r) * Q.nch;
+    const double *rp = bpart ? bpart + Q.mofs + static_cast<int64_t>(r) * Q.nf2q
+                             : rpart + Q.rofs + static_cast<int64_t>(r) * Q.nch;
     for (int t = wave; t <= E1; t += kBFgsThreads / kWave) {
         const double *src = t < E1 ? gp + static_cast<int64_t>(t) * Q.nch : rp;
+        const int cnt = t < E1 || !bpart ? Q.nch : Q.nf2q;
         double a0 = 0.0, a1 = 0.0;
         int q = lane;
-        for (; q + kWave < Q.nch; q += 2 * kWave) {
+        for (; q + kWave < cnt; q += 2 * kWave) {
             a0 += src[q];
             a1 += src[q + kWave];
         }
-        for (; q < Q.nch; q += kWave)
+        for (; q < cnt; q += kWave)
             a0 += src[q];
         const double acc = wave_sum(a0 + a1);
         if (lane == 0)
@@ -259,7 +264,8 @@ template <int S>
 hipError_t bfgs_rec_launch_s(const BatchArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfgs_rec<S>, dim3(a.npairs), dim3(kBFgsThreads), 0, st, a.gl, a.sys, a.pairs, a.nrhs,
-                       a.rpart, a.gpart, a.nu, a.cscale, a.fp32, a.rec_hscale, a.dbg);
+                       a.rpart, a.bres && !a.mom ? a.mpart : nullptr, a.gpart, a.nu, a.cscale, a.fp32,
+                       a.rec_hscale, a.dbg);
     return hipGetLastError();
 }
 

@@ -191,6 +191,10 @@ struct BatchArgs {
     // and k_bres_f2 ||r||^2, per band; k_bfgs_mom sums them; no Gram kernel
     int mom = 0;
     double *mpart = nullptr;
+    // residual over the band table (k_bres_f2; every context with f2): its
+    // ||r||^2 per band in slot bres_slot of bres_slots per right-hand side of
+    // mpart (the moments kind: bmom_slots(s), 2s + 1; the recurrence kind: 1, 0)
+    int bres = 0, bres_slots = 0, bres_slot = 0;
 };
 
 hipError_t launch_bresidual(const BatchArgs &a, hipStream_t st, bool write_p0);
