@@ -135,9 +135,9 @@ struct BSys {
     int64_t gofs;                    // Gram partials of pair (q, r): gofs + r*E*nch
     int64_t rofs;                    // residual partials of pair (q, r): rofs + r*nch
     int32_t pair0, nch;
-    // moments kind: the two-step basis's bands of this system are entries
-    // f2first .. f2first + nf2q - 1 of the band table; slot k of pair (q, r)
-    // holds one partial per band at mofs + (r bmom_slots(s) + k) nf2q
+    // two steps per launch: this system's bands are entries f2first ..
+    // f2first + nf2q - 1 of the band table; slot k of pair (q, r) holds one
+    // partial per band at mofs + (r slots + k) nf2q (slots: bres_slots)
     int64_t mofs;
     int32_t f2first, nf2q;
     // bands of this system in the band table of the whole batch: what a pair
